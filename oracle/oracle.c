@@ -1,0 +1,303 @@
+/* oracle.c - serial FP64 CPU oracle for the per-patch MOL hydro update of
+ * Wang, Abel & Kaehler, "Adaptive Mesh Fluid Simulations on GPU" (Secs. 4-5).
+ *
+ * TEST INFRASTRUCTURE ONLY: the reference the GPU library is checked against.
+ * Nothing on the product path links or calls it.  It is written as plain loops
+ * that follow the paper's equations in the paper's order, one cell and one face
+ * at a time, with no blocking, fusion or reuse beyond what the definitions say.
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math (no FMA contraction, so every
+ * operation below is one IEEE-rounded operation in the order written).
+ *
+ * Readings of the paper taken here (the paper is silent or garbled):
+ *  - PLM face states use half the limited slope (the printed formula omits the
+ *    factor 1/2; without it a linear profile reconstructs the neighbour value).
+ *  - The reconstructed primitives are (rho, e, vx, vy, vz), the set the paper's
+ *    1D flux kernel stages; the face pressure is p = (gamma-1) rho e.
+ *  - The Riemann flux is the formula the paper prints in Sec. 4 (the symmetric
+ *    one-speed form: F = (F_L + F_R - lambda0 (U_R - U_L))/2 with conserved
+ *    U_R - U_L); the two-speed HLL of Harten, Lax & van Leer is a flag.
+ *  - c_s = sqrt(gamma p / rho) at each face state; in a y or z sweep the normal
+ *    velocity of that sweep replaces v_x in lambda^+-.
+ *  - Ghost layers are refilled before each RK stage; "outflow" is a zero-gradient
+ *    copy of the edge cell's conserved variables; reflect mirrors and negates the
+ *    normal momentum.
+ *  - CFL rule (absent from the paper): dt = C / max_cells sum_d (|v_d|+c_s)/dx_d.
+ */
+#include "oracle.h"
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- geometry */
+typedef struct {
+  int level, n[3], g[3], s[3], bc[6];
+  int64_t off, S;
+} geom;
+
+static geom get_geom(const int32_t* m, int64_t off, int ndim) {
+  geom G;
+  G.level = m[0];
+  for (int d = 0; d < 3; ++d) {
+    G.n[d] = m[4 + d];
+    G.g[d] = (d < ndim) ? m[7] : 0;
+    G.s[d] = G.n[d] + 2 * G.g[d];
+  }
+  for (int f = 0; f < 6; ++f) G.bc[f] = m[8 + f];
+  G.off = off;
+  G.S = (int64_t)G.s[0] * G.s[1] * G.s[2];
+  return G;
+}
+
+/* Element index of variable k of the cell with active-relative coordinates c[3]
+ * (c[d] in [-g, n+g)). */
+static int64_t at(const geom* G, int k, const int c[3]) {
+  int64_t cell = ((int64_t)(c[2] + G->g[2]) * G->s[1] + (c[1] + G->g[1])) * G->s[0] + (c[0] + G->g[0]);
+  return G->off + (int64_t)k * G->S + cell;
+}
+
+static int is_level(const int32_t* m, int level) { return level < 0 || m[0] == level; }
+
+/* ---------------------------------------------------------------- physics */
+double or_minmod3(double a, double b, double c) {
+  /* Sec. 4: minmod(a,b,c) = 0.25 (sgn a + sgn b) |sgn a + sgn c| min(|a|,|b|,|c|). */
+  double sa = (a > 0) - (a < 0), sb = (b > 0) - (b < 0), sc = (c > 0) - (c < 0);
+  double m = fmin(fabs(a), fmin(fabs(b), fabs(c)));
+  return 0.25 * (sa + sb) * fabs(sa + sc) * m;
+}
+
+int or_prim(const or_phys* ph, const double U[5], double q[6]) {
+  /* Sec. 4: U = (rho, rho v, rho E), E = v^2/2 + e, ideal gas p = (gamma-1) rho e. */
+  int bad = 0;
+  for (int k = 0; k < 5; ++k)
+    if (!isfinite(U[k])) bad = 1;
+  double rho = U[0];
+  double vx = U[1] / rho, vy = U[2] / rho, vz = U[3] / rho;
+  double kin = 0.5 * ((U[1] * U[1] + U[2] * U[2]) + U[3] * U[3]) / rho; /* rho v^2 / 2 */
+  double e = (U[4] - kin) / rho;
+  if (!(rho > 0) && !(ph->rho_floor > 0)) bad = 1;
+  if (!(e > 0) && !(ph->e_floor > 0)) bad = 1;
+  if (ph->rho_floor > 0 && rho < ph->rho_floor) rho = ph->rho_floor;
+  if (ph->e_floor > 0 && e < ph->e_floor) e = ph->e_floor;
+  q[0] = rho;
+  q[1] = e;
+  q[2] = vx;
+  q[3] = vy;
+  q[4] = vz;
+  q[5] = (ph->gamma - 1.0) * rho * e;
+  return bad;
+}
+
+/* Conserved state, pressure and sound speed of one primitive face state q = (rho,e,vx,vy,vz). */
+static void face_state(const or_phys* ph, const double q[5], double U[5], double* p, double* c) {
+  double rho = q[0], e = q[1], vx = q[2], vy = q[3], vz = q[4];
+  *p = (ph->gamma - 1.0) * rho * e;
+  *c = sqrt(ph->gamma * (*p) / rho);
+  U[0] = rho;
+  U[1] = rho * vx;
+  U[2] = rho * vy;
+  U[3] = rho * vz;
+  U[4] = rho * (e + 0.5 * ((vx * vx + vy * vy) + vz * vz));
+}
+
+void or_phys_flux(const or_phys* ph, int d, const double q[5], double F[5]) {
+  /* Sec. 4 flux vectors: F^d = (rho v_d, rho v_d v + p e_d, rho (v^2/2 + h) v_d),
+   * with rho (v^2/2 + h) = rho E + p since h = e + p/rho. */
+  double U[5], p, c;
+  face_state(ph, q, U, &p, &c);
+  double vd = q[2 + d];
+  F[0] = U[1 + d];
+  for (int j = 0; j < 3; ++j) F[1 + j] = U[1 + d] * q[2 + j] + (j == d ? p : 0.0);
+  F[4] = (U[4] + p) * vd;
+}
+
+void or_face_flux(const or_phys* ph, int d, const double qL[5], const double qR[5], double F[5]) {
+  /* Sec. 4 Riemann flux.  lambda^+- = v_d +- c_s for each face state,
+   * a+ = max(0, lambda+_L, lambda+_R), a- = max(0, -lambda-_L, -lambda-_R),
+   * lambda0 = max(a+, a-);  F = 0.5 (F_L + F_R - lambda0 (U_R - U_L)). */
+  double UL[5], UR[5], FL[5], FR[5], pL, pR, cL, cR;
+  face_state(ph, qL, UL, &pL, &cL);
+  face_state(ph, qR, UR, &pR, &cR);
+  or_phys_flux(ph, d, qL, FL);
+  or_phys_flux(ph, d, qR, FR);
+  double vL = qL[2 + d], vR = qR[2 + d];
+  double ap = fmax(0.0, fmax(vL + cL, vR + cR));
+  double am = fmax(0.0, fmax(-(vL - cL), -(vR - cR)));
+  if (ph->flux == OR_FLUX_HLL2) {
+    /* Two-speed HLL (Harten, Lax & van Leer 1983) with S_R = a+, S_L = -a-. */
+    for (int k = 0; k < 5; ++k)
+      F[k] = ((ap * FL[k] + am * FR[k]) - (ap * am) * (UR[k] - UL[k])) / (ap + am);
+  } else {
+    double lam = fmax(ap, am);
+    for (int k = 0; k < 5; ++k) F[k] = 0.5 * ((FL[k] + FR[k]) - lam * (UR[k] - UL[k]));
+  }
+}
+
+/* ---------------------------------------------------------------- O1 ghosts */
+int or_fill_ghosts(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph,
+                   double* V, int32_t level) {
+  for (int p = 0; p < np; ++p) {
+    const int32_t* m = meta + (size_t)p * OR_META;
+    if (!is_level(m, level)) continue;
+    geom G = get_geom(m, off[p], ph->ndim);
+    for (int d = 0; d < ph->ndim; ++d) {
+      int a = (d + 1) % 3, b = (d + 2) % 3; /* the two other dimensions */
+      for (int side = 0; side < 2; ++side) {
+        int bc = G.bc[2 * d + side];
+        if (bc == OR_BC_EXTERNAL) continue; /* filled by the caller */
+        for (int layer = 1; layer <= G.g[d]; ++layer) {
+          int gi = side == 0 ? -layer : G.n[d] - 1 + layer; /* ghost index along d */
+          int si;                                            /* source index along d */
+          double sgn = 1.0;
+          if (bc == OR_BC_OUTFLOW) {
+            si = side == 0 ? 0 : G.n[d] - 1;
+          } else if (bc == OR_BC_PERIODIC) {
+            si = ((gi % G.n[d]) + G.n[d]) % G.n[d];
+          } else { /* reflect about the boundary face */
+            si = side == 0 ? layer - 1 : G.n[d] - layer;
+            sgn = -1.0;
+          }
+          for (int ib = 0; ib < G.n[b]; ++ib)
+            for (int ia = 0; ia < G.n[a]; ++ia) {
+              int cg[3], cs[3];
+              cg[d] = gi; cg[a] = ia; cg[b] = ib;
+              cs[d] = si; cs[a] = ia; cs[b] = ib;
+              for (int k = 0; k < ph->nvar; ++k) {
+                double v = V[at(&G, k, cs)];
+                if (k == 1 + d) v = sgn * v;
+                V[at(&G, k, cg)] = v;
+              }
+            }
+        }
+      }
+    }
+  }
+  return 0;
+}
+
+/* ---------------------------------------------------------------- O2-O6 L(U) */
+int or_patch_L(const int32_t* m, int64_t off, const or_phys* ph, const double* V, double* L) {
+  geom G = get_geom(m, off, ph->ndim);
+  int bad = 0;
+  int64_t nact = (int64_t)G.n[0] * G.n[1] * G.n[2];
+  for (int64_t i = 0; i < 5 * nact; ++i) L[i] = 0.0;
+  int maxn = G.n[0] > G.n[1] ? G.n[0] : G.n[1];
+  if (G.n[2] > maxn) maxn = G.n[2];
+  /* line buffers, indexed by position along the line + 2 (cells -2 .. n+1) */
+  double(*q)[5] = malloc(sizeof(double[5]) * (size_t)(maxn + 4));
+  double(*sig)[5] = malloc(sizeof(double[5]) * (size_t)(maxn + 4));
+  double(*F)[5] = malloc(sizeof(double[5]) * (size_t)(maxn + 1));
+  for (int d = 0; d < ph->ndim; ++d) {
+    /* Sec. 4 MOL equation: the d-flux needs only cells along d; level l has dx0/2^l. */
+    double dxd = ldexp(ph->dx0[d], -G.level);
+    int a = (d + 1) % 3, b = (d + 2) % 3, n = G.n[d];
+    for (int ib = 0; ib < G.n[b]; ++ib)
+      for (int ia = 0; ia < G.n[a]; ++ia) {
+        /* O2: primitives of cells -2 .. n+1 along the line */
+        for (int i = -2; i <= n + 1; ++i) {
+          int c[3];
+          c[d] = i; c[a] = ia; c[b] = ib;
+          double Uc[5], w[6];
+          for (int k = 0; k < 5; ++k) Uc[k] = V[at(&G, k, c)];
+          bad |= or_prim(ph, Uc, w);
+          for (int k = 0; k < 5; ++k) q[i + 2][k] = w[k];
+        }
+        /* O3: limited slope of cells -1 .. n (Sec. 4 PLM with theta-minmod) */
+        for (int i = -1; i <= n; ++i)
+          for (int k = 0; k < 5; ++k) {
+            double qm = q[i + 1][k], q0 = q[i + 2][k], qp = q[i + 3][k];
+            sig[i + 2][k] = or_minmod3(ph->theta * (q0 - qm), ph->theta * (qp - q0), (qp - qm) / 2.0);
+          }
+        /* O4-O5: flux at face f (between cells f-1 and f), f = 0 .. n */
+        for (int f = 0; f <= n; ++f) {
+          double qL[5], qR[5];
+          for (int k = 0; k < 5; ++k) {
+            qL[k] = q[f + 1][k] + 0.5 * sig[f + 1][k]; /* u_{f-1/2,l} = u_{f-1} + sigma_{f-1}/2 */
+            qR[k] = q[f + 2][k] - 0.5 * sig[f + 2][k]; /* u_{f-1/2,r} = u_f - sigma_f/2 */
+          }
+          or_face_flux(ph, d, qL, qR, F[f]);
+        }
+        /* O6: L_i -= (F_{i+1/2} - F_{i-1/2}) / dx_d, dimensions in the order x, y, z */
+        for (int i = 0; i < n; ++i) {
+          int c[3];
+          c[d] = i; c[a] = ia; c[b] = ib;
+          int64_t cell = ((int64_t)c[2] * G.n[1] + c[1]) * G.n[0] + c[0];
+          for (int k = 0; k < 5; ++k) L[k * nact + cell] = L[k * nact + cell] - (F[i + 1][k] - F[i][k]) / dxd;
+        }
+      }
+  }
+  free(q);
+  free(sig);
+  free(F);
+  return bad;
+}
+
+/* ---------------------------------------------------------------- O7 stages */
+int or_stage(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph,
+             const double* V, const double* U0, double* out, double dt, int32_t stage, int32_t level) {
+  int bad = 0;
+  for (int p = 0; p < np; ++p) {
+    const int32_t* m = meta + (size_t)p * OR_META;
+    if (!is_level(m, level)) continue;
+    geom G = get_geom(m, off[p], ph->ndim);
+    int64_t nact = (int64_t)G.n[0] * G.n[1] * G.n[2];
+    double* L = malloc(sizeof(double) * 5 * (size_t)nact);
+    bad |= or_patch_L(m, off[p], ph, V, L);
+    for (int k3 = 0; k3 < G.n[2]; ++k3)
+      for (int j = 0; j < G.n[1]; ++j)
+        for (int i = 0; i < G.n[0]; ++i) {
+          int c[3] = {i, j, k3};
+          int64_t cell = ((int64_t)k3 * G.n[1] + j) * G.n[0] + i;
+          for (int k = 0; k < 5; ++k) {
+            int64_t e = at(&G, k, c);
+            double u1 = V[e] + dt * L[k * nact + cell]; /* Sec. 4 TVD-RK2: U + dt L(U) */
+            out[e] = stage == 1 ? u1 : 0.5 * U0[e] + 0.5 * u1;
+          }
+        }
+    free(L);
+  }
+  return bad;
+}
+
+int or_rk2_step(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph,
+                double* U, double* W, double dt, int32_t level) {
+  /* Sec. 4 (Shu-Osher TVD-RK2): U1 = Un + dt L(Un); Un+1 = Un/2 + U1/2 + dt L(U1)/2. */
+  int bad = 0;
+  or_fill_ghosts(np, meta, off, ph, U, level);
+  bad |= or_stage(np, meta, off, ph, U, NULL, W, dt, 1, level);
+  or_fill_ghosts(np, meta, off, ph, W, level);
+  bad |= or_stage(np, meta, off, ph, W, U, U, dt, 2, level);
+  return bad;
+}
+
+/* ---------------------------------------------------------------- O9 CFL */
+double or_max_speed(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph,
+                    const double* U, int32_t level, int* flag) {
+  double smax = 0.0;
+  int bad = 0;
+  for (int p = 0; p < np; ++p) {
+    const int32_t* m = meta + (size_t)p * OR_META;
+    if (!is_level(m, level)) continue;
+    geom G = get_geom(m, off[p], ph->ndim);
+    for (int k3 = 0; k3 < G.n[2]; ++k3)
+      for (int j = 0; j < G.n[1]; ++j)
+        for (int i = 0; i < G.n[0]; ++i) {
+          int c[3] = {i, j, k3};
+          double Uc[5], w[6];
+          for (int k = 0; k < 5; ++k) Uc[k] = U[at(&G, k, c)];
+          bad |= or_prim(ph, Uc, w);
+          double cs = sqrt(ph->gamma * w[5] / w[0]);
+          double s = 0.0;
+          for (int d = 0; d < ph->ndim; ++d) s = s + (fabs(w[2 + d]) + cs) / ldexp(ph->dx0[d], -G.level);
+          if (s > smax) smax = s;
+        }
+  }
+  if (flag) *flag = bad;
+  return smax;
+}
+
+double or_cfl_dt(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph,
+                 const double* U, double cfl, int32_t level) {
+  int bad = 0;
+  double s = or_max_speed(np, meta, off, ph, U, level, &bad);
+  return cfl / s;
+}

@@ -1,0 +1,75 @@
+/* oracle.h - serial FP64 CPU oracle for the per-patch MOL hydro update of
+ * Wang, Abel & Kaehler, "Adaptive Mesh Fluid Simulations on GPU".
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, obviously correct
+ * reference that the GPU path is checked against.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark load it; the product
+ * path never links, imports or calls it.  It shares no code, header or table
+ * with the GPU library.
+ *
+ * Storage convention (the same *format* the GPU library accepts, written here
+ * independently): a patch has n[d] active cells and g[d] ghost layers per side
+ * in each active dimension d < ndim (g[d] = 0, n[d] = 1 in absent dimensions);
+ * s[d] = n[d] + 2 g[d].  Variable k of cell (i,j,k) (storage indices, x fastest)
+ * lives at  U[off + k*S + (kz*s[1] + jy)*s[0] + ix]  with S = s[0]*s[1]*s[2].
+ * Variables are the conserved U = (rho, rho vx, rho vy, rho vz, rho E) of the
+ * paper's Sec. 4, with rho E the total energy density.
+ *
+ * Patch metadata is an int32 array of OR_META entries per patch:
+ *   [0] level, [1..3] lo (lower active index in level space), [4..6] n,
+ *   [7] ng, [8..13] bc for faces -x,+x,-y,+y,-z,+z, [14..15] unused.
+ */
+#ifndef PAPER_ORACLE_H
+#define PAPER_ORACLE_H
+#include <stdint.h>
+
+#define OR_META 16
+enum { OR_BC_OUTFLOW = 0, OR_BC_PERIODIC = 1, OR_BC_REFLECT = 2, OR_BC_EXTERNAL = 3 };
+enum { OR_FLUX_PAPER = 0, OR_FLUX_HLL2 = 1 };
+
+typedef struct {
+  int32_t nvar, ndim;
+  double gamma, theta;
+  double dx0[3];
+  int32_t flux, pad;
+  double rho_floor, e_floor;
+} or_phys;
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Three-argument minmod of Sec. 4 (0.25(sgn a+sgn b)|sgn a+sgn c| min|.|). */
+double or_minmod3(double a, double b, double c);
+/* Conserved -> (rho, e, vx, vy, vz, p) for one cell; returns 1 if unphysical. */
+int or_prim(const or_phys* ph, const double U[5], double q[6]);
+/* Face flux in direction d from primitive face states qL, qR = (rho,e,vx,vy,vz). */
+void or_face_flux(const or_phys* ph, int d, const double qL[5], const double qR[5], double F[5]);
+/* Physical flux F^d(U(q)) of Sec. 4 for one primitive state. */
+void or_phys_flux(const or_phys* ph, int d, const double q[5], double F[5]);
+
+/* O1: fill the face ghosts (two layers or ng, whichever is set) of every patch
+ * on `level` (-1 = all) from the boundary condition of each face. */
+int or_fill_ghosts(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph,
+                   double* V, int32_t level);
+/* L(V) of the MOL equation for one patch, written to L (5 x active cells, x fastest).
+ * V must have its ghosts filled.  Returns 1 if an unphysical state was met. */
+int or_patch_L(const int32_t* meta, int64_t off, const or_phys* ph, const double* V, double* L);
+/* One RK2 stage over the patches of `level`: stage 1 out = V + dt L(V);
+ * stage 2 out = 0.5 U0 + 0.5 (V + dt L(V)).  Active cells only. */
+int or_stage(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph,
+             const double* V, const double* U0, double* out, double dt, int32_t stage, int32_t level);
+/* One full TVD-RK2 step of `level` on U (in place), W = scratch arena of the same size. */
+int or_rk2_step(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph,
+                double* U, double* W, double dt, int32_t level);
+/* Largest signal speed sum_d (|v_d| + c_s)/dx_d over active cells of `level`. */
+double or_max_speed(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph,
+                    const double* U, int32_t level, int* flag);
+/* dt = cfl / max speed (one level or a single-level table). */
+double or_cfl_dt(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph,
+                 const double* U, double cfl, int32_t level);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

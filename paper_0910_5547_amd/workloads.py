@@ -1,0 +1,284 @@
+"""Seeded synthetic inputs for the per-patch hydro update (shared by both sides).
+
+This module holds the problem set-ups only: patch geometry (the descriptor
+table in a neutral numpy form) and initial conserved states built from
+primitive fields.  It contains none of the update's arithmetic (no
+reconstruction, flux, divergence or time stepping) and imports neither the GPU
+library nor the oracle; both sides marshal a :class:`PatchSet` into their own
+formats.
+
+Set-ups (the paper's workloads are analytic problems fully specified in its
+text; no dataset is involved):
+
+* :func:`sod` - the 1D shock tube of Sec. 6.1 (Sod 1978), at any N.
+* :func:`grf` / :func:`periodic_turbulent_box` - a 3D periodic box with a
+  Gaussian random density field and Mach 0.5 random velocities, the synthetic
+  stand-in for the paper's uniform-grid 3D runs of Sec. 6.2.
+* :func:`uneven_patches` - thousands of independent patches of uneven sizes
+  8..32 per dimension with smooth states and random planar shocks, the
+  synthetic stand-in for the many grids of an AMR hierarchy (Sec. 3, Sec. 6.3).
+* :func:`advected_wave` - a smooth density wave advected at v = 1 (exact
+  solution known), for convergence tests.
+
+Initial states are set from (rho, v, p) with the ideal-gas relation of Sec. 4,
+rho E = p/(gamma-1) + rho |v|^2 / 2 - the definition of the conserved energy,
+needed identically by both sides to build the same input.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+BC_OUTFLOW, BC_PERIODIC, BC_REFLECT, BC_EXTERNAL = 0, 1, 2, 3
+NVAR = 5
+
+
+@dataclasses.dataclass
+class PatchSet:
+    """A table of patches in a single FP64 arena (SoA per patch).
+
+    Patch p stores ``s = n + 2 g`` cells per dimension (``g = ng`` in the first
+    ``ndim`` dimensions, 0 elsewhere); variable k of patch p starts at element
+    ``offset[p] + k * prod(s)``; x is the fastest index.
+    """
+
+    ndim: int
+    level: np.ndarray   # (np,) int32
+    lo: np.ndarray      # (np,3) int32, lower active index in level space
+    n: np.ndarray       # (np,3) int32, active cells (1 in absent dims)
+    ng: np.ndarray      # (np,) int32
+    bc: np.ndarray      # (np,6) int32, faces -x,+x,-y,+y,-z,+z
+    offset: np.ndarray  # (np,) int64
+    arena: int          # total elements of one arena copy
+    gamma: float = 1.4
+    theta: float = 1.0
+    dx0: tuple = (1.0, 1.0, 1.0)
+
+    @property
+    def npatch(self) -> int:
+        return int(self.n.shape[0])
+
+    def stored_shape(self, p: int):
+        g = [int(self.ng[p]) if d < self.ndim else 0 for d in range(3)]
+        return tuple(int(self.n[p, d]) + 2 * g[d] for d in range(3)), g
+
+    def active_cells(self, level: int = -1) -> int:
+        sel = np.ones(self.npatch, bool) if level < 0 else (self.level == level)
+        return int(np.prod(self.n[sel].astype(np.int64), axis=1).sum())
+
+    def meta(self) -> np.ndarray:
+        """(np, 16) int32 rows: level, lo[3], n[3], ng, bc[6], 0, 0."""
+        m = np.zeros((self.npatch, 16), np.int32)
+        m[:, 0] = self.level
+        m[:, 1:4] = self.lo
+        m[:, 4:7] = self.n
+        m[:, 7] = self.ng
+        m[:, 8:14] = self.bc
+        return m
+
+    def view(self, U: np.ndarray, p: int) -> np.ndarray:
+        """(5, sz, sy, sx) view of patch p (storage incl. ghosts) in arena U."""
+        s, _ = self.stored_shape(p)
+        S = s[0] * s[1] * s[2]
+        o = int(self.offset[p])
+        return U[o:o + NVAR * S].reshape(NVAR, s[2], s[1], s[0])
+
+    def active(self, U: np.ndarray, p: int) -> np.ndarray:
+        """(5, nz, ny, nx) view of the active cells of patch p."""
+        v = self.view(U, p)
+        _, g = self.stored_shape(p)
+        n = self.n[p]
+        return v[:, g[2]:g[2] + n[2], g[1]:g[1] + n[1], g[0]:g[0] + n[0]]
+
+
+def make_patchset(ndim, n, ng, bc, level=None, lo=None, gamma=1.4, theta=1.0, dx0=(1.0, 1.0, 1.0),
+                  align=64) -> PatchSet:
+    """Lay out patches back to back in one arena, each start aligned to ``align`` elements."""
+    n = np.asarray(n, np.int32).reshape(-1, 3)
+    npch = n.shape[0]
+    ng = np.broadcast_to(np.asarray(ng, np.int32), (npch,)).copy()
+    bc = np.broadcast_to(np.asarray(bc, np.int32), (npch, 6)).copy()
+    level = np.zeros(npch, np.int32) if level is None else np.asarray(level, np.int32)
+    lo = np.zeros((npch, 3), np.int32) if lo is None else np.asarray(lo, np.int32).reshape(-1, 3)
+    off = np.zeros(npch, np.int64)
+    cur = 0
+    for p in range(npch):
+        s = [int(n[p, d]) + (2 * int(ng[p]) if d < ndim else 0) for d in range(3)]
+        cur = (cur + align - 1) // align * align
+        off[p] = cur
+        cur += NVAR * s[0] * s[1] * s[2]
+    return PatchSet(ndim, level, lo, n, ng, bc, off, cur, float(gamma), float(theta),
+                    tuple(float(x) for x in dx0))
+
+
+def conserved(rho, vx, vy, vz, p, gamma):
+    """Conserved (rho, rho v, rho E) from primitives (Sec. 4 ideal gas)."""
+    rho = np.asarray(rho, np.float64)
+    E = p / (gamma - 1.0) + 0.5 * rho * (vx * vx + vy * vy + vz * vz)
+    return np.stack(np.broadcast_arrays(rho, rho * vx, rho * vy, rho * vz, E))
+
+
+def new_arena(ps: PatchSet, fill=np.nan) -> np.ndarray:
+    """An arena whose ghost cells hold ``fill`` (NaN: any read of an unfilled ghost shows)."""
+    return np.full(ps.arena, fill, np.float64)
+
+
+# ---------------------------------------------------------------- 1D set-ups
+def sod(N=400, ng=2, gamma=1.4, theta=1.0, x0=0.5):
+    """Sod shock tube (Sec. 6.1): rho,p = 1,1 | 0.125,0.1, v = 0, on [0,1] with outflow ends.
+
+    With N even the interface x0 = 0.5 lies on a cell face, so no cell is mixed.
+    """
+    ps = make_patchset(1, [[N, 1, 1]], ng, [BC_OUTFLOW] * 6, gamma=gamma, theta=theta,
+                       dx0=(1.0 / N, 1.0, 1.0))
+    x = (np.arange(N) + 0.5) / N
+    left = x < x0
+    rho = np.where(left, 1.0, 0.125)
+    p = np.where(left, 1.0, 0.1)
+    z = np.zeros(N)
+    U = new_arena(ps)
+    ps.active(U, 0)[...] = conserved(rho, z, z, z, p, gamma).reshape(5, 1, 1, N)
+    return ps, U
+
+
+def advected_wave(N, ng=2, gamma=1.4, theta=1.0, amp=0.2, ndim=1, axis=0):
+    """rho = 1 + amp sin(2 pi x_axis), v_axis = 1, p = 1, periodic unit box (N^ndim)."""
+    n = [N if d < ndim else 1 for d in range(3)]
+    dx0 = tuple(1.0 / N if d < ndim else 1.0 for d in range(3))
+    ps = make_patchset(ndim, [n], ng, [BC_PERIODIC] * 6, gamma=gamma, theta=theta, dx0=dx0)
+    xc = (np.arange(N) + 0.5) / N
+    shape = (n[2], n[1], n[0])
+    coord = [xc.reshape((1, 1, N)), xc.reshape((1, N, 1)) if ndim > 1 else 0, xc.reshape((N, 1, 1)) if ndim > 2 else 0]
+    rho = np.broadcast_to(1.0 + amp * np.sin(2 * np.pi * coord[axis]), shape)
+    v = [np.zeros(shape) for _ in range(3)]
+    v[axis] = np.ones(shape)
+    U = new_arena(ps)
+    ps.active(U, 0)[...] = conserved(rho, v[0], v[1], v[2], np.ones(shape), gamma)
+    return ps, U
+
+
+# ---------------------------------------------------------------- random fields
+def grf(shape, seed, kmin=1.0, kmax=16.0, alpha=2.0):
+    """Gaussian random field on a periodic grid of ``shape`` (z, y, x).
+
+    White N(0,1) noise (PCG64 ``default_rng(seed)``) -> rFFT -> multiply by
+    |k|^(-alpha/2) for kmin <= |k| <= kmax (integer wave-vector components,
+    Euclidean norm) and 0 elsewhere -> inverse FFT -> zero mean, unit rms.
+    Per-mode power is therefore proportional to |k|^-alpha.
+    """
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal(shape)
+    f = np.fft.rfftn(w)
+    ks = [np.fft.fftfreq(s, 1.0 / s) for s in shape[:-1]] + [np.fft.rfftfreq(shape[-1], 1.0 / shape[-1])]
+    kk = np.zeros(f.shape)
+    for ax, k in enumerate(ks):
+        sh = [1] * len(shape)
+        sh[ax] = -1
+        kk = kk + k.reshape(sh) ** 2
+    kmag = np.sqrt(kk)
+    band = (kmag >= kmin) & (kmag <= kmax)
+    filt = np.zeros_like(kmag)
+    filt[band] = kmag[band] ** (-alpha / 2.0)
+    g = np.fft.irfftn(f * filt, s=shape)
+    g -= g.mean()
+    g /= np.sqrt(np.mean(g * g))
+    return g
+
+
+def periodic_turbulent_box(N=256, seed=20, gamma=5.0 / 3.0, theta=1.0, mach=0.5, ng=2, kmax=16.0,
+                           patch=None):
+    """3D periodic unit box, rho = 1 + 0.1 g, v_d = A g_d (rms |v| = mach * c_s0), p = 1.
+
+    g, g_x, g_y, g_z are :func:`grf` fields with seeds seed..seed+3 in 1 <= |k| <= kmax.
+    ``patch=None`` gives one N^3 patch with periodic faces; ``patch=P`` splits the
+    box into (N/P)^3 patches of P^3 whose faces are EXTERNAL (sibling ghosts).
+    """
+    shape = (N, N, N)
+    rho = 1.0 + 0.1 * grf(shape, seed, 1.0, kmax)
+    cs0 = math.sqrt(gamma * 1.0 / 1.0)
+    A = mach * cs0 / math.sqrt(3.0)
+    vx, vy, vz = (A * grf(shape, seed + 1 + i, 1.0, kmax) for i in range(3))
+    U5 = conserved(rho, vx, vy, vz, np.ones(shape), gamma)
+    if patch is None:
+        ps = make_patchset(3, [[N, N, N]], ng, [BC_PERIODIC] * 6, gamma=gamma, theta=theta,
+                           dx0=(1.0 / N,) * 3)
+        U = new_arena(ps)
+        ps.active(U, 0)[...] = U5
+        return ps, U
+    m = N // patch
+    assert m * patch == N
+    los = np.array([[i * patch, j * patch, k * patch] for k in range(m) for j in range(m) for i in range(m)],
+                   np.int32)
+    ps = make_patchset(3, [[patch] * 3] * len(los), ng, [BC_EXTERNAL] * 6, lo=los, gamma=gamma, theta=theta,
+                       dx0=(1.0 / N,) * 3)
+    U = new_arena(ps)
+    for p, lo in enumerate(los):
+        ps.active(U, p)[...] = U5[:, lo[2]:lo[2] + patch, lo[1]:lo[1] + patch, lo[0]:lo[0] + patch]
+    return ps, U
+
+
+def random_state(ps: PatchSet, seed, U=None, amp=0.3, vamp=0.5, shocks=0.0):
+    """Smooth random state on every patch of ``ps`` (see :func:`uneven_patches`)."""
+    rng = np.random.default_rng(seed)
+    g = ps.gamma
+    U = new_arena(ps) if U is None else U
+    for p in range(ps.npatch):
+        n = ps.n[p]
+        xi = [(np.arange(int(n[d])) + 0.5) / int(n[d]) for d in range(3)]
+        Z, Y, X = np.meshgrid(xi[2], xi[1], xi[0], indexing="ij")
+        pos = np.stack([X, Y, Z])
+
+        def S():
+            tot = np.zeros(X.shape)
+            for _ in range(3):
+                while True:
+                    k = rng.integers(-2, 3, size=3)
+                    k[ps.ndim:] = 0
+                    if 0 < (k * k).sum() <= 4:
+                        break
+                ph = rng.uniform(0, 2 * np.pi)
+                tot += np.sin(2 * np.pi * np.tensordot(k, pos, axes=1) + ph)
+            return tot / 3.0
+
+        rho = 1.0 + amp * S()
+        vel = [vamp * S() if d < ps.ndim else np.zeros(X.shape) for d in range(3)]
+        pr = 1.0 + amp * S()
+        if shocks > 0 and rng.uniform() < shocks:
+            nv = rng.standard_normal(3)
+            nv[ps.ndim:] = 0
+            nv /= np.linalg.norm(nv)
+            x0 = rng.uniform(0.25, 0.75, size=3)
+            down = np.tensordot(nv, pos - x0.reshape(3, 1, 1, 1), axes=1) < 0
+            # Rankine-Hugoniot jump of pressure ratio 10 into the local pre-shock state
+            p2 = 10.0 * pr
+            ratio = ((g + 1) * 10.0 + (g - 1)) / ((g - 1) * 10.0 + (g + 1))
+            A = 2.0 / ((g + 1) * rho)
+            B = (g - 1) * pr / (g + 1)
+            du = (p2 - pr) * np.sqrt(A / (p2 + B))
+            for d in range(3):
+                vel[d] = np.where(down, vel[d] + du * nv[d], vel[d])
+            rho = np.where(down, rho * ratio, rho)
+            pr = np.where(down, p2, pr)
+        ps.active(U, p)[...] = conserved(rho, vel[0], vel[1], vel[2], pr, g)
+    return U
+
+
+def uneven_patches(npatch=4000, seed=30, sizes=(8, 16, 24, 32), ng=3, gamma=5.0 / 3.0, theta=1.0,
+                   dx=1.0 / 64, shock_frac=0.2, with_state=True):
+    """Independent patches with each n_d drawn uniformly from ``sizes`` (seeded).
+
+    Outflow on every face.  State per patch in local coordinates xi in [0,1]^3:
+    rho = 1 + 0.2 S, v_d = 0.3 S, p = 1 + 0.2 S, each S the mean of 3 sinusoids
+    with random integer wave vectors (|k| <= 2) and phases; a Bernoulli(shock_frac)
+    subset gets a planar shock of pressure ratio 10 (normal uniform on the sphere,
+    through a uniform point of the central half of the patch).
+    """
+    rng = np.random.default_rng(seed)
+    n = rng.choice(np.asarray(sizes, np.int32), size=(npatch, 3))
+    ps = make_patchset(3, n, ng, [BC_OUTFLOW] * 6, gamma=gamma, theta=theta, dx0=(dx, dx, dx))
+    if not with_state:
+        return ps, None
+    U = random_state(ps, seed + 1, amp=0.2, vamp=0.3, shocks=shock_frac)
+    return ps, U
