@@ -1,0 +1,192 @@
+/* amr_hydro.h - C ABI of the MI355X (gfx950) per-patch hydro update.
+ *
+ * The library advances the Euler equations of Wang, Abel & Kaehler,
+ * "Adaptive Mesh Fluid Simulations on GPU", Sec. 4 (conservation law in
+ * conserved variables U = (rho, rho vx, rho vy, rho vz, rho E), ideal-gas EOS
+ * p = (gamma-1) rho e), discretised by the method of lines (Sec. 4, MOL
+ * equation dU/dt = L(U)) with PLM theta-minmod reconstruction of primitives
+ * (Sec. 4, PLM and minmod equations), the paper's Riemann flux on every face of
+ * every active dimension (Sec. 4, flux equation) and the two-stage TVD
+ * Runge-Kutta scheme (Sec. 4, RK2 equation; three-step form of Sec. 5.1), on
+ * each grid patch of a block-structured AMR hierarchy (Sec. 3), one patch being
+ * the unit of GPU work (Sec. 5.2, Sec. 8).
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns an amr_status: AMR_OK (0) or a negative code.
+ *   - Device pointers (U, dt_dev) are caller-owned device memory (hipMalloc or
+ *     a framework allocator); the caller keeps them alive until the stream
+ *     work that uses them completes.
+ *   - Streams: all work is enqueued on the caller's stream `stream` (0 = the
+ *     null stream) and returns without waiting, unless a host pointer for a
+ *     result is given (then the call synchronises that stream).
+ *   - Argument errors are detected on the host before anything is enqueued and
+ *     return AMR_EINVAL with nothing changed.  HIP runtime failures return
+ *     AMR_EHIP.  An unphysical state met on the device (rho <= 0, e <= 0 or a
+ *     non-finite value in a cell the stencil reads) is latched in the table and
+ *     returned as AMR_EUNPHYSICAL by the next synchronising call
+ *     (amr_cfl_dt with dt_host, amr_table_status); the U it produced is not
+ *     meaningful.  Recovery (restore U^n, retry with a smaller dt) is the
+ *     caller's.
+ *   - A table is not thread-safe; calls on one table must be serialised.
+ *
+ * The U arena (layout of conserved state, caller-owned, FP64)
+ *   One contiguous array of doubles holds every patch.  Patch p with n[d]
+ *   active cells and ng ghost layers per side in each active dimension d < ndim
+ *   (no ghosts, n[d] = 1 in absent dimensions) stores s[d] = n[d] + 2 g[d]
+ *   cells per dimension, x fastest; variable k (0..4 in the order of U above)
+ *   of storage cell (ix, iy, iz) is at element
+ *       offset + k * S + (iz * s[1] + iy) * s[0] + ix,   S = s[0] s[1] s[2].
+ *   Active cells are ix in [g, g + n[0]) and likewise in y and z.  Patches
+ *   must not overlap.  Ghost storage is only read on faces whose boundary
+ *   condition is AMR_BC_EXTERNAL (filled by the library from other patches);
+ *   the other conditions are applied by index mapping, so those ghost cells
+ *   may hold anything.  The library never writes ghost cells of non-EXTERNAL
+ *   faces and writes only active cells of U otherwise.
+ */
+#ifndef AMR_HYDRO_H
+#define AMR_HYDRO_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t amr_status;
+#define AMR_OK 0
+#define AMR_EINVAL (-1)       /* bad argument; nothing was enqueued            */
+#define AMR_ENOMEM (-2)       /* device or host allocation failed             */
+#define AMR_EHIP (-3)         /* a HIP runtime call failed                     */
+#define AMR_EUNPHYSICAL (-4)  /* rho <= 0, e <= 0 or non-finite state met       */
+#define AMR_ESTATE (-5)       /* call not valid in the table's current state    */
+
+/* Boundary condition of one patch face (Sec. 3 ghost zones; on-the-fly maps):
+ *   OUTFLOW  ghost = copy of the nearest active cell (zero gradient),
+ *   PERIODIC ghost = active cell one patch-length away (wrap within the patch),
+ *   REFLECT  ghost = mirror image across the face, normal momentum negated,
+ *   EXTERNAL ghost = filled by the library from the same-level patch that
+ *            covers it (sibling copy); ghost storage is read by the stencil. */
+enum { AMR_BC_OUTFLOW = 0, AMR_BC_PERIODIC = 1, AMR_BC_REFLECT = 2, AMR_BC_EXTERNAL = 3 };
+/* Face flux: AMR_FLUX_PAPER = the formula printed in Sec. 4,
+ *   F = (F_L + F_R - lambda0 (U_R - U_L)) / 2, lambda0 = max(a+, a-);
+ * AMR_FLUX_HLL2 = the two-speed HLL flux with the same a+, a-:
+ *   F = (a+ F_L + a- F_R - a+ a- (U_R - U_L)) / (a+ + a-). */
+enum { AMR_FLUX_PAPER = 0, AMR_FLUX_HLL2 = 1 };
+/* Arithmetic: FP64 throughout, or FP32 reconstruction and face flux with the
+ * conserved->primitive conversion (pressure recovery), the flux divergence and
+ * the RK combine in FP64. */
+enum { AMR_PREC_FP64 = 0, AMR_PREC_MIXED = 1 };
+/* Execution form: PLAIN = one launch per patch per stage; BATCHED = one
+ * persistent launch per stage over a tile list of all selected patches, the
+ * whole RK2 step replayed from a captured HIP graph. */
+enum { AMR_EXEC_PLAIN = 0, AMR_EXEC_BATCHED = 1 };
+
+/* flags of amr_hydro_rk2_step */
+#define AMR_STEP_FUSE_DT 0x1u /* stage 2 also reduces the max signal speed of U^{n+1}; the
+                                 next amr_cfl_dt on the same U and level then reads it
+                                 instead of scanning U again */
+
+typedef struct {
+  int32_t level;    /* refinement level, 0 = root; cell width dx0[d] / 2^level          */
+  int32_t lo[3];    /* index of the first active cell in level index space             */
+  int32_t n[3];     /* active cells per dimension, >= 1; 1 in dimensions >= ndim       */
+  int32_t ng;       /* ghost layers per side in active dimensions, 2 <= ng <= 8, ng <= n */
+  int64_t offset;   /* element offset of variable 0 of this patch in the U arena       */
+  int32_t bc[6];    /* AMR_BC_* of faces -x, +x, -y, +y, -z, +z                         */
+  int32_t reserved[2]; /* must be 0                                                    */
+} amr_patch_desc;
+
+typedef struct {
+  int32_t nvar;      /* number of conserved variables; must be 5 (Sec. 4)                */
+  int32_t ndim;      /* 1, 2 or 3 active dimensions                                      */
+  double gamma;      /* adiabatic index of p = (gamma-1) rho e, > 1                      */
+  double theta;      /* PLM limiter parameter, 0 <= theta <= 2 (Sec. 4)                  */
+  double dx0[3];     /* root-level cell widths, > 0                                      */
+  int32_t flux;      /* AMR_FLUX_*                                                       */
+  int32_t precision; /* AMR_PREC_*                                                       */
+  int32_t exec;      /* AMR_EXEC_*                                                       */
+  int32_t periodic;  /* bit d set: the root domain is periodic in d, so EXTERNAL ghost
+                        cells beyond the domain wrap (needs domain[d])                   */
+  int32_t domain[3]; /* root-level domain extent in cells per dimension (0 = not given)  */
+  int32_t reserved0; /* must be 0                                                        */
+  double rho_floor;  /* > 0: floor applied to recovered density (primitives only); 0 = off */
+  double e_floor;    /* > 0: floor applied to recovered specific internal energy; 0 = off */
+} amr_physics;
+
+typedef struct amr_table amr_table; /* opaque, library-owned */
+
+/* Create a table for `npatch` patches (Sec. 3 hierarchy as a flat list).
+ * Copies the descriptors, validates them (AMR_EINVAL on: npatch < 1, n < 1,
+ * ng out of range in an active dimension, n > 1 in an absent dimension,
+ * overlapping storage, unknown bc/flux/precision/exec, nvar != 5,
+ * gamma <= 1, theta outside [0,2], dx0 <= 0, a PERIODIC face whose opposite
+ * face is not PERIODIC), allocates the device-side copy, the stage scratch
+ * arena U^(1) (same size as the U arena) and the reduction/flag words, builds
+ * the tile lists and selects the default tile shape.  Uses the current HIP
+ * device; `stream` orders the uploads.  On success *out owns all of that until
+ * amr_patch_table_destroy. */
+amr_status amr_patch_table_create(const amr_patch_desc* patches, int32_t npatch, const amr_physics* phys,
+                                  hipStream_t stream, amr_table** out);
+
+/* Free everything the table owns (waits for the device to finish using it). */
+amr_status amr_patch_table_destroy(amr_table* table);
+
+/* Number of doubles the U arena must hold (max over patches of offset + 5 S). */
+int64_t amr_table_arena_elems(const amr_table* table);
+
+/* Global CFL time step (the rule the paper leaves unstated; see the design
+ * notes): dt = cfl / max over active cells of sum_d (|v_d| + c_s) / dx_d, with
+ * c_s = sqrt(gamma p / rho), over the patches of `level` (-1 = all levels).
+ * With several levels and level = -1 the root step of a factor-2 subcycled
+ * hierarchy is returned: dt0 = cfl * min_l 2^l / smax_l.  The result is written
+ * to dt_dev[0] (device, caller-owned).  If dt_host is not NULL the call waits
+ * for the stream, copies the value there, and returns AMR_EUNPHYSICAL if the
+ * device flag is set.  The max is order-independent, so the value is
+ * deterministic. */
+amr_status amr_cfl_dt(amr_table* table, const double* U, double cfl, int32_t level, double* dt_dev,
+                      double* dt_host, hipStream_t stream);
+
+/* One TVD-RK2 step (Sec. 4, RK2 equation) of the patches of `level` (-1 = all),
+ * in place:  U^(1) = U^n + dt L(U^n) (into the table's scratch arena), then
+ * U^{n+1} = U^n/2 + (U^(1) + dt L(U^(1)))/2 written over U^n.  dt is read from
+ * dt_dev[0] on the device when the step runs (so a captured step replays with
+ * new values).  EXTERNAL ghosts of the stage input are filled before each
+ * stage.  flags: AMR_STEP_*.  Asynchronous. */
+amr_status amr_hydro_rk2_step(amr_table* table, double* U, const double* dt_dev, int32_t level, uint32_t flags,
+                              hipStream_t stream);
+
+/* Coarse/fine flux correction and restriction for `coarse_level` (Berger &
+ * Colella refluxing, Sec. 3).  Returns AMR_ESTATE for tables without a
+ * coarse/fine interface at that level. */
+amr_status amr_flux_correct(amr_table* table, double* U, int32_t coarse_level, hipStream_t stream);
+
+/* Wait for `stream`, then return AMR_EUNPHYSICAL if any kernel latched an
+ * unphysical state since the table was created or last cleared, else AMR_OK.
+ * Clears the latch. */
+amr_status amr_table_status(amr_table* table, hipStream_t stream);
+
+/* Tile shape control (batched and plain forms share the kernels).
+ * amr_table_num_tilings: number of compiled tile shapes.
+ * amr_table_set_tiling: select shape `id` (0 <= id < num) and z-slab length
+ *   zslab (>= 1; 0 = the shape's default); invalidates a captured graph.
+ * amr_table_get_tiling: current id and zslab.
+ * amr_table_tiling_shape: the (TX, TY) cells per tile of shape `id`. */
+int32_t amr_table_num_tilings(const amr_table* table);
+amr_status amr_table_set_tiling(amr_table* table, int32_t id, int32_t zslab);
+amr_status amr_table_get_tiling(const amr_table* table, int32_t* id, int32_t* zslab);
+amr_status amr_table_tiling_shape(const amr_table* table, int32_t id, int32_t* tx, int32_t* ty);
+
+/* Autotuner: time every (shape, zslab) candidate on the caller's data with
+ * HIP events (each candidate runs `reps` full RK2 steps on a copy of U held
+ * in the table's scratch, so U is not modified), keep the fastest, and
+ * return its time per step in *ms_best (nullable).  Synchronises the stream. */
+amr_status amr_autotune(amr_table* table, const double* U, const double* dt_dev, int32_t level, int32_t reps,
+                        hipStream_t stream, float* ms_best);
+
+const char* amr_status_string(amr_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMR_HYDRO_H */

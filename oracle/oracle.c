@@ -133,6 +133,44 @@ void or_face_flux(const or_phys* ph, int d, const double qL[5], const double qR[
 }
 
 /* ---------------------------------------------------------------- O1 ghosts */
+/* EXTERNAL face of patch p: each ghost cell takes the value of the same cell
+ * (in level index space) of the same-level patch that holds it as an active
+ * cell (Sec. 3: grids of one level exchange boundary values). */
+static void fill_external(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph, double* V, int p,
+                          const geom* G, int d, int side) {
+  const int32_t* m = meta + (size_t)p * OR_META;
+  int a = (d + 1) % 3, b = (d + 2) % 3;
+  for (int layer = 1; layer <= G->g[d]; ++layer) {
+    int gi = side == 0 ? -layer : G->n[d] - 1 + layer;
+    for (int ib = 0; ib < G->n[b]; ++ib)
+      for (int ia = 0; ia < G->n[a]; ++ia) {
+        int cg[3], L[3];
+        cg[d] = gi; cg[a] = ia; cg[b] = ib;
+        for (int e = 0; e < 3; ++e) {
+          L[e] = m[1 + e] + cg[e]; /* level index space */
+          if (e < ph->ndim && ((ph->periodic >> e) & 1)) {
+            int dom = ph->domain[e] << m[0];
+            L[e] = ((L[e] % dom) + dom) % dom;
+          }
+        }
+        for (int q = 0; q < np; ++q) {
+          const int32_t* mq = meta + (size_t)q * OR_META;
+          if (mq[0] != m[0]) continue;
+          int inside = 1;
+          for (int e = 0; e < ph->ndim; ++e)
+            if (L[e] < mq[1 + e] || L[e] >= mq[1 + e] + mq[4 + e]) inside = 0;
+          if (!inside) continue;
+          geom Q = get_geom(mq, off[q], ph->ndim);
+          int cs[3] = {0, 0, 0};
+          for (int e = 0; e < ph->ndim; ++e) cs[e] = L[e] - mq[1 + e];
+          for (int k = 0; k < ph->nvar; ++k) V[at(G, k, cg)] = V[at(&Q, k, cs)];
+          break;
+        }
+      }
+  }
+}
+
+
 int or_fill_ghosts(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph,
                    double* V, int32_t level) {
   for (int p = 0; p < np; ++p) {
@@ -143,7 +181,10 @@ int or_fill_ghosts(int32_t np, const int32_t* meta, const int64_t* off, const or
       int a = (d + 1) % 3, b = (d + 2) % 3; /* the two other dimensions */
       for (int side = 0; side < 2; ++side) {
         int bc = G.bc[2 * d + side];
-        if (bc == OR_BC_EXTERNAL) continue; /* filled by the caller */
+        if (bc == OR_BC_EXTERNAL) {
+          fill_external(np, meta, off, ph, V, p, &G, d, side);
+          continue;
+        }
         for (int layer = 1; layer <= G.g[d]; ++layer) {
           int gi = side == 0 ? -layer : G.n[d] - 1 + layer; /* ghost index along d */
           int si;                                            /* source index along d */

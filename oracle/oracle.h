@@ -31,7 +31,8 @@ typedef struct {
   int32_t nvar, ndim;
   double gamma, theta;
   double dx0[3];
-  int32_t flux, pad;
+  int32_t flux, periodic;  /* periodic: bit d = root domain periodic in d (EXTERNAL ghosts wrap) */
+  int32_t domain[3], pad;  /* root-level domain extent in cells */
   double rho_floor, e_floor;
 } or_phys;
 
@@ -48,8 +49,11 @@ void or_face_flux(const or_phys* ph, int d, const double qL[5], const double qR[
 /* Physical flux F^d(U(q)) of Sec. 4 for one primitive state. */
 void or_phys_flux(const or_phys* ph, int d, const double q[5], double F[5]);
 
-/* O1: fill the face ghosts (two layers or ng, whichever is set) of every patch
- * on `level` (-1 = all) from the boundary condition of each face. */
+/* O1: fill the face ghosts (all ng layers, over the active range of the other
+ * dimensions) of every patch on `level` (-1 = all) from the boundary condition
+ * of each face.  EXTERNAL ghosts are copied from the same-level patch whose
+ * active cells contain them (after periodic wrap of the root domain); ghosts
+ * with no such patch are left untouched. */
 int or_fill_ghosts(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph,
                    double* V, int32_t level);
 /* L(V) of the MOL equation for one patch, written to L (5 x active cells, x fastest).

@@ -23,7 +23,8 @@ FLUX_PAPER, FLUX_HLL2 = 0, 1
 
 class Phys(C.Structure):
     _fields_ = [("nvar", C.c_int32), ("ndim", C.c_int32), ("gamma", C.c_double), ("theta", C.c_double),
-                ("dx0", C.c_double * 3), ("flux", C.c_int32), ("pad", C.c_int32),
+                ("dx0", C.c_double * 3), ("flux", C.c_int32), ("periodic", C.c_int32),
+                ("domain", C.c_int32 * 3), ("pad", C.c_int32),
                 ("rho_floor", C.c_double), ("e_floor", C.c_double)]
 
 
@@ -63,11 +64,14 @@ def _dp(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-def phys(gamma=1.4, theta=1.0, ndim=3, dx0=(1.0, 1.0, 1.0), flux=FLUX_PAPER, rho_floor=0.0, e_floor=0.0):
+def phys(gamma=1.4, theta=1.0, ndim=3, dx0=(1.0, 1.0, 1.0), flux=FLUX_PAPER, rho_floor=0.0, e_floor=0.0,
+         periodic=0, domain=(0, 0, 0)):
     ph = Phys()
     ph.nvar, ph.ndim, ph.gamma, ph.theta = 5, ndim, gamma, theta
+    ph.periodic = periodic
     for d in range(3):
         ph.dx0[d] = dx0[d]
+        ph.domain[d] = int(domain[d])
     ph.flux, ph.rho_floor, ph.e_floor = flux, rho_floor, e_floor
     return ph
 
@@ -101,9 +105,10 @@ def phys_flux(ph, d, q):
 class Oracle:
     """Oracle bound to one patch table.  All arrays are FP64 arenas laid out as ``ps``."""
 
-    def __init__(self, ps, flux=FLUX_PAPER, rho_floor=0.0, e_floor=0.0, theta=None):
+    def __init__(self, ps, flux=FLUX_PAPER, rho_floor=0.0, e_floor=0.0, theta=None, periodic=0, domain=(0, 0, 0)):
         self.ps = ps
-        self.ph = phys(ps.gamma, ps.theta if theta is None else theta, ps.ndim, ps.dx0, flux, rho_floor, e_floor)
+        self.ph = phys(ps.gamma, ps.theta if theta is None else theta, ps.ndim, ps.dx0, flux, rho_floor, e_floor,
+                       periodic, domain)
         self.meta = np.ascontiguousarray(ps.meta(), np.int32)
         self.off = np.ascontiguousarray(ps.offset, np.int64)
         self._W = None

@@ -1,0 +1,65 @@
+// amr_internal.h - kernel argument blocks and launcher declarations shared by
+// the kernels (amr_kernels.hip) and the host library (amr_api.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "amr_device.h"
+
+namespace amr {
+
+struct StageArgs {
+  const double* V;               // stage input arena (EXTERNAL ghosts filled)
+  const double* U0;              // U^n (stage 2 only)
+  double* out;                   // stage output arena (U^(1), or U^{n+1} in place over U^n)
+  const double* dt;              // device scalar, read when the stage runs
+  const PatchDev* patches;
+  const Tile* tiles;
+  int ntiles;
+  int pad;
+  int* flag;                     // unphysical-state latch
+  unsigned long long* smax;      // stage 2: per-level max signal speed of U^{n+1}, or nullptr
+  Consts c;
+};
+
+struct CflArgs {
+  const double* U;
+  const PatchDev* patches;
+  const Tile* tiles;
+  int ntiles, tx, ty, pad;
+  int* flag;
+  unsigned long long* smax;      // per-level maxima
+  Consts c;
+};
+
+// Block-wide max of a non-negative double merged into *dst with a 64-bit
+// atomicMax on its bit pattern.  Must be called by every lane of the block.
+__device__ __forceinline__ void block_max_to(unsigned long long* dst, double v) {
+  __shared__ double red[NT / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();  // red[] may still be read by a previous call
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
+    if (m > 0) atomicMax(dst, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+hipError_t launch_stage(int mixed, int shape, int stage, int grid, hipStream_t s, const StageArgs& a);
+const void* stage_kernel_ptr(int mixed, int shape, int stage);
+hipError_t launch_cfl(int grid, hipStream_t s, const CflArgs& a);
+hipError_t launch_cfl_finalize(hipStream_t s, const unsigned long long* smax, int lmin, int lmax, int root,
+                               double cfl, double* dt);
+hipError_t launch_copy_ghosts(int grid, hipStream_t s, const CopyOp* ops, int nops, const PatchDev* p, double* A);
+hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, int n, unsigned long long v);
+hipError_t launch_fill_i32(hipStream_t s, int* p, int n, int v);
+
+// Compiled tile shapes (TX x TY lanes = 256); shape 0 is the 1D shape.
+constexpr int NSHAPES = 5;
+constexpr int SHAPE_TX[NSHAPES] = {256, 32, 64, 16, 128};
+constexpr int SHAPE_TY[NSHAPES] = {1, 8, 4, 16, 2};
+
+}  // namespace amr

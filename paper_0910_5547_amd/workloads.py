@@ -181,7 +181,7 @@ def grf(shape, seed, kmin=1.0, kmax=16.0, alpha=2.0):
     band = (kmag >= kmin) & (kmag <= kmax)
     filt = np.zeros_like(kmag)
     filt[band] = kmag[band] ** (-alpha / 2.0)
-    g = np.fft.irfftn(f * filt, s=shape)
+    g = np.fft.irfftn(f * filt, s=shape, axes=tuple(range(len(shape))))
     g -= g.mean()
     g /= np.sqrt(np.mean(g * g))
     return g

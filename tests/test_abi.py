@@ -1,0 +1,141 @@
+"""C-ABI checks that need no GPU: the HIP library loads, exports every entry
+point include/amr_hydro.h declares, its structs have the layout the binding
+assumes, and argument validation (done on the host before any HIP call)
+rejects malformed tables with AMR_EINVAL."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_0910_5547_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "amr_hydro.h")
+
+
+@pytest.fixture(scope="module")
+def amr():
+    from paper_0910_5547_amd import amr as A
+    if not os.path.exists(A.LIB_PATH):
+        from paper_0910_5547_amd import build
+        build.build()
+    A.lib()
+    return A
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(amr_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_entry_point_is_exported(amr):
+    names = declared_functions()
+    assert "amr_hydro_rk2_step" in names and "amr_cfl_dt" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", amr.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r" T (amr_\w+)", out))
+    assert set(names) <= exported, set(names) - exported
+    assert set(names) == set(amr.EXPORTED)
+    for n in names:
+        getattr(amr.lib(), n)
+
+
+def test_struct_layout_matches_binding(amr, tmp_path):
+    prog = tmp_path / "layout.c"
+    prog.write_text('''
+#include <stddef.h>
+#include <stdio.h>
+#include "amr_hydro.h"
+#define F(T, m) printf(#T "." #m " %zu\\n", offsetof(T, m));
+int main(void) {
+  printf("amr_patch_desc %zu\\n", sizeof(amr_patch_desc));
+  printf("amr_physics %zu\\n", sizeof(amr_physics));
+  F(amr_patch_desc, level) F(amr_patch_desc, lo) F(amr_patch_desc, n) F(amr_patch_desc, ng)
+  F(amr_patch_desc, offset) F(amr_patch_desc, bc) F(amr_patch_desc, reserved)
+  F(amr_physics, gamma) F(amr_physics, theta) F(amr_physics, dx0) F(amr_physics, flux)
+  F(amr_physics, precision) F(amr_physics, exec) F(amr_physics, periodic) F(amr_physics, domain)
+  F(amr_physics, reserved0) F(amr_physics, rho_floor) F(amr_physics, e_floor)
+  return 0;
+}''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include",
+                    str(prog), "-o", str(exe)], check=True)
+    got = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                               check=True).stdout.split("\n") if line)
+    assert int(got["amr_patch_desc"]) == C.sizeof(amr.amr_patch_desc)
+    assert int(got["amr_physics"]) == C.sizeof(amr.amr_physics)
+    for key, val in got.items():
+        if "." in key:
+            T, m = key.split(".")
+            assert getattr(getattr(amr, T), m).offset == int(val), key
+
+
+def _create(amr, ps, **kw):
+    descs = amr.descriptors(ps)
+    ph = amr.physics(ps, **kw)
+    h = C.c_void_p()
+    st = amr.lib().amr_patch_table_create(descs, len(descs), C.byref(ph), None, C.byref(h))
+    return st, descs, ph
+
+
+@pytest.mark.parametrize("mutate", [
+    lambda d, ph: setattr(d[0], "ng", 1),
+    lambda d, ph: setattr(d[0], "ng", 9),
+    lambda d, ph: d[0].n.__setitem__(0, 0),
+    lambda d, ph: d[0].n.__setitem__(0, 1),          # n < ng in an active dimension
+    lambda d, ph: setattr(d[1], "offset", d[0].offset + 10),  # overlapping storage
+    lambda d, ph: setattr(d[0], "offset", -1),
+    lambda d, ph: d[0].bc.__setitem__(0, 7),
+    lambda d, ph: d[0].bc.__setitem__(0, 1),          # periodic on one side only
+    lambda d, ph: setattr(d[0], "level", -1),
+    lambda d, ph: d[0].reserved.__setitem__(0, 1),
+    lambda d, ph: setattr(ph, "nvar", 8),
+    lambda d, ph: setattr(ph, "ndim", 4),
+    lambda d, ph: setattr(ph, "gamma", 1.0),
+    lambda d, ph: setattr(ph, "theta", 2.5),
+    lambda d, ph: ph.dx0.__setitem__(1, 0.0),
+    lambda d, ph: setattr(ph, "flux", 5),
+    lambda d, ph: setattr(ph, "precision", 3),
+    lambda d, ph: setattr(ph, "exec", 2),
+    lambda d, ph: setattr(ph, "periodic", 1),         # periodic root domain without extent
+])
+def test_invalid_tables_are_rejected_on_the_host(amr, mutate):
+    ps = W.make_patchset(3, [[8, 8, 8], [8, 8, 8]], 2, [W.BC_OUTFLOW] * 6)
+    descs = amr.descriptors(ps)
+    ph = amr.physics(ps)
+    mutate(descs, ph)
+    h = C.c_void_p()
+    st = amr.lib().amr_patch_table_create(descs, len(descs), C.byref(ph), None, C.byref(h))
+    assert st == amr.AMR_EINVAL
+    assert not h.value
+
+
+def test_uncovered_external_ghosts_are_rejected(amr):
+    ps = W.make_patchset(3, [[8, 8, 8]], 2, [W.BC_EXTERNAL] + [W.BC_OUTFLOW] * 5)
+    descs = amr.descriptors(ps)
+    ph = amr.physics(ps)
+    h = C.c_void_p()
+    assert amr.lib().amr_patch_table_create(descs, 1, C.byref(ph), None, C.byref(h)) == amr.AMR_EINVAL
+
+
+def test_null_arguments(amr):
+    L = amr.lib()
+    assert L.amr_patch_table_create(None, 1, None, None, None) == amr.AMR_EINVAL
+    assert L.amr_patch_table_destroy(None) == amr.AMR_EINVAL
+    assert L.amr_hydro_rk2_step(None, None, None, -1, 0, None) == amr.AMR_EINVAL
+    assert L.amr_cfl_dt(None, None, 0.8, -1, None, None, None) == amr.AMR_EINVAL
+    assert L.amr_table_status(None, None) == amr.AMR_EINVAL
+    assert L.amr_table_arena_elems(None) == -1
+    assert amr.amr_status_string(amr.AMR_EUNPHYSICAL).startswith("AMR_EUNPHYSICAL")
+
+
+def test_workload_generators_are_seeded():
+    ps, U = W.uneven_patches(npatch=6, seed=30)
+    ps2, U2 = W.uneven_patches(npatch=6, seed=30)
+    assert np.array_equal(ps.n, ps2.n) and np.array_equal(U, U2, equal_nan=True)
+    g = W.grf((16, 16, 16), 20, 1, 4)
+    assert abs(g.mean()) < 1e-12 and abs(np.sqrt((g * g).mean()) - 1) < 1e-12

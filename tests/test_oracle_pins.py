@@ -320,3 +320,22 @@ def test_unphysical_state_is_flagged(oracle_lib):
     assert o.rk2_step(U.copy(), 0.01) == 0
     ps.active(U, 0)[4, 0, 0, 3] = -1.0
     assert o.rk2_step(U, 0.01) == 1
+
+
+def test_external_sibling_ghosts_equal_single_patch(oracle_lib):
+    """A periodic box cut into 8 patches with EXTERNAL faces (sibling ghosts, periodic
+    wrap of the root domain) evolves bitwise like the same box as one periodic patch."""
+    N, P = 16, 8
+    ps1, U1 = W.periodic_turbulent_box(N=N, seed=3, kmax=4.0)
+    ps8, U8 = W.periodic_turbulent_box(N=N, seed=3, kmax=4.0, patch=P)
+    o1 = oracle_lib.Oracle(ps1)
+    o8 = oracle_lib.Oracle(ps8, periodic=7, domain=(N, N, N))
+    for _ in range(3):
+        dt = o1.cfl_dt(U1, 0.8)
+        assert dt == o8.cfl_dt(U8, 0.8)
+        o1.rk2_step(U1, dt)
+        o8.rk2_step(U8, dt)
+    a = ps1.active(U1, 0)
+    for p in range(ps8.npatch):
+        lo = ps8.lo[p]
+        assert np.array_equal(ps8.active(U8, p), a[:, lo[2]:lo[2] + P, lo[1]:lo[1] + P, lo[0]:lo[0] + P])
