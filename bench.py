@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Benchmark of the per-patch hydro update: cell-updates/s of full TVD-RK2 steps.
+
+One "step" is the whole hot path over the workload: the CFL time step (a
+device-side reduction; fused into the previous step's second stage) and one
+TVD-RK2 step (two stage kernels: conserved->primitive, PLM, face fluxes,
+divergence, RK combine).  Inputs are resident in HBM before the timed region.
+
+Workloads (seeded, synthetic; see paper_0910_5547_amd.workloads):
+  box256       256^3 periodic box, gamma 5/3, GRF density (k^-2, 1<=|k|<=16),
+               Mach 0.5 GRF velocities, p = 1 (the default, one patch)
+  patches4000  4000 independent patches, sizes 8..32 per dimension, 3 ghost
+               layers, smooth states with random planar shocks in 20%
+
+Three forms are timed on identical inputs: plain FP64 (one launch per patch
+per stage), batched FP64 (persistent launch per stage, graph-replayed step) and
+batched mixed (FP32 reconstruction and flux, FP64 accumulation).  `value` is
+the batched mixed form.  Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0           # MI355X HBM3E
+BYTES_PER_CELL_STEP = 200        # 5 passes x 5 variables x 8 B (stage 1: read U, write U1; stage 2: read U1, U, write)
+BYTES_STAGE = (80, 120)          # per active cell, stage 1 and stage 2
+METRIC = "cell-updates/s per RK2 step (batched FP32/FP64 vs plain FP64); % HBM peak"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    from paper_0910_5547_amd import workloads as W
+    if name == "box256":
+        ps, U = W.periodic_turbulent_box(N=256, seed=20)
+        desc = "periodic box 256^3, gamma=5/3, rho=1+0.1 GRF(k^-2, 1<=|k|<=16, seed 20), Mach 0.5 GRF velocities, p=1"
+    elif name == "patches4000":
+        ps, U = W.uneven_patches(npatch=4000, seed=30)
+        desc = "4000 patches, n_d in {8,16,24,32} (seed 30), ng=3, outflow, smooth states + 20% planar shocks"
+    elif name.startswith("box"):
+        N = int(name[3:])
+        ps, U = W.periodic_turbulent_box(N=N, seed=20, kmax=min(16.0, N / 4))
+        desc = f"periodic box {N}^3"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return ps, U, desc
+
+
+def time_form(A, torch, ps, U, precision, exec_form, steps, warmup, tune=True):
+    T = A.Table(ps, precision=precision, exec_form=exec_form)
+    Ud = T.upload(U)
+    T.cfl_dt(Ud, 0.8)
+    if tune:
+        ms = A.amr_autotune(T.h, Ud, T.dt, -1, 3)
+        log(f"  autotune: best {A.amr_table_get_tiling(T.h)} at {ms:.3f} ms/step")
+    fuse = A.AMR_STEP_FUSE_DT
+    for _ in range(warmup):
+        A.amr_cfl_dt(T.h, Ud, 0.8, -1, T.dt)
+        A.amr_hydro_rk2_step(T.h, Ud, T.dt, -1, fuse)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        A.amr_cfl_dt(T.h, Ud, 0.8, -1, T.dt)
+        A.amr_hydro_rk2_step(T.h, Ud, T.dt, -1, fuse)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    # kernel durations: the same launches, eagerly enqueued with HIP events around each stage
+    st = [0.0, 0.0]
+    for _ in range(steps):
+        A.amr_cfl_dt(T.h, Ud, 0.8, -1, T.dt)
+        A.amr_hydro_rk2_step(T.h, Ud, T.dt, -1, fuse | A.AMR_STEP_TIMED)
+        a, b = A.amr_table_last_stage_ms(T.h)
+        st[0] += a
+        st[1] += b
+    status = T.status()
+    tiling = A.amr_table_get_tiling(T.h)
+    T.close()
+    if status != A.AMR_OK:
+        raise SystemExit(f"unphysical state during the benchmark: {A.amr_status_string(status)}")
+    return {"ms_per_step": 1e3 * wall / steps, "event_ms_per_step": ev_ms / steps,
+            "stage_ms": [st[0] / steps, st[1] / steps], "tiling": list(tiling)}
+
+
+def cpu_baseline(ps_full, U_full, budget_s=12.0):
+    """The FP64 oracle, serial, on a bounded sample of the same workload."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_0910_5547_amd import workloads as W
+    if ps_full.npatch == 1:
+        B = 64
+        a = ps_full.active(U_full, 0)[:, :B, :B, :B]
+        ps = W.make_patchset(3, [[B, B, B]], 2, [W.BC_PERIODIC] * 6, gamma=ps_full.gamma, dx0=ps_full.dx0)
+        U = W.new_arena(ps)
+        ps.active(U, 0)[...] = a
+        what = f"{B}^3 periodic sub-box of the workload's field"
+    else:
+        k = 64
+        sel = list(range(k))
+        n = ps_full.n[sel]
+        ps = W.make_patchset(3, n, ps_full.ng[sel], [W.BC_OUTFLOW] * 6, gamma=ps_full.gamma, dx0=ps_full.dx0)
+        U = W.new_arena(ps)
+        for i, p in enumerate(sel):
+            ps.active(U, i)[...] = ps_full.active(U_full, p)
+        what = f"first {k} of the workload's patches"
+    o = O.Oracle(ps)
+    cells = ps.active_cells()
+    steps, t = 0, 0.0
+    while t < budget_s and steps < 1000:
+        dt = o.cfl_dt(U, 0.8)
+        t0 = time.perf_counter()
+        o.cfl_dt(U, 0.8)
+        o.rk2_step(U, dt)
+        t += time.perf_counter() - t0
+        steps += 1
+    return {"value": cells * steps / t, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{what}: {cells} cells x {steps} RK2 steps (+ CFL) in {t:.1f} s, serial FP64"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="box256")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the library's autotuner per form first (default: the library's default tiling)")
+    ap.add_argument("--forms", default="plain_fp64,batched_fp64,batched_mixed")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding of the patch table is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_0910_5547_amd import amr as A
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    A.lib()
+
+    t0 = time.time()
+    ps, U, desc = make_workload(args.workload)
+    cells = ps.active_cells()
+    log(f"workload {args.workload}: {cells} cells, {ps.npatch} patches, arena {ps.arena * 8 / 1e9:.2f} GB "
+        f"(built in {time.time() - t0:.1f} s)")
+    forms = {"plain_fp64": (A.AMR_PREC_FP64, A.AMR_EXEC_PLAIN), "batched_fp64": (A.AMR_PREC_FP64, A.AMR_EXEC_BATCHED),
+             "batched_mixed": (A.AMR_PREC_MIXED, A.AMR_EXEC_BATCHED)}
+    res = {}
+    for name in args.forms.split(","):
+        prec, exe = forms[name]
+        log(f"form {name}")
+        r = time_form(A, torch, ps, U, prec, exe, args.steps, args.warmup, tune=args.tune)
+        r["value"] = cells / (r["ms_per_step"] * 1e-3)
+        r["hbm_frac_step"] = BYTES_PER_CELL_STEP * cells / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBPS
+        kern_ms = sum(r["stage_ms"])
+        r["stage_kernel_GBps"] = BYTES_PER_CELL_STEP * cells / (kern_ms * 1e-3) / 1e9
+        log(f"  {name}: {r['ms_per_step']:.3f} ms/step, {r['value'] / 1e9:.2f} G cell-updates/s, "
+            f"stages {r['stage_ms'][0]:.3f}+{r['stage_ms'][1]:.3f} ms, {r['stage_kernel_GBps']:.0f} GB/s")
+        res[name] = r
+
+    main_form = "batched_mixed" if "batched_mixed" in res else list(res)[-1]
+    m = res[main_form]
+    stage_ms = m["stage_ms"]
+    achieved = BYTES_PER_CELL_STEP * cells / (sum(stage_ms) * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": m["value"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": m["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if main_form == "batched_mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "cells": cells, "patches": ps.npatch, "form": main_form,
+                   "tiling": m["tiling"], "cfl": 0.8, "theta": ps.theta, "flux": "paper (Sec. 4)"},
+        "hbm_frac": m["hbm_frac_step"],
+        "forms": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"], "hbm_frac": v["hbm_frac_step"],
+                      "stage_ms": v["stage_ms"], "tiling": v["tiling"]} for k, v in res.items()},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": f"stage_kernel ({main_form}), 2 launches/step, {BYTES_STAGE[0]}+{BYTES_STAGE[1]} "
+                               f"B/cell, avg {sum(stage_ms) / 2:.4f} ms/launch"},
+    }
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(ps, U)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -86,6 +86,9 @@ enum { AMR_EXEC_PLAIN = 0, AMR_EXEC_BATCHED = 1 };
 #define AMR_STEP_FUSE_DT 0x1u /* stage 2 also reduces the max signal speed of U^{n+1}; the
                                  next amr_cfl_dt on the same U and level then reads it
                                  instead of scanning U again */
+#define AMR_STEP_TIMED 0x2u   /* enqueue this step eagerly (same kernels, same launch
+                                 shapes as the batched graph) with HIP events around each
+                                 stage kernel; read them with amr_table_last_stage_ms */
 
 typedef struct {
   int32_t level;    /* refinement level, 0 = root; cell width dx0[d] / 2^level          */
@@ -183,6 +186,11 @@ amr_status amr_table_tiling_shape(const amr_table* table, int32_t id, int32_t* t
  * return its time per step in *ms_best (nullable).  Synchronises the stream. */
 amr_status amr_autotune(amr_table* table, const double* U, const double* dt_dev, int32_t level, int32_t reps,
                         hipStream_t stream, float* ms_best);
+
+/* Durations of the two stage kernels of the last AMR_STEP_TIMED step (in ms,
+ * from HIP events on the step's stream; summed over launches in the plain
+ * form).  Waits for that step.  AMR_ESTATE if no timed step was run. */
+amr_status amr_table_last_stage_ms(amr_table* table, float ms[2]);
 
 const char* amr_status_string(amr_status status);
 

@@ -24,11 +24,12 @@ AMR_FLUX_PAPER, AMR_FLUX_HLL2 = 0, 1
 AMR_PREC_FP64, AMR_PREC_MIXED = 0, 1
 AMR_EXEC_PLAIN, AMR_EXEC_BATCHED = 0, 1
 AMR_STEP_FUSE_DT = 0x1
+AMR_STEP_TIMED = 0x2
 
 EXPORTED = ("amr_patch_table_create", "amr_patch_table_destroy", "amr_table_arena_elems", "amr_cfl_dt",
             "amr_hydro_rk2_step", "amr_flux_correct", "amr_table_status", "amr_table_num_tilings",
             "amr_table_set_tiling", "amr_table_get_tiling", "amr_table_tiling_shape", "amr_autotune",
-            "amr_status_string")
+            "amr_table_last_stage_ms", "amr_status_string")
 
 
 class amr_patch_desc(C.Structure):
@@ -74,6 +75,7 @@ def lib():
         L.amr_table_get_tiling.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
         L.amr_table_tiling_shape.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32)]
         L.amr_autotune.argtypes = [vp, vp, vp, i32, i32, vp, C.POINTER(C.c_float)]
+        L.amr_table_last_stage_ms.argtypes = [vp, C.POINTER(C.c_float)]
         L.amr_status_string.argtypes = [i32]
         L.amr_status_string.restype = C.c_char_p
         for name in EXPORTED:
@@ -203,6 +205,12 @@ def amr_autotune(h, U, dt_dev, level=-1, reps=3, stream=None):
     _check(lib().amr_autotune(h, _ptr(U), _ptr(dt_dev), int(level), int(reps), _stream(stream), C.byref(ms)),
            "amr_autotune")
     return ms.value
+
+
+def amr_table_last_stage_ms(h):
+    ms = (C.c_float * 2)()
+    _check(lib().amr_table_last_stage_ms(h, ms), "amr_table_last_stage_ms")
+    return float(ms[0]), float(ms[1])
 
 
 # ------------------------------------------------------------------ convenience

@@ -65,6 +65,8 @@ struct amr_table {
   const double* fused_U = nullptr;
   int fused_level = -2;
   int occ[2][NSHAPES][2] = {};  // resident stage workgroups per CU
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // AMR_STEP_TIMED: before/between/after the stages
+  bool timed_valid = false;
 };
 
 #define HIPCHECK(x)                                     \
@@ -178,8 +180,10 @@ amr_status enqueue_ghosts(amr_table* t, double* A, int level, hipStream_t s) {
   return AMR_OK;
 }
 
-// Enqueue one RK2 step (both stages) on stream s.
-amr_status enqueue_step(amr_table* t, double* U, const double* dt, int level, uint32_t flags, hipStream_t s) {
+// Enqueue one RK2 step (both stages) on stream s; with `ev`, record ev[0] before
+// stage 1's launches, ev[1] between the stages and ev[2] after stage 2's.
+amr_status enqueue_step(amr_table* t, double* U, const double* dt, int level, uint32_t flags, hipStream_t s,
+                        hipEvent_t* ev = nullptr) {
   TileSet* ts = nullptr;
   amr_status st = get_tiles(t, level, t->shape, t->zslab, &ts);
   if (st != AMR_OK) return st;
@@ -191,6 +195,7 @@ amr_status enqueue_step(amr_table* t, double* U, const double* dt, int level, ui
     double* V = stage == 1 ? U : t->U1;
     st = enqueue_ghosts(t, V, level, s);
     if (st != AMR_OK) return st;
+    if (ev) HIPCHECK(hipEventRecord(ev[stage - 1], s));
     StageArgs a{};
     a.V = V;
     a.U0 = stage == 2 ? U : nullptr;
@@ -213,6 +218,7 @@ amr_status enqueue_step(amr_table* t, double* U, const double* dt, int level, ui
       }
     }
   }
+  if (ev) HIPCHECK(hipEventRecord(ev[2], s));
   return AMR_OK;
 }
 
@@ -428,6 +434,8 @@ amr_status amr_patch_table_destroy(amr_table* t) {
   if (t->fused_d) (void)hipFree(t->fused_d);
   if (t->ops_d) (void)hipFree(t->ops_d);
   if (t->cap_stream) (void)hipStreamDestroy(t->cap_stream);
+  for (auto& e : t->ev)
+    if (e) (void)hipEventDestroy(e);
   delete t;
   return AMR_OK;
 }
@@ -436,9 +444,17 @@ int64_t amr_table_arena_elems(const amr_table* t) { return t ? t->arena : -1; }
 
 amr_status amr_hydro_rk2_step(amr_table* t, double* U, const double* dt_dev, int32_t level, uint32_t flags,
                               hipStream_t stream) {
-  if (!t || !U || !dt_dev || level < -1 || level > t->max_level || (flags & ~AMR_STEP_FUSE_DT)) return AMR_EINVAL;
+  if (!t || !U || !dt_dev || level < -1 || level > t->max_level || (flags & ~(AMR_STEP_FUSE_DT | AMR_STEP_TIMED)))
+    return AMR_EINVAL;
   const bool fuse = (flags & AMR_STEP_FUSE_DT) != 0;
-  if (t->ph.exec == AMR_EXEC_BATCHED) {
+  if (flags & AMR_STEP_TIMED) {
+    for (auto& e : t->ev)
+      if (!e) HIPCHECK(hipEventCreate(&e));
+    t->timed_valid = false;
+    amr_status st = enqueue_step(t, U, dt_dev, level, flags & AMR_STEP_FUSE_DT, stream, t->ev);
+    if (st != AMR_OK) return st;
+    t->timed_valid = true;
+  } else if (t->ph.exec == AMR_EXEC_BATCHED) {
     GraphCache& g = t->gc;
     if (!(g.exec && g.U == U && g.dt == dt_dev && g.level == level && g.flags == flags && g.shape == t->shape &&
           g.zslab == t->zslab)) {
@@ -541,6 +557,15 @@ amr_status amr_table_status(amr_table* t, hipStream_t stream) {
     HIPCHECK(hipStreamSynchronize(stream));
     return AMR_EUNPHYSICAL;
   }
+  return AMR_OK;
+}
+
+amr_status amr_table_last_stage_ms(amr_table* t, float ms[2]) {
+  if (!t || !ms) return AMR_EINVAL;
+  if (!t->timed_valid) return AMR_ESTATE;
+  HIPCHECK(hipEventSynchronize(t->ev[2]));
+  HIPCHECK(hipEventElapsedTime(&ms[0], t->ev[0], t->ev[1]));
+  HIPCHECK(hipEventElapsedTime(&ms[1], t->ev[1], t->ev[2]));
   return AMR_OK;
 }
 
