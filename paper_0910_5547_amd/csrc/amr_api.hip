@@ -123,13 +123,36 @@ amr_status get_tiles(amr_table* t, int level, int shape, int zslab, TileSet** ou
   }
   ts.n = (int)list.size();
   if (ts.n > 0) {
-    // batched form walks the whole list: order it longest-first (LPT) so the
-    // persistent workgroups finish together; plain form uses the per-patch
-    // ranges, so keep a second, unsorted copy at the end of the same buffer.
-    std::vector<Tile> sorted = list;
-    std::stable_sort(sorted.begin(), sorted.end(), [](const Tile& a, const Tile& b) {
-      return (a.z1 - a.z0) > (b.z1 - b.z0);
-    });
+    // The batched form's persistent workgroup b runs on XCD b % 8 (the dispatcher
+    // deals workgroups round-robin over the 8 XCDs) and walks positions b, b+G, ...
+    // (G, the grid, is a multiple of 8).  Split the list - in patch, z-slab, y, x
+    // order - into 8 contiguous chunks of equal cost and interleave them, so that
+    // every XCD works on one compact region and a tile's halo is its neighbours'
+    // interior in the same L2.  Within a chunk, longer tiles go first (LPT) so the
+    // workgroups finish together; equal-cost tiles keep their spatial order.
+    // The plain form uses the per-patch ranges of the unsorted list, kept as a
+    // second copy at the end of the same buffer.
+    const int NX = 8;
+    auto cost = [](const Tile& a) { return (int64_t)(a.z1 - a.z0) + 2; };
+    int64_t total = 0;
+    for (const Tile& a : list) total += cost(a);
+    std::vector<std::vector<Tile>> chunk(NX);
+    int64_t acc = 0;
+    for (const Tile& a : list) {
+      const int c = (int)std::min<int64_t>(NX - 1, acc * NX / std::max<int64_t>(total, 1));
+      chunk[c].push_back(a);
+      acc += cost(a);
+    }
+    size_t longest = 0;
+    for (auto& c : chunk) {
+      std::stable_sort(c.begin(), c.end(), [&](const Tile& a, const Tile& b) { return cost(a) > cost(b); });
+      longest = std::max(longest, c.size());
+    }
+    std::vector<Tile> sorted;
+    sorted.reserve(list.size());
+    for (size_t m = 0; m < longest; ++m)
+      for (int c = 0; c < NX; ++c)
+        if (m < chunk[c].size()) sorted.push_back(chunk[c][m]);
     std::vector<Tile> both = sorted;
     both.insert(both.end(), list.begin(), list.end());
     if (hipMalloc(&ts.d, sizeof(Tile) * both.size()) != hipSuccess) return AMR_ENOMEM;
@@ -144,6 +167,7 @@ Consts consts_of(const amr_table* t) {
   Consts c{};
   c.gamma = t->ph.gamma;
   c.gm1 = t->ph.gamma - 1.0;
+  c.gg1 = t->ph.gamma * (t->ph.gamma - 1.0);
   c.theta = t->ph.theta;
   c.rho_floor = t->ph.rho_floor;
   c.e_floor = t->ph.e_floor;
@@ -161,7 +185,8 @@ int occupancy_grid(amr_table* t, int stage, int ntiles) {
     const void* k = stage_kernel_ptr(mixed, t->shape, stage);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, NT, 0) != hipSuccess || per_cu < 1) per_cu = 1;
   }
-  return std::max(1, std::min(ntiles, per_cu * t->ncu));
+  const int g = std::max(1, std::min(ntiles, per_cu * t->ncu));
+  return g >= 8 ? g / 8 * 8 : g;  // a multiple of the XCD count (tile list interleave)
 }
 
 // Enqueue the EXTERNAL ghost fill of arena A for the patches of `level`.
@@ -377,6 +402,7 @@ amr_status amr_patch_table_create(const amr_patch_desc* patches, int32_t npatch,
       P.g[d] = d < phys->ndim ? D.ng : 0;
       P.s[d] = P.n[d] + 2 * P.g[d];
       P.dx[d] = ldexp(phys->dx0[d], -D.level);
+      P.rdx[d] = 1.0 / P.dx[d];
       S *= P.s[d];
     }
     P.S = S;
@@ -523,6 +549,7 @@ amr_status amr_cfl_dt(amr_table* t, const double* U, double cfl, int32_t level, 
       a.ntiles = ts->n;
       a.tx = SHAPE_TX[t->shape];
       a.ty = SHAPE_TY[t->shape];
+      a.fast = t->ph.precision == AMR_PREC_MIXED;
       a.flag = t->flag_d;
       a.smax = t->smax_d;
       a.c = consts_of(t);

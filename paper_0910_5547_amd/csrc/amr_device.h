@@ -3,11 +3,17 @@
 //
 // RT is the reconstruction type: double for the FP64 path, float for the mixed
 // path (FP32 reconstruction and face flux).  The conserved->primitive
-// conversion, the flux divergence and the RK combine are always double.  In
-// the double instantiation every expression below performs the same IEEE
-// operations in the same order as the plain definition of the scheme (the
-// translation unit is built with -ffp-contract=off), so the FP64 path is
-// reproducible operation by operation.
+// conversion, the flux divergence and the RK combine are always double.
+//
+// FP64 path: every expression performs the same IEEE operations in the same
+// order as the plain definition of the scheme (the translation unit is built
+// with -ffp-contract=off), so it reproduces a serial FP64 evaluation of the
+// scheme bit for bit.
+// Mixed path (Fast<float>): the same formulas evaluated for throughput -
+// fused multiply-adds, one FP64 reciprocal of rho per conversion instead of
+// five divisions, c_s = sqrt(gamma (gamma-1) e) (equal to sqrt(gamma p / rho)
+// for the ideal gas) with the hardware square root, flux divergence as a
+// multiply by 1/dx.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -32,6 +38,7 @@ struct PatchDev {
   int level;
   int pad;
   double dx[3];  // cell widths at this level
+  double rdx[3]; // 1/dx (mixed path)
 };
 
 // One unit of stage-kernel work: a TX x TY column block of one patch, marched
@@ -49,9 +56,26 @@ struct CopyOp {
 };
 
 struct Consts {
-  double gamma, gm1, theta, rho_floor, e_floor;
+  double gamma, gm1, gg1, theta, rho_floor, e_floor;  // gg1 = gamma (gamma - 1)
   int ndim, flux;
 };
+
+// Reconstruction-type traits: the mixed path is evaluated for speed.
+template <typename RT>
+struct Fast {
+  static constexpr bool value = false;
+};
+template <>
+struct Fast<float> {
+  static constexpr bool value = true;
+};
+
+// a*b + c: two roundings in source order on the FP64 path, one fused op on the mixed path.
+template <typename RT>
+__device__ __forceinline__ RT madd(RT a, RT b, RT c) {
+  if constexpr (Fast<RT>::value) return fmaf(a, b, c);
+  else return a * b + c;
+}
 
 // ------------------------------------------------------------------ indexing
 __device__ __forceinline__ int64_t cell_elem(const PatchDev& P, int i, int j, int k) {
@@ -100,9 +124,21 @@ __device__ __forceinline__ void load_cons(const double* __restrict__ A, const Pa
 template <typename RT>
 __device__ __forceinline__ bool cons2prim(const double u[NVAR], const Consts& c, RT q[NVAR]) {
   const double rho = u[0];
-  const double vx = u[1] / rho, vy = u[2] / rho, vz = u[3] / rho;
-  const double kin = 0.5 * ((u[1] * u[1] + u[2] * u[2]) + u[3] * u[3]) / rho;
-  double e = (u[4] - kin) / rho;
+  double vx, vy, vz, e;
+  if constexpr (Fast<RT>::value) {
+    const double ri = 1.0 / rho;
+    vx = u[1] * ri;
+    vy = u[2] * ri;
+    vz = u[3] * ri;
+    const double kin = 0.5 * fma(u[1], vx, fma(u[2], vy, u[3] * vz));
+    e = (u[4] - kin) * ri;
+  } else {
+    vx = u[1] / rho;
+    vy = u[2] / rho;
+    vz = u[3] / rho;
+    const double kin = 0.5 * ((u[1] * u[1] + u[2] * u[2]) + u[3] * u[3]) / rho;
+    e = (u[4] - kin) / rho;
+  }
   bool bad = !(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]) && isfinite(u[3]) && isfinite(u[4]));
   double r = rho;
   if (!(r > 0) && !(c.rho_floor > 0)) bad = true;
@@ -118,27 +154,48 @@ __device__ __forceinline__ bool cons2prim(const double u[NVAR], const Consts& c,
 }
 
 // Largest signal speed of one cell, sum_d (|v_d| + c_s)/dx_d (the CFL rule).
-__device__ __forceinline__ double cell_speed(const double u[NVAR], const Consts& c, const double dx[3], int& bad) {
-  double q[NVAR];
-  bad |= cons2prim<double>(u, c, q) ? 1 : 0;
-  const double p = c.gm1 * q[0] * q[1];
-  const double cs = sqrt(c.gamma * p / q[0]);
-  double s = 0.0;
-  s = s + (fabs(q[2]) + cs) / dx[0];
-  if (c.ndim > 1) s = s + (fabs(q[3]) + cs) / dx[1];
-  if (c.ndim > 2) s = s + (fabs(q[4]) + cs) / dx[2];
-  return s;
+// FAST selects the mixed path's evaluation (used for tables of that precision,
+// both by the CFL kernel and by the fused reduction in stage 2).
+template <bool FAST>
+__device__ __forceinline__ double cell_speed(const double u[NVAR], const Consts& c, const PatchDev& P, int& bad) {
+  if constexpr (FAST) {
+    float q[NVAR];
+    bad |= cons2prim<float>(u, c, q) ? 1 : 0;
+    const double cs = (double)__builtin_amdgcn_sqrtf((float)c.gg1 * q[1]);
+    double s = (fabs((double)q[2]) + cs) * P.rdx[0];
+    if (c.ndim > 1) s = fma(fabs((double)q[3]) + cs, P.rdx[1], s);
+    if (c.ndim > 2) s = fma(fabs((double)q[4]) + cs, P.rdx[2], s);
+    return s;
+  } else {
+    double q[NVAR];
+    bad |= cons2prim<double>(u, c, q) ? 1 : 0;
+    const double p = c.gm1 * q[0] * q[1];
+    const double cs = sqrt(c.gamma * p / q[0]);
+    double s = 0.0;
+    s = s + (fabs(q[2]) + cs) / P.dx[0];
+    if (c.ndim > 1) s = s + (fabs(q[3]) + cs) / P.dx[1];
+    if (c.ndim > 2) s = s + (fabs(q[4]) + cs) / P.dx[2];
+    return s;
+  }
 }
 
 // Three-argument minmod of Sec. 4:
 //   0.25 (sgn a + sgn b) |sgn a + sgn c| min(|a|,|b|,|c|)
-// = sgn(a) min(|a|,|b|,|c|) when a, b, c share a strict sign, else 0.
-template <typename RT>
-__device__ __forceinline__ RT minmod3(RT a, RT b, RT c) {
-  const RT m = fmin(fabs(a), fmin(fabs(b), fabs(c)));
-  const bool pos = (a > RT(0)) & (b > RT(0)) & (c > RT(0));
-  const bool neg = (a < RT(0)) & (b < RT(0)) & (c < RT(0));
-  return (pos | neg) ? copysign(m, a) : RT(0);
+// = sgn(a) max(0, min(|a|, sgn(a) b, sgn(a) c)): equal to the printed form for
+// every input (up to the sign of a zero result), evaluated with sign-bit
+// arithmetic, one min3 and one max.
+__device__ __forceinline__ float minmod3(float a, float b, float c) {
+  const unsigned sa = __float_as_uint(a) & 0x80000000u;
+  const float bb = __uint_as_float(__float_as_uint(b) ^ sa), cc = __uint_as_float(__float_as_uint(c) ^ sa);
+  const float m = fmaxf(fminf(fabsf(a), fminf(bb, cc)), 0.0f);
+  return __uint_as_float(__float_as_uint(m) | sa);
+}
+__device__ __forceinline__ double minmod3(double a, double b, double c) {
+  const unsigned long long sa = (unsigned long long)__double_as_longlong(a) & 0x8000000000000000ull;
+  const double bb = __longlong_as_double((long long)((unsigned long long)__double_as_longlong(b) ^ sa));
+  const double cc = __longlong_as_double((long long)((unsigned long long)__double_as_longlong(c) ^ sa));
+  const double m = fmax(fmin(fabs(a), fmin(bb, cc)), 0.0);
+  return __longlong_as_double((long long)((unsigned long long)__double_as_longlong(m) | sa));
 }
 
 // PLM limited slope of the middle of three cells (Sec. 4 with theta):
@@ -146,12 +203,12 @@ __device__ __forceinline__ RT minmod3(RT a, RT b, RT c) {
 // face states are q_{i-1} + sigma_{i-1}/2 (left) and q_i - sigma_i/2 (right).
 template <typename RT>
 __device__ __forceinline__ RT plm_slope(RT qm, RT q0, RT qp, RT theta) {
-  return minmod3<RT>(theta * (q0 - qm), theta * (qp - q0), (qp - qm) / RT(2));
+  return minmod3(theta * (q0 - qm), theta * (qp - q0), (qp - qm) * RT(0.5));
 }
 
 template <typename RT>
 struct FaceConsts {
-  RT gamma, gm1;
+  RT gamma, gm1, gg1;
 };
 
 // Conserved state U(q), pressure and sound speed of one face state.
@@ -159,12 +216,17 @@ template <typename RT>
 __device__ __forceinline__ void face_state(const RT q[NVAR], const FaceConsts<RT>& k, RT U[NVAR], RT& p, RT& c) {
   const RT rho = q[0], e = q[1], vx = q[2], vy = q[3], vz = q[4];
   p = k.gm1 * rho * e;
-  c = sqrt(k.gamma * p / rho);
   U[0] = rho;
   U[1] = rho * vx;
   U[2] = rho * vy;
   U[3] = rho * vz;
-  U[4] = rho * (e + RT(0.5) * ((vx * vx + vy * vy) + vz * vz));
+  if constexpr (Fast<RT>::value) {
+    c = __builtin_amdgcn_sqrtf(k.gg1 * e);  // gamma p / rho = gamma (gamma-1) e
+    U[4] = rho * fmaf(0.5f, fmaf(vx, vx, fmaf(vy, vy, vz * vz)), e);
+  } else {
+    c = sqrt(k.gamma * p / rho);
+    U[4] = rho * (e + RT(0.5) * ((vx * vx + vy * vy) + vz * vz));
+  }
 }
 
 // Riemann flux in direction D at a face with primitive states qL, qR (Sec. 4
@@ -192,30 +254,19 @@ __device__ __forceinline__ void riemann_flux(const RT qL[NVAR], const RT qR[NVAR
   const RT am = fmax(RT(0), fmax(-(vL - cL), -(vR - cR)));
   if (kind == FLUX_HLL2) {
     const RT apm = ap * am, den = ap + am;
+    if constexpr (Fast<RT>::value) {
+      const RT rden = 1.0f / den;
 #pragma unroll
-    for (int v = 0; v < NVAR; ++v) F[v] = ((ap * FL[v] + am * FR[v]) - apm * (UR[v] - UL[v])) / den;
+      for (int v = 0; v < NVAR; ++v) F[v] = fmaf(-apm, UR[v] - UL[v], fmaf(ap, FL[v], am * FR[v])) * rden;
+    } else {
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) F[v] = ((ap * FL[v] + am * FR[v]) - apm * (UR[v] - UL[v])) / den;
+    }
   } else {
     const RT lam = fmax(ap, am);
 #pragma unroll
-    for (int v = 0; v < NVAR; ++v) F[v] = RT(0.5) * ((FL[v] + FR[v]) - lam * (UR[v] - UL[v]));
+    for (int v = 0; v < NVAR; ++v) F[v] = RT(0.5) * madd(-lam, UR[v] - UL[v], FL[v] + FR[v]);
   }
-}
-
-// Flux at the face between the 2nd and 3rd of four consecutive cells q0..q3
-// along D: reconstruct both face states, then the Riemann flux.
-template <typename RT, int D>
-__device__ __forceinline__ void face_flux4(const RT q0[NVAR], const RT q1[NVAR], const RT q2[NVAR],
-                                           const RT q3[NVAR], RT theta, const FaceConsts<RT>& k, int kind,
-                                           RT F[NVAR]) {
-  RT qL[NVAR], qR[NVAR];
-#pragma unroll
-  for (int v = 0; v < NVAR; ++v) {
-    const RT s1 = plm_slope<RT>(q0[v], q1[v], q2[v], theta);
-    const RT s2 = plm_slope<RT>(q1[v], q2[v], q3[v], theta);
-    qL[v] = q1[v] + RT(0.5) * s1;
-    qR[v] = q2[v] - RT(0.5) * s2;
-  }
-  riemann_flux<RT, D>(qL, qR, k, kind, F);
 }
 
 }  // namespace amr

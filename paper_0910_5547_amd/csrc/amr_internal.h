@@ -25,7 +25,7 @@ struct CflArgs {
   const double* U;
   const PatchDev* patches;
   const Tile* tiles;
-  int ntiles, tx, ty, pad;
+  int ntiles, tx, ty, fast;         // fast: the mixed path's evaluation of the CFL rule
   int* flag;
   unsigned long long* smax;      // per-level maxima
   Consts c;

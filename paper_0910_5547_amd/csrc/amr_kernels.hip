@@ -4,15 +4,21 @@
 // Stage kernel.  One workgroup of 256 lanes owns a TX x TY block of cell
 // columns of one patch and marches it through the planes z0..z1-1 of its tile:
 //   * the z direction lives in registers: each lane keeps, for its own column,
-//     the conserved state and primitives of planes z and z+1, the limited
-//     z-slope of plane z and the z-face flux F_{z-1/2}, and loads plane z+2
-//     per step (so every cell of the column is read from HBM once per stage);
+//     the primitives of planes z and z+1, the limited z-slope of plane z and the
+//     z-face flux F_{z-1/2}, and loads plane z+2 per step (so every cell of the
+//     column is read from HBM once per stage; the re-read of the cell for the
+//     update two planes later is served by L2);
 //   * the x-y plane lives in LDS: the primitives of plane z for the block plus
-//     a 2-cell face halo (no corners: the MOL stencil is a cross, Sec. 4);
-//     every x- and y-face of the block is computed ONCE by one lane and stored
-//     in LDS, so the two cells sharing a face use the same bits (the flux
-//     difference telescopes: conservation holds to round-off in both
-//     precisions);
+//     a 2-cell face halo (no corners: the MOL stencil is a cross, Sec. 4),
+//     double-buffered across planes.  Per plane: (1) every cell's limited
+//     slope in x and y is computed once and turned into the two face states it
+//     contributes (q - sigma/2 on its low face, q + sigma/2 on its high face);
+//     (2) every x- and y-face flux of the block is computed once, by one lane,
+//     from its two face states, and written over them; (3) each cell reads its
+//     two x and two y fluxes.  The two cells sharing a face use the same bits,
+//     so the flux difference telescopes and totals are conserved to round-off
+//     in both precisions.  The z-face flux of each column is computed between
+//     (2) and (3), overlapping with the other waves' face work;
 //   * L(U) is accumulated in FP64 in the order x, y, z (MOL equation), and the
 //     TVD-RK2 stage combine is applied in FP64 before one store per variable.
 // Stage 2 writes U^{n+1} over U^n in place: U^n is only read at the cell being
@@ -27,19 +33,24 @@
 
 namespace amr {
 
+// Occupancy target: three 256-lane workgroups per CU for the FP32-reconstruction
+// instantiations (<= 168 VGPRs), two for FP64 (LDS-bound at two per CU anyway).
 template <typename RT, int TX, int TY, int STAGE>
-__global__ __launch_bounds__(NT) void stage_kernel(StageArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Fast<RT>::value ? 3 : 2)))
+void stage_kernel(StageArgs a) {
   static_assert(TX * TY == NT, "one lane per column of the tile");
-  constexpr bool HASY = TY > 1;               // 1D tiles carry no y rows
-  constexpr int PR = HASY ? TY + 4 : 1;       // LDS rows of the primitive plane
-  constexpr int RO = HASY ? 2 : 0;            // row offset of tile row 0
-  constexpr int FYR = HASY ? TY + 1 : 1;
-  __shared__ RT sP[NVAR][PR][TX + 4];
-  __shared__ RT sFx[NVAR][TY][TX + 1];
-  __shared__ RT sFy[NVAR][FYR][TX];
+  constexpr bool FAST = Fast<RT>::value;
+  constexpr bool HASY = TY > 1;          // 1D tiles carry no y rows
+  constexpr int PR = HASY ? TY + 4 : 1;  // LDS rows of the primitive plane
+  constexpr int RO = HASY ? 2 : 0;       // row offset of tile row 0
+  constexpr int YR = HASY ? TY + 1 : 1;  // y-face rows
+  constexpr int HMAX = HASY ? (4 * (TX + TY) + NT - 1) / NT : 1;  // halo cells per lane
+  __shared__ RT sP[2][NVAR][PR][TX + 4];                    // primitives of the plane (+ face halo)
+  __shared__ RT sXL[NVAR][TY][TX + 1], sXR[NVAR][TY][TX + 1];  // x-face states; sXL then holds F^x
+  __shared__ RT sYL[NVAR][YR][TX], sYR[NVAR][YR][TX];          // y-face states; sYL then holds F^y
 
   const Consts C = a.c;
-  const FaceConsts<RT> K{(RT)C.gamma, (RT)C.gm1};
+  const FaceConsts<RT> K{(RT)C.gamma, (RT)C.gm1, (RT)C.gg1};
   const RT theta = (RT)C.theta;
   const int kind = C.flux;
   const int tid = threadIdx.x;
@@ -47,6 +58,7 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageArgs a) {
   const double dt = *a.dt;
   int bad = 0;
   double smax = 0.0;
+  int buf = 0;
 
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const Tile T = a.tiles[t];
@@ -57,135 +69,217 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageArgs a) {
     const int i = T.x0 + cx, j = T.y0 + cy;
     const bool hasz = C.ndim == 3;
     const bool hasy = HASY && C.ndim >= 2;
+    // element of this lane's column in plane 0 (the column is inside the patch) and
+    // the stride between planes; plane k of the column is at col0 + kk * pstride,
+    // kk being k after the z boundary map (uniform across the workgroup)
+    const int64_t pstride = (int64_t)P.s[0] * P.s[1];
+    const int64_t col0 = P.off + (int64_t)P.g[2] * pstride + (int64_t)(j + P.g[1]) * P.s[0] + (i + P.g[0]);
+    auto load_col = [&](int kz, double u[NVAR]) {
+      bool fz = false;
+      const int kk = map_index(kz, P.n[2], P.bc[4], P.bc[5], fz);
+      const int64_t e = col0 + (int64_t)kk * pstride;
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) u[v] = a.V[e + v * P.S];
+      if (fz) u[3] = -u[3];
+    };
 
-    // z-direction register queue (3D only)
-    double Vz[NVAR], Vz1[NVAR];
+    // z-direction register queue (3D only): primitives of planes k and k+1, the
+    // z-slope of plane k and the flux F_{k-1/2}
     RT qz[NVAR], qz1[NVAR], sgz[NVAR], Fzm[NVAR];
     if (hasz && act) {
       double u[NVAR];
       RT qa[NVAR], qb[NVAR];
-      load_cons(a.V, P, i, j, T.z0 - 2, u);
+      load_col(T.z0 - 2, u);
       bad |= cons2prim<RT>(u, C, qa);
-      load_cons(a.V, P, i, j, T.z0 - 1, u);
+      load_col(T.z0 - 1, u);
       bad |= cons2prim<RT>(u, C, qb);
-      load_cons(a.V, P, i, j, T.z0, Vz);
-      bad |= cons2prim<RT>(Vz, C, qz);
-      load_cons(a.V, P, i, j, T.z0 + 1, Vz1);
-      bad |= cons2prim<RT>(Vz1, C, qz1);
+      load_col(T.z0, u);
+      bad |= cons2prim<RT>(u, C, qz);
+      load_col(T.z0 + 1, u);
+      bad |= cons2prim<RT>(u, C, qz1);
       RT qL[NVAR], qR[NVAR];
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) {
         const RT sa = plm_slope<RT>(qa[v], qb[v], qz[v], theta);
         sgz[v] = plm_slope<RT>(qb[v], qz[v], qz1[v], theta);
-        qL[v] = qb[v] + RT(0.5) * sa;
-        qR[v] = qz[v] - RT(0.5) * sgz[v];
+        qL[v] = madd(RT(0.5), sa, qb[v]);
+        qR[v] = madd(RT(-0.5), sgz[v], qz[v]);
       }
       riemann_flux<RT, 2>(qL, qR, K, kind, Fzm);
     }
 
-    for (int k = T.z0; k < T.z1; ++k) {
-      // issue this step's HBM reads early: plane k+2 of the column, U^n of the cell
-      double Vn2[NVAR], U0c[NVAR];
-      if (hasz && act) load_cons(a.V, P, i, j, k + 2, Vn2);
-      if (STAGE == 2 && act) {
-        const int64_t e = cell_elem(P, i, j, k);
+    // Face halo of every plane: x halo = cols -2,-1,nxT,nxT+1 of every row, y halo =
+    // rows -2,-1,nyT,nyT+1 of every column.  Lane tid owns halo cells tid + s*NT; their
+    // conserved states are loaded one plane ahead so the loads' latency overlaps a
+    // whole plane of work.
+    const int nhx = 4 * nyT, nhy = hasy ? 4 * nxT : 0;
+    int hrow[HMAX], hcol[HMAX], hflip[HMAX];
+    int64_t hbase[HMAX];  // element of the halo cell's source in plane 0 (boundary maps applied)
+    double Hn[HMAX][NVAR];
+    auto load_halo = [&](int s, int kz, double u[NVAR]) {
+      const int64_t e = hbase[s] + (int64_t)kz * pstride;
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) U0c[v] = a.U0[e + v * P.S];
+      for (int v = 0; v < NVAR; ++v) u[v] = a.V[e + v * P.S];
+      if (hflip[s] == 1) u[1] = -u[1];
+      if (hflip[s] == 2) u[2] = -u[2];
+    };
+#pragma unroll
+    for (int s = 0; s < HMAX; ++s) {
+      const int h = tid + s * NT;
+      if (h < nhx) {
+        hrow[s] = h >> 2;
+        const int w = h & 3;
+        hcol[s] = w < 2 ? w - 2 : nxT + (w - 2);
+      } else {
+        const int h2 = h - nhx;
+        hcol[s] = h2 >> 2;
+        const int w = h2 & 3;
+        hrow[s] = w < 2 ? w - 2 : nyT + (w - 2);
       }
-      double Vc[NVAR];
-      RT qc[NVAR];
+      bool fx = false, fy = false;
+      const int ii = map_index(T.x0 + hcol[s], P.n[0], P.bc[0], P.bc[1], fx);
+      const int jj = map_index(T.y0 + hrow[s], P.n[1], P.bc[2], P.bc[3], fy);
+      hflip[s] = fx ? 1 : (fy ? 2 : 0);
+      hbase[s] = P.off + (int64_t)P.g[2] * pstride + (int64_t)(jj + P.g[1]) * P.s[0] + (ii + P.g[0]);
+      if (h < nhx + nhy) load_halo(s, T.z0, Hn[s]);
+    }
+    // lane -> (row, column) of the flattened slope and face index spaces: exact
+    // float reciprocals (indices < 2^10, divisors <= 2^9) instead of integer division
+    const float r_x1 = 1.0f / (float)(nxT + 1), r_x2 = 1.0f / (float)(nxT + 2), r_x0 = 1.0f / (float)nxT;
+    auto idiv = [](int w, float r) { return (int)(((float)w + 0.5f) * r); };
+
+    for (int k = T.z0; k < T.z1; ++k) {
+      // this step's HBM read first: plane k+2 of the column
+      double Vn2[NVAR];
+      if (hasz && act) load_col(k + 2, Vn2);
+      // halo of plane k (prefetched) into LDS, then prefetch the halo of plane k+1
+#pragma unroll
+      for (int s = 0; s < HMAX; ++s) {
+        if (tid + s * NT < nhx + nhy) {
+          RT q[NVAR];
+          bad |= cons2prim<RT>(Hn[s], C, q);
+#pragma unroll
+          for (int v = 0; v < NVAR; ++v) sP[buf][v][hrow[s] + RO][hcol[s] + 2] = q[v];
+          if (k + 1 < T.z1) load_halo(s, k + 1, Hn[s]);
+        }
+      }
       if (act) {
+        RT qc[NVAR];
         if (hasz) {
 #pragma unroll
-          for (int v = 0; v < NVAR; ++v) { Vc[v] = Vz[v]; qc[v] = qz[v]; }
+          for (int v = 0; v < NVAR; ++v) qc[v] = qz[v];
         } else {
-          load_cons(a.V, P, i, j, k, Vc);
-          bad |= cons2prim<RT>(Vc, C, qc);
+          double u[NVAR];
+          load_col(k, u);
+          bad |= cons2prim<RT>(u, C, qc);
         }
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) sP[v][cy + RO][cx + 2] = qc[v];
+        for (int v = 0; v < NVAR; ++v) sP[buf][v][cy + RO][cx + 2] = qc[v];
       }
-      // face halo of plane k: x halo = cols -2,-1,nxT,nxT+1 of every row;
-      // y halo = rows -2,-1,nyT,nyT+1 of every column.
-      const int nhx = 4 * nyT, nhy = hasy ? 4 * nxT : 0;
-      for (int h = tid; h < nhx + nhy; h += NT) {
-        int col, row;
-        if (h < nhx) {
-          row = h >> 2;
-          const int w = h & 3;
-          col = w < 2 ? w - 2 : nxT + (w - 2);
-        } else {
-          const int h2 = h - nhx;
-          col = h2 >> 2;
-          const int w = h2 & 3;
-          row = w < 2 ? w - 2 : nyT + (w - 2);
-        }
-        double u[NVAR];
-        RT q[NVAR];
-        load_cons(a.V, P, T.x0 + col, T.y0 + row, k, u);
-        bad |= cons2prim<RT>(u, C, q);
-#pragma unroll
-        for (int v = 0; v < NVAR; ++v) sP[v][row + RO][col + 2] = q[v];
-      }
-      __syncthreads();
+      __syncthreads();  // (A) plane primitives ready; previous plane's fluxes consumed
 
-      // every x- and y-face of the block, once: face f lies between tile cells f-1 and f
+      // (1) slopes, once per cell: x for cells -1..nxT of every row, y for rows -1..nyT of every column
+      const int nsx = (nxT + 2) * nyT, nsy = hasy ? nxT * (nyT + 2) : 0;
+      for (int w = tid; w < nsx + nsy; w += NT) {
+        if (w < nsx) {
+          const int row = idiv(w, r_x2), c = w - row * (nxT + 2) - 1;
+#pragma unroll
+          for (int v = 0; v < NVAR; ++v) {
+            const RT qm = sP[buf][v][row + RO][c + 1], q0 = sP[buf][v][row + RO][c + 2],
+                     qp = sP[buf][v][row + RO][c + 3];
+            const RT sg = plm_slope<RT>(qm, q0, qp, theta);
+            if (c >= 0) sXR[v][row][c] = madd(RT(-0.5), sg, q0);       // right state of face c
+            if (c < nxT) sXL[v][row][c + 1] = madd(RT(0.5), sg, q0);   // left state of face c+1
+          }
+        } else {
+          const int w2 = w - nsx;
+          const int r = idiv(w2, r_x0) - 1, col = w2 - (r + 1) * nxT;
+#pragma unroll
+          for (int v = 0; v < NVAR; ++v) {
+            const RT qm = sP[buf][v][r + RO - 1][col + 2], q0 = sP[buf][v][r + RO][col + 2],
+                     qp = sP[buf][v][r + RO + 1][col + 2];
+            const RT sg = plm_slope<RT>(qm, q0, qp, theta);
+            if (r >= 0) sYR[v][r][col] = madd(RT(-0.5), sg, q0);
+            if (r < nyT) sYL[v][r + 1][col] = madd(RT(0.5), sg, q0);
+          }
+        }
+      }
+      __syncthreads();  // (B) face states ready
+
+      // the stage input and (stage 2) U^n of this cell, for the update: read here so
+      // the face pass hides the latency (the stage input was read two planes ago and
+      // is normally still in L2)
+      double Vc[NVAR], U0c[NVAR];
+      const int64_t ecell = col0 + (int64_t)k * pstride;
+      if (act) {
+        const int64_t e = ecell;
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) Vc[v] = a.V[e + v * P.S];
+        if (STAGE == 2) {
+#pragma unroll
+          for (int v = 0; v < NVAR; ++v) U0c[v] = a.U0[e + v * P.S];
+        }
+      }
+
+      // (2) every x- and y-face flux of the block, once: face f lies between tile cells f-1 and f
       const int nfx = (nxT + 1) * nyT, nfy = hasy ? nxT * (nyT + 1) : 0;
       for (int w = tid; w < nfx + nfy; w += NT) {
-        RT q0[NVAR], q1[NVAR], q2[NVAR], q3[NVAR], F[NVAR];
+        RT qL[NVAR], qR[NVAR], F[NVAR];
         if (w < nfx) {
-          const int row = w / (nxT + 1), f = w - row * (nxT + 1);
+          const int row = idiv(w, r_x1), f = w - row * (nxT + 1);
 #pragma unroll
-          for (int v = 0; v < NVAR; ++v) {
-            q0[v] = sP[v][row + RO][f];
-            q1[v] = sP[v][row + RO][f + 1];
-            q2[v] = sP[v][row + RO][f + 2];
-            q3[v] = sP[v][row + RO][f + 3];
-          }
-          face_flux4<RT, 0>(q0, q1, q2, q3, theta, K, kind, F);
+          for (int v = 0; v < NVAR; ++v) { qL[v] = sXL[v][row][f]; qR[v] = sXR[v][row][f]; }
+          riemann_flux<RT, 0>(qL, qR, K, kind, F);
 #pragma unroll
-          for (int v = 0; v < NVAR; ++v) sFx[v][row][f] = F[v];
+          for (int v = 0; v < NVAR; ++v) sXL[v][row][f] = F[v];
         } else {
           const int w2 = w - nfx;
-          const int f = w2 / nxT, col = w2 - f * nxT;
+          const int f = idiv(w2, r_x0), col = w2 - f * nxT;
 #pragma unroll
-          for (int v = 0; v < NVAR; ++v) {
-            q0[v] = sP[v][f][col + 2];
-            q1[v] = sP[v][f + 1][col + 2];
-            q2[v] = sP[v][f + 2][col + 2];
-            q3[v] = sP[v][f + 3][col + 2];
-          }
-          face_flux4<RT, 1>(q0, q1, q2, q3, theta, K, kind, F);
+          for (int v = 0; v < NVAR; ++v) { qL[v] = sYL[v][f][col]; qR[v] = sYR[v][f][col]; }
+          riemann_flux<RT, 1>(qL, qR, K, kind, F);
 #pragma unroll
-          for (int v = 0; v < NVAR; ++v) sFy[v][f][col] = F[v];
+          for (int v = 0; v < NVAR; ++v) sYL[v][f][col] = F[v];
         }
       }
-      __syncthreads();
+      // z-face flux F_{k+1/2} of this column from the register queue
+      RT Fzp[NVAR], qn2[NVAR], sg1[NVAR];
+      if (hasz && act) {
+        RT qL[NVAR], qR[NVAR];
+        bad |= cons2prim<RT>(Vn2, C, qn2);
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) {
+          sg1[v] = plm_slope<RT>(qz[v], qz1[v], qn2[v], theta);
+          qL[v] = madd(RT(0.5), sgz[v], qz[v]);
+          qR[v] = madd(RT(-0.5), sg1[v], qz1[v]);
+        }
+        riemann_flux<RT, 2>(qL, qR, K, kind, Fzp);
+      }
+      __syncthreads();  // (C) fluxes ready
 
+      // (3) L(U) in the order x, y, z, then the TVD-RK2 stage combine
       if (act) {
         double L[NVAR];
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) L[v] = 0.0 - ((double)sFx[v][cy][cx + 1] - (double)sFx[v][cy][cx]) / P.dx[0];
+        for (int v = 0; v < NVAR; ++v) {
+          const double d = (double)sXL[v][cy][cx + 1] - (double)sXL[v][cy][cx];
+          if constexpr (FAST) L[v] = -d * P.rdx[0];
+          else L[v] = 0.0 - d / P.dx[0];
+        }
         if (hasy) {
 #pragma unroll
-          for (int v = 0; v < NVAR; ++v)
-            L[v] = L[v] - ((double)sFy[v][cy + 1][cx] - (double)sFy[v][cy][cx]) / P.dx[1];
+          for (int v = 0; v < NVAR; ++v) {
+            const double d = (double)sYL[v][cy + 1][cx] - (double)sYL[v][cy][cx];
+            if constexpr (FAST) L[v] = fma(-d, P.rdx[1], L[v]);
+            else L[v] = L[v] - d / P.dx[1];
+          }
         }
         if (hasz) {
-          RT qn2[NVAR], sg1[NVAR], qL[NVAR], qR[NVAR], Fzp[NVAR];
-          bad |= cons2prim<RT>(Vn2, C, qn2);
 #pragma unroll
           for (int v = 0; v < NVAR; ++v) {
-            sg1[v] = plm_slope<RT>(qz[v], qz1[v], qn2[v], theta);
-            qL[v] = qz[v] + RT(0.5) * sgz[v];
-            qR[v] = qz1[v] - RT(0.5) * sg1[v];
-          }
-          riemann_flux<RT, 2>(qL, qR, K, kind, Fzp);
-#pragma unroll
-          for (int v = 0; v < NVAR; ++v) {
-            L[v] = L[v] - ((double)Fzp[v] - (double)Fzm[v]) / P.dx[2];
-            Vz[v] = Vz1[v];
-            Vz1[v] = Vn2[v];
+            const double d = (double)Fzp[v] - (double)Fzm[v];
+            if constexpr (FAST) L[v] = fma(-d, P.rdx[2], L[v]);
+            else L[v] = L[v] - d / P.dx[2];
             qz[v] = qz1[v];
             qz1[v] = qn2[v];
             sgz[v] = sg1[v];
@@ -193,17 +287,19 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageArgs a) {
           }
         }
         // TVD-RK2 (Sec. 4): stage 1 U1 = U + dt L(U); stage 2 U^{n+1} = U^n/2 + (U1 + dt L(U1))/2
-        const int64_t e = cell_elem(P, i, j, k);
+        const int64_t e = ecell;
         double un[NVAR];
 #pragma unroll
         for (int v = 0; v < NVAR; ++v) {
-          const double u1 = Vc[v] + dt * L[v];
+          double u1;
+          if constexpr (FAST) u1 = fma(dt, L[v], Vc[v]);
+          else u1 = Vc[v] + dt * L[v];
           un[v] = (STAGE == 1) ? u1 : 0.5 * U0c[v] + 0.5 * u1;
           a.out[e + v * P.S] = un[v];
         }
-        if (STAGE == 2 && a.smax != nullptr) smax = fmax(smax, cell_speed(un, C, P.dx, bad));
+        if (STAGE == 2 && a.smax != nullptr) smax = fmax(smax, cell_speed<FAST>(un, C, P, bad));
       }
-      __syncthreads();
+      buf ^= 1;
     }
     if (STAGE == 2 && a.smax != nullptr) {  // fused next-dt reduction, per level
       block_max_to(a.smax + P.level, smax);
@@ -217,6 +313,7 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageArgs a) {
 // Max signal speed over the active cells of the tile list (one plane of a tile
 // per workgroup iteration); the block max is merged into smax[level] with a
 // 64-bit atomicMax on the bit pattern (non-negative doubles order as integers).
+template <bool FAST>
 __global__ __launch_bounds__(NT) void cfl_kernel(CflArgs a) {
   const Consts C = a.c;
   int bad = 0;
@@ -234,7 +331,7 @@ __global__ __launch_bounds__(NT) void cfl_kernel(CflArgs a) {
       double u[NVAR];
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) u[v] = a.U[e + v * P.S];
-      smax = fmax(smax, cell_speed(u, C, P.dx, bad));
+      smax = fmax(smax, cell_speed<FAST>(u, C, P, bad));
     }
     block_max_to(a.smax + P.level, smax);
   }
@@ -336,7 +433,8 @@ const void* stage_kernel_ptr(int mixed, int shape, int stage) {
 }
 
 hipError_t launch_cfl(int grid, hipStream_t s, const CflArgs& a) {
-  hipLaunchKernelGGL(cfl_kernel, dim3(grid), dim3(NT), 0, s, a);
+  if (a.fast) hipLaunchKernelGGL(cfl_kernel<true>, dim3(grid), dim3(NT), 0, s, a);
+  else hipLaunchKernelGGL(cfl_kernel<false>, dim3(grid), dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_cfl_finalize(hipStream_t s, const unsigned long long* smax, int lmin, int lmax, int root,
