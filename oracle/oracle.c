@@ -136,8 +136,63 @@ void or_face_flux(const or_phys* ph, int d, const double qL[5], const double qR[
 /* EXTERNAL face of patch p: each ghost cell takes the value of the same cell
  * (in level index space) of the same-level patch that holds it as an active
  * cell (Sec. 3: grids of one level exchange boundary values). */
+/* Coarse data at time fraction alpha between the coarse level's old and new states
+ * (linear in time), for one storage element. */
+static double coarse_at(const double* Cold, const double* Cnew, double alpha, int64_t e) {
+  double a = (1.0 - alpha) * Cold[e];
+  double b = alpha * Cnew[e];
+  return a + b;
+}
+
+/* Two-argument minmod (the classic limiter of the prolongation slopes). */
+static double minmod2(double a, double b) {
+  if (a > 0 && b > 0) return a < b ? a : b;
+  if (a < 0 && b < 0) return a > b ? a : b;
+  return 0.0;
+}
+
+/* Coarse -> fine conservative prolongation of one fine ghost cell at level index L
+ * (Berger & Colella refinement by 2): the coarse cell C = L/2 holding it, a limited
+ * linear profile per dimension with slopes minmod(u(C+1)-u(C), u(C)-u(C-1)) of the
+ * time-interpolated coarse state, evaluated at the fine cell's centre (offset +-1/4
+ * of a coarse cell).  The 2^d children of C average to u(C).  Returns 0 if no coarse
+ * patch holds C. */
+static int prolong_cell(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph, const double* Cold,
+                        const double* Cnew, double alpha, int level, const int L[3], double out[5]) {
+  int Cc[3] = {0, 0, 0};
+  for (int e = 0; e < ph->ndim; ++e) Cc[e] = L[e] >> 1; /* L >= 0 after the periodic wrap */
+  for (int q = 0; q < np; ++q) {
+    const int32_t* mq = meta + (size_t)q * OR_META;
+    if (mq[0] != level - 1) continue;
+    int inside = 1;
+    for (int e = 0; e < ph->ndim; ++e)
+      if (Cc[e] < mq[1 + e] || Cc[e] >= mq[1 + e] + mq[4 + e]) inside = 0;
+    if (!inside) continue;
+    geom Q = get_geom(mq, off[q], ph->ndim);
+    int c0[3] = {0, 0, 0};
+    for (int e = 0; e < ph->ndim; ++e) c0[e] = Cc[e] - mq[1 + e];
+    for (int k = 0; k < 5; ++k) {
+      double u0 = coarse_at(Cold, Cnew, alpha, at(&Q, k, c0));
+      double v = u0;
+      for (int e = 0; e < ph->ndim; ++e) {
+        int cp[3] = {c0[0], c0[1], c0[2]}, cm[3] = {c0[0], c0[1], c0[2]};
+        cp[e] += 1;
+        cm[e] -= 1;
+        double up = coarse_at(Cold, Cnew, alpha, at(&Q, k, cp));
+        double um = coarse_at(Cold, Cnew, alpha, at(&Q, k, cm));
+        double sg = minmod2(up - u0, u0 - um);
+        double sgn = (L[e] & 1) ? 0.25 : -0.25;
+        v = v + sgn * sg;
+      }
+      out[k] = v;
+    }
+    return 1;
+  }
+  return 0;
+}
+
 static void fill_external(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph, double* V, int p,
-                          const geom* G, int d, int side) {
+                          const geom* G, int d, int side, const double* Cold, const double* Cnew, double alpha) {
   const int32_t* m = meta + (size_t)p * OR_META;
   int a = (d + 1) % 3, b = (d + 2) % 3;
   for (int layer = 1; layer <= G->g[d]; ++layer) {
@@ -153,6 +208,7 @@ static void fill_external(int32_t np, const int32_t* meta, const int64_t* off, c
             L[e] = ((L[e] % dom) + dom) % dom;
           }
         }
+        int found = 0;
         for (int q = 0; q < np; ++q) {
           const int32_t* mq = meta + (size_t)q * OR_META;
           if (mq[0] != m[0]) continue;
@@ -164,7 +220,13 @@ static void fill_external(int32_t np, const int32_t* meta, const int64_t* off, c
           int cs[3] = {0, 0, 0};
           for (int e = 0; e < ph->ndim; ++e) cs[e] = L[e] - mq[1 + e];
           for (int k = 0; k < ph->nvar; ++k) V[at(G, k, cg)] = V[at(&Q, k, cs)];
+          found = 1;
           break;
+        }
+        if (!found && m[0] > 0 && Cold && Cnew) {
+          double u[5];
+          if (prolong_cell(np, meta, off, ph, Cold, Cnew, alpha, m[0], L, u))
+            for (int k = 0; k < ph->nvar; ++k) V[at(G, k, cg)] = u[k];
         }
       }
   }
@@ -173,6 +235,11 @@ static void fill_external(int32_t np, const int32_t* meta, const int64_t* off, c
 
 int or_fill_ghosts(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph,
                    double* V, int32_t level) {
+  return or_fill_ghosts_amr(np, meta, off, ph, V, level, NULL, NULL, 0.0);
+}
+
+int or_fill_ghosts_amr(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph, double* V,
+                       int32_t level, const double* Cold, const double* Cnew, double alpha) {
   for (int p = 0; p < np; ++p) {
     const int32_t* m = meta + (size_t)p * OR_META;
     if (!is_level(m, level)) continue;
@@ -182,7 +249,7 @@ int or_fill_ghosts(int32_t np, const int32_t* meta, const int64_t* off, const or
       for (int side = 0; side < 2; ++side) {
         int bc = G.bc[2 * d + side];
         if (bc == OR_BC_EXTERNAL) {
-          fill_external(np, meta, off, ph, V, p, &G, d, side);
+          fill_external(np, meta, off, ph, V, p, &G, d, side, Cold, Cnew, alpha);
           continue;
         }
         for (int layer = 1; layer <= G.g[d]; ++layer) {
@@ -217,6 +284,21 @@ int or_fill_ghosts(int32_t np, const int32_t* meta, const int64_t* off, const or
 
 /* ---------------------------------------------------------------- O2-O6 L(U) */
 int or_patch_L(const int32_t* m, int64_t off, const or_phys* ph, const double* V, double* L) {
+  return or_patch_L_rec(m, off, ph, V, L, NULL);
+}
+
+int64_t or_face_record_size(const int32_t* m, const or_phys* ph) {
+  int64_t tot = 0;
+  for (int d = 0; d < ph->ndim; ++d) {
+    int64_t c = 5 * (int64_t)(m[4 + d] + 1);
+    for (int e = 0; e < 3; ++e)
+      if (e != d) c *= m[4 + e];
+    tot += c;
+  }
+  return tot;
+}
+
+int or_patch_L_rec(const int32_t* m, int64_t off, const or_phys* ph, const double* V, double* L, double* Frec) {
   geom G = get_geom(m, off, ph->ndim);
   int bad = 0;
   int64_t nact = (int64_t)G.n[0] * G.n[1] * G.n[2];
@@ -257,6 +339,18 @@ int or_patch_L(const int32_t* m, int64_t off, const or_phys* ph, const double* V
           }
           or_face_flux(ph, d, qL, qR, F[f]);
         }
+        if (Frec) { /* every face flux of the line: [v][ib][ia][f] within this dimension's block */
+          int64_t base = 0;
+          for (int e = 0; e < d; ++e) {
+            int64_t c = 5 * (int64_t)(G.n[e] + 1);
+            for (int e2 = 0; e2 < 3; ++e2)
+              if (e2 != e) c *= G.n[e2];
+            base += c;
+          }
+          for (int k = 0; k < 5; ++k)
+            for (int f = 0; f <= n; ++f)
+              Frec[base + (((int64_t)k * G.n[b] + ib) * G.n[a] + ia) * (n + 1) + f] = F[f][k];
+        }
         /* O6: L_i -= (F_{i+1/2} - F_{i-1/2}) / dx_d, dimensions in the order x, y, z */
         for (int i = 0; i < n; ++i) {
           int c[3];
@@ -275,6 +369,12 @@ int or_patch_L(const int32_t* m, int64_t off, const or_phys* ph, const double* V
 /* ---------------------------------------------------------------- O7 stages */
 int or_stage(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph,
              const double* V, const double* U0, double* out, double dt, int32_t stage, int32_t level) {
+  return or_stage_rec(np, meta, off, ph, V, U0, out, dt, stage, level, NULL, NULL);
+}
+
+int or_stage_rec(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph, const double* V,
+                 const double* U0, double* out, double dt, int32_t stage, int32_t level, const int64_t* rec_off,
+                 double* Frec) {
   int bad = 0;
   for (int p = 0; p < np; ++p) {
     const int32_t* m = meta + (size_t)p * OR_META;
@@ -282,7 +382,7 @@ int or_stage(int32_t np, const int32_t* meta, const int64_t* off, const or_phys*
     geom G = get_geom(m, off[p], ph->ndim);
     int64_t nact = (int64_t)G.n[0] * G.n[1] * G.n[2];
     double* L = malloc(sizeof(double) * 5 * (size_t)nact);
-    bad |= or_patch_L(m, off[p], ph, V, L);
+    bad |= or_patch_L_rec(m, off[p], ph, V, L, (Frec && rec_off && rec_off[p] >= 0) ? Frec + rec_off[p] : NULL);
     for (int k3 = 0; k3 < G.n[2]; ++k3)
       for (int j = 0; j < G.n[1]; ++j)
         for (int i = 0; i < G.n[0]; ++i) {

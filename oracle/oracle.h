@@ -56,6 +56,21 @@ void or_phys_flux(const or_phys* ph, int d, const double q[5], double F[5]);
  * with no such patch are left untouched. */
 int or_fill_ghosts(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph,
                    double* V, int32_t level);
+/* As or_fill_ghosts, and EXTERNAL ghost cells that no same-level patch holds are
+ * prolonged (conservative minmod-linear, refinement 2) from level-1 data taken at
+ * time fraction alpha between Cold and Cnew (arenas with the coarse ghosts filled). */
+int or_fill_ghosts_amr(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph, double* V,
+                       int32_t level, const double* Cold, const double* Cnew, double alpha);
+/* Size of the face-flux record of one patch: for each active dimension d, 5 x
+ * (n_d + 1) x prod(other n), laid out [v][b][a][face] with (a, b) the other two
+ * dimensions in cyclic order after d. */
+int64_t or_face_record_size(const int32_t* meta, const or_phys* ph);
+/* L(V) as or_patch_L, also writing every face flux to Frec (if not NULL). */
+int or_patch_L_rec(const int32_t* meta, int64_t off, const or_phys* ph, const double* V, double* L, double* Frec);
+/* or_stage that also records each patch's face fluxes at Frec + rec_off[p] (rec_off[p] < 0: none). */
+int or_stage_rec(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph, const double* V,
+                 const double* U0, double* out, double dt, int32_t stage, int32_t level, const int64_t* rec_off,
+                 double* Frec);
 /* L(V) of the MOL equation for one patch, written to L (5 x active cells, x fastest).
  * V must have its ghosts filled.  Returns 1 if an unphysical state was met. */
 int or_patch_L(const int32_t* meta, int64_t off, const or_phys* ph, const double* V, double* L);

@@ -48,6 +48,10 @@ def lib():
         L.or_phys_flux.argtypes = [pp, C.c_int, dp, dp]
         L.or_phys_flux.restype = None
         L.or_fill_ghosts.argtypes = [C.c_int32, ip, lp, pp, dp, C.c_int32]
+        L.or_fill_ghosts_amr.argtypes = [C.c_int32, ip, lp, pp, dp, C.c_int32, dp, dp, C.c_double]
+        L.or_face_record_size.restype = C.c_int64
+        L.or_face_record_size.argtypes = [ip, pp]
+        L.or_stage_rec.argtypes = [C.c_int32, ip, lp, pp, dp, dp, dp, C.c_double, C.c_int32, C.c_int32, lp, dp]
         L.or_patch_L.argtypes = [ip, C.c_int64, pp, dp, dp]
         L.or_stage.argtypes = [C.c_int32, ip, lp, pp, dp, dp, dp, C.c_double, C.c_int32, C.c_int32]
         L.or_rk2_step.argtypes = [C.c_int32, ip, lp, pp, dp, dp, C.c_double, C.c_int32]
@@ -150,3 +154,226 @@ class Oracle:
             t += dt
             steps += 1
         return steps
+
+
+class AmrOracle:
+    """Subcycled two-stage RK step of a block-structured hierarchy (factor-2
+    refinement in space and time), written from Sec. 3-4 of the paper and the
+    Berger & Colella scheme it builds on:
+
+    * level l advances with dt_l = dt0 / 2^l; after a level-l step its children
+      take two steps, then the coarse level is corrected;
+    * EXTERNAL ghosts come from same-level neighbours, else by conservative
+      minmod-linear prolongation from the coarse level interpolated linearly in
+      time between its old and new states (stage times t and t + dt_l);
+    * the fine patches' boundary fluxes are accumulated (dt/2 per stage, Sec. 4
+      RK2 weights) into registers; each uncovered coarse cell next to a fine
+      patch replaces its own interface flux by the fine average:
+      U_c += s (R_c - <R_f>) / dx_c, s = +1 if the interface is its high face;
+    * coarse cells covered by a fine patch become the mean of their children.
+    """
+
+    def __init__(self, ps, periodic=0, domain=(0, 0, 0), flux=FLUX_PAPER, rho_floor=0.0, e_floor=0.0):
+        self.ps = ps
+        self.o = Oracle(ps, flux=flux, rho_floor=rho_floor, e_floor=e_floor, periodic=periodic, domain=domain)
+        self.periodic, self.domain = periodic, domain
+        self.nlev = int(ps.level.max()) + 1
+        L = lib()
+        sizes = [int(L.or_face_record_size(self.o.meta[p:p + 1].ctypes.data_as(C.POINTER(C.c_int32)),
+                                          C.byref(self.o.ph))) for p in range(ps.npatch)]
+        self.rec_off = np.zeros(ps.npatch, np.int64)
+        self.rec_off[1:] = np.cumsum(sizes)[:-1]
+        self.F1 = np.zeros(max(1, sum(sizes)))
+        self.F2 = np.zeros_like(self.F1)
+        self.snap = None
+        self.W = None
+        self.reg = {}
+        self.dt = [0.0] * self.nlev
+
+    # -------------------------------------------------------------- pieces
+    def _args(self):
+        return self.o._args()
+
+    def fill(self, V, level, Cold=None, Cnew=None, alpha=0.0):
+        lib().or_fill_ghosts_amr(*self._args(), _dp(V), level, _dp(Cold) if Cold is not None else None,
+                                 _dp(Cnew) if Cnew is not None else None, alpha)
+
+    def _stage(self, V, U0, out, dt, stage, level, rec):
+        bad = lib().or_stage_rec(*self._args(), _dp(V), _dp(U0) if U0 is not None else None, _dp(out), dt, stage,
+                                 level, self.rec_off.ctypes.data_as(C.POINTER(C.c_int64)), _dp(rec))
+        if bad:
+            raise FloatingPointError(f"oracle met an unphysical state on level {level}")
+
+    def _face_block(self, rec, p, d):
+        """(5, n_b, n_a, n_d + 1) view of patch p's recorded d-face fluxes."""
+        n = [int(x) for x in self.ps.n[p]]
+        base = int(self.rec_off[p])
+        for e in range(d):
+            c = 5 * (n[e] + 1)
+            for e2 in range(3):
+                if e2 != e:
+                    c *= n[e2]
+            base += c
+        a, b = (d + 1) % 3, (d + 2) % 3
+        size = 5 * n[b] * n[a] * (n[d] + 1)
+        return rec[base:base + size].reshape(5, n[b], n[a], n[d] + 1)
+
+    def _patch_at(self, level, C3):
+        ps = self.ps
+        for q in range(ps.npatch):
+            if ps.level[q] != level:
+                continue
+            if all(ps.lo[q, e] <= C3[e] < ps.lo[q, e] + ps.n[q, e] for e in range(ps.ndim)):
+                return q
+        return -1
+
+    def _wrap(self, level, e, x):
+        if (self.periodic >> e) & 1:
+            dom = self.domain[e] << level
+            return x % dom
+        return x
+
+    def _covered(self, level, C3):
+        """True if coarse cell C3 (level) lies under a patch of level + 1."""
+        ps = self.ps
+        for q in range(ps.npatch):
+            if ps.level[q] != level + 1:
+                continue
+            if all(ps.lo[q, e] <= 2 * C3[e] < ps.lo[q, e] + ps.n[q, e] for e in range(ps.ndim)):
+                return True
+        return False
+
+    def correct(self, U, l):
+        """Berger-Colella refluxing of level l against its children."""
+        ps = self.ps
+        dtc = self.dt[l]
+        for p in range(ps.npatch):
+            if ps.level[p] != l + 1:
+                continue
+            for d in range(ps.ndim):
+                a, b = (d + 1) % 3, (d + 2) % 3
+                for side in (0, 1):
+                    if ps.bc[p, 2 * d + side] != 3:
+                        continue
+                    R = self.reg[(p, d, side)]  # (5, n_b, n_a)
+                    Ff = int(ps.lo[p, d]) + (0 if side == 0 else int(ps.n[p, d]))
+                    cf = Ff // 2
+                    Cd = self._wrap(l, d, cf - 1 if side == 0 else cf)
+                    na, nb = int(ps.n[p, a]), int(ps.n[p, b])
+                    ca_lo, cb_lo = int(ps.lo[p, a]) >> 1, int(ps.lo[p, b]) >> 1
+                    ca_n, cb_n = max(1, na // 2) if a < ps.ndim else 1, max(1, nb // 2) if b < ps.ndim else 1
+                    for jb in range(cb_n):
+                        for ja in range(ca_n):
+                            C3 = [0, 0, 0]
+                            C3[d], C3[a], C3[b] = Cd, ca_lo + ja, cb_lo + jb
+                            if self._covered(l, C3):
+                                continue
+                            q = self._patch_at(l, C3)
+                            if q < 0:
+                                continue
+                            # fine average over the 2^(ndim-1) fine faces under this coarse face
+                            ia = [2 * ja, 2 * ja + 1] if a < ps.ndim else [0]
+                            ib = [2 * jb, 2 * jb + 1] if b < ps.ndim else [0]
+                            Rf = np.zeros(5)
+                            for y in ib:
+                                for x in ia:
+                                    Rf = Rf + R[:, y, x]
+                            Rf = Rf / float(len(ia) * len(ib))
+                            qa, qb = C3[a] - int(ps.lo[q, a]), C3[b] - int(ps.lo[q, b])
+                            fl = C3[d] - int(ps.lo[q, d]) + (1 if side == 0 else 0)
+                            F1 = self._face_block(self.F1, q, d)[:, qb, qa, fl]
+                            F2 = self._face_block(self.F2, q, d)[:, qb, qa, fl]
+                            Rc = 0.5 * dtc * F1
+                            Rc = Rc + 0.5 * dtc * F2
+                            sgn = 1.0 if side == 0 else -1.0
+                            dxc = self.ps.dx0[d] / 2 ** l
+                            cell = [C3[e] - int(ps.lo[q, e]) for e in range(3)]
+                            act = ps.active(U, q)
+                            act[:, cell[2], cell[1], cell[0]] += sgn * (Rc - Rf) / dxc
+
+    def restrict(self, U, l):
+        """Covered coarse cells of level l become the mean of their 2^ndim children."""
+        ps = self.ps
+        nd = ps.ndim
+        for p in range(ps.npatch):
+            if ps.level[p] != l + 1:
+                continue
+            fine = ps.active(U, p)
+            lo, n = ps.lo[p], ps.n[p]
+            cn = [int(n[e]) // 2 if e < nd else 1 for e in range(3)]
+            for kz in range(cn[2]):
+                for jy in range(cn[1]):
+                    for ix in range(cn[0]):
+                        C3 = [(int(lo[0]) >> 1) + ix, (int(lo[1]) >> 1) + jy, (int(lo[2]) >> 1) + kz]
+                        q = self._patch_at(l, C3)
+                        acc = np.zeros(5)
+                        for dz in (range(2) if nd > 2 else [0]):
+                            for dy in (range(2) if nd > 1 else [0]):
+                                for dx in range(2):
+                                    acc = acc + fine[:, 2 * kz + dz if nd > 2 else 0, 2 * jy + dy if nd > 1 else 0,
+                                                     2 * ix + dx]
+                        cell = [C3[e] - int(ps.lo[q, e]) for e in range(3)]
+                        ps.active(U, q)[:, cell[2], cell[1], cell[0]] = acc / float(2 ** nd)
+
+    # -------------------------------------------------------------- driver
+    def cfl_dt0(self, U, cfl):
+        """Root step of the subcycled hierarchy: cfl / max_l (smax_l 2^-l)."""
+        S = 0.0
+        for l in range(self.nlev):
+            s, _ = self.o.max_speed(U, l)
+            S = max(S, s / 2 ** l)
+        return cfl / S
+
+    def advance(self, U, dt0):
+        if self.W is None:
+            self.W = np.full_like(U, np.nan)
+            self.snap = np.full_like(U, np.nan)
+        self.dt = [dt0 / 2 ** l for l in range(self.nlev)]
+        self._advance(U, 0, 0)
+
+    def _level_ranges(self, l):
+        ps = self.ps
+        out = []
+        for p in range(ps.npatch):
+            if ps.level[p] == l:
+                s, _ = ps.stored_shape(p)
+                o = int(ps.offset[p])
+                out.append((o, o + 5 * s[0] * s[1] * s[2]))
+        return out
+
+    def _advance(self, U, l, s):
+        ps = self.ps
+        dt = self.dt[l]
+        kids = bool(np.any(ps.level == l + 1))
+        if l > 0:
+            Cold, Cnew, a1, a2 = self.snap, U, 0.5 * s, 0.5 * (s + 1)
+        else:
+            Cold, Cnew, a1, a2 = None, None, 0.0, 0.0
+        self.fill(U, l, Cold, Cnew, a1)
+        if kids:
+            for lo, hi in self._level_ranges(l):
+                self.snap[lo:hi] = U[lo:hi]
+        self._stage(U, None, self.W, dt, 1, l, self.F1)
+        self.fill(self.W, l, Cold, Cnew, a2)
+        self._stage(self.W, U, U, dt, 2, l, self.F2)
+        if l > 0:  # fine registers: dt/2 per stage on every EXTERNAL boundary face
+            for p in range(ps.npatch):
+                if ps.level[p] != l:
+                    continue
+                for d in range(ps.ndim):
+                    for side in (0, 1):
+                        if ps.bc[p, 2 * d + side] != 3:
+                            continue
+                        f = 0 if side == 0 else int(ps.n[p, d])
+                        r = self.reg.setdefault((p, d, side), np.zeros(self._face_block(self.F1, p, d).shape[:3]))
+                        r += 0.5 * dt * self._face_block(self.F1, p, d)[..., f]
+                        r += 0.5 * dt * self._face_block(self.F2, p, d)[..., f]
+        if kids:
+            self.fill(U, l, Cold, Cnew, a2)
+            for key in list(self.reg):
+                if ps.level[key[0]] == l + 1:
+                    self.reg[key][...] = 0.0
+            self._advance(U, l + 1, 0)
+            self._advance(U, l + 1, 1)
+            self.correct(U, l)
+            self.restrict(U, l)

@@ -282,3 +282,101 @@ def uneven_patches(npatch=4000, seed=30, sizes=(8, 16, 24, 32), ng=3, gamma=5.0 
         return ps, None
     U = random_state(ps, seed + 1, amp=0.2, vamp=0.3, shocks=shock_frac)
     return ps, U
+
+
+def two_level_box(Nc=16, fine_lo=(4, 4, 4), fine_n=(8, 8, 8), ng=3, gamma=5.0 / 3.0, theta=1.0, seed=40,
+                  ndim=3, amp=0.2, vamp=0.4, uniform=False, coarse_split=1):
+    """A periodic box of Nc^ndim root cells with one level-1 patch (refinement 2).
+
+    The fine patch covers root cells [fine_lo, fine_lo + fine_n) (even bounds).
+    The state is a smooth periodic field given on the level-1 grid of the whole
+    domain; root cells are the means of their 2^ndim children, so the initial
+    hierarchy is consistent.  Root patches: the box cut into coarse_split^ndim
+    patches with EXTERNAL faces (periodic root domain); the fine patch has
+    EXTERNAL faces everywhere (ghosts from the root level by prolongation).
+    Returns (PatchSet, U, periodic_mask, domain).
+    """
+    Nf = 2 * Nc
+    rng = np.random.default_rng(seed)
+    shape_f = tuple(Nf if d < ndim else 1 for d in (2, 1, 0))
+    xs = [(np.arange(Nf if d < ndim else 1) + 0.5) / Nf for d in range(3)]
+    Z, Y, X = np.meshgrid(xs[2], xs[1], xs[0], indexing="ij")
+    pos = [X, Y, Z]
+
+    def field():
+        tot = np.zeros(shape_f)
+        for _ in range(3):
+            k = rng.integers(-2, 3, size=3)
+            k[ndim:] = 0
+            if not k.any():
+                k[0] = 1
+            ph = rng.uniform(0, 2 * np.pi)
+            tot += np.sin(2 * np.pi * (k[0] * pos[0] + k[1] * pos[1] + k[2] * pos[2]) + ph)
+        return tot / 3.0
+
+    if uniform:
+        rho = np.full(shape_f, 1.3)
+        vel = [np.full(shape_f, 0.3), np.full(shape_f, -0.2 if ndim > 1 else 0.0), np.full(shape_f, 0.1 if ndim > 2 else 0.0)]
+        pr = np.full(shape_f, 0.8)
+    else:
+        rho = 1.0 + amp * field()
+        vel = [vamp * field() if d < ndim else np.zeros(shape_f) for d in range(3)]
+        pr = 1.0 + amp * field()
+    Uf = conserved(rho, vel[0], vel[1], vel[2], pr, gamma)
+    # root field: mean of the 2^ndim children
+    Uc = Uf
+    for ax in range(ndim):
+        axis = 3 - ax
+        sl0 = [slice(None)] * 4
+        sl1 = [slice(None)] * 4
+        sl0[axis] = slice(0, None, 2)
+        sl1[axis] = slice(1, None, 2)
+        Uc = Uc[tuple(sl0)] + Uc[tuple(sl1)]
+    Uc = Uc / float(2 ** ndim)
+    m = coarse_split
+    Pc = Nc // m
+    los, ns, levels, bcs = [], [], [], []
+    rng_idx = [range(m) if d < ndim else range(1) for d in range(3)]
+    for kz in rng_idx[2]:
+        for jy in rng_idx[1]:
+            for ix in rng_idx[0]:
+                los.append([ix * Pc if ndim > 0 else 0, jy * Pc if ndim > 1 else 0, kz * Pc if ndim > 2 else 0])
+                ns.append([Pc if d < ndim else 1 for d in range(3)])
+                levels.append(0)
+    flo = [2 * fine_lo[d] if d < ndim else 0 for d in range(3)]
+    fn = [2 * fine_n[d] if d < ndim else 1 for d in range(3)]
+    los.append(flo)
+    ns.append(fn)
+    levels.append(1)
+    dx0 = tuple(1.0 / Nc if d < ndim else 1.0 for d in range(3))
+    ps = make_patchset(ndim, ns, ng, [BC_EXTERNAL] * 6, level=levels, lo=los, gamma=gamma, theta=theta, dx0=dx0)
+    U = new_arena(ps)
+    for p in range(ps.npatch):
+        lo, n = ps.lo[p], ps.n[p]
+        src = Uc if ps.level[p] == 0 else Uf
+        ps.active(U, p)[...] = src[:, lo[2]:lo[2] + n[2], lo[1]:lo[1] + n[1], lo[0]:lo[0] + n[0]]
+    periodic = (1 << ndim) - 1
+    domain = tuple(Nc if d < ndim else 0 for d in range(3))
+    return ps, U, periodic, domain
+
+
+def composite_totals(ps, U):
+    """Totals of the 5 conserved variables over the composite grid (cells not covered
+    by a finer patch), each cell weighted by its volume."""
+    nd = ps.ndim
+    tot = np.zeros(5)
+    for p in range(ps.npatch):
+        l = int(ps.level[p])
+        vol = np.prod([ps.dx0[d] / 2 ** l for d in range(nd)])
+        a = ps.active(U, p).copy()
+        mask = np.ones(a.shape[1:], bool)
+        for q in range(ps.npatch):
+            if ps.level[q] != l + 1:
+                continue
+            lo = [max(int(ps.lo[q, d]) // 2, int(ps.lo[p, d])) - int(ps.lo[p, d]) if d < nd else 0 for d in range(3)]
+            hi = [min((int(ps.lo[q, d]) + int(ps.n[q, d])) // 2, int(ps.lo[p, d]) + int(ps.n[p, d])) - int(ps.lo[p, d])
+                  if d < nd else 1 for d in range(3)]
+            if all(hi[d] > lo[d] for d in range(3)):
+                mask[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = False
+        tot += vol * np.array([math.fsum(a[k][mask].ravel()) for k in range(5)])
+    return tot

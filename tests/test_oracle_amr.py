@@ -1,0 +1,207 @@
+"""Pins of the oracle's two-level (subcycled, refluxed) step.
+
+Checks against what Berger-Colella refinement fixes: a uniform state stays
+uniform, composite totals are conserved to round-off with refluxing (and are not
+without it), covered coarse cells equal the mean of their children, and the
+composite solution inside the fine patch is closer to an all-fine reference
+than an all-coarse run is (prolongation and time interpolation are consistent).
+"""
+import numpy as np
+import pytest
+
+from paper_0910_5547_amd import workloads as W
+
+
+def _run(oracle_lib, ps, U, per, dom, steps, correct=True):
+    a = oracle_lib.AmrOracle(ps, periodic=per, domain=dom)
+    if not correct:
+        a.correct = lambda U, l: None
+    for _ in range(steps):
+        a.advance(U, a.cfl_dt0(U, 0.8))
+    return a
+
+
+@pytest.mark.parametrize("ndim,split", [(3, 2), (2, 1), (1, 2)])
+def test_uniform_state_stays_uniform(oracle_lib, ndim, split):
+    ps, U, per, dom = W.two_level_box(Nc=16, fine_lo=(4, 4, 4)[:ndim] + (0,) * (3 - ndim),
+                                      fine_n=(8, 8, 8)[:ndim] + (1,) * (3 - ndim), uniform=True, ndim=ndim,
+                                      coarse_split=split)
+    U0 = U.copy()
+    _run(oracle_lib, ps, U, per, dom, 3)
+    for p in range(ps.npatch):
+        a, b = ps.active(U, p), ps.active(U0, p)
+        assert np.max(np.abs(a - b) / np.maximum(np.abs(b), 1)) <= 1e-15
+
+
+@pytest.mark.parametrize("ndim", [3, 2, 1])
+def test_composite_conservation_with_refluxing(oracle_lib, ndim):
+    lo = (4, 6, 4)[:ndim] + (0,) * (3 - ndim)
+    n = (8, 6, 8)[:ndim] + (1,) * (3 - ndim)
+    ps, U, per, dom = W.two_level_box(Nc=16, fine_lo=lo, fine_n=n, ndim=ndim, coarse_split=2, seed=41)
+    t0 = W.composite_totals(ps, U)
+    scale = W.composite_totals(ps, np.abs(U))
+    _run(oracle_lib, ps, U, per, dom, 4)
+    t1 = W.composite_totals(ps, U)
+    assert np.all(np.abs(t1 - t0) <= 1e-13 * scale), (t1 - t0) / scale
+    # negative control: without refluxing the totals drift far above round-off
+    ps, U, per, dom = W.two_level_box(Nc=16, fine_lo=lo, fine_n=n, ndim=ndim, coarse_split=2, seed=41)
+    _run(oracle_lib, ps, U, per, dom, 4, correct=False)
+    t2 = W.composite_totals(ps, U)
+    live = scale > 0
+    assert np.max(np.abs(t2 - t0)[live] / scale[live]) > 1e-8
+
+
+def test_restriction_is_the_mean_of_children(oracle_lib):
+    ps, U, per, dom = W.two_level_box(Nc=16, coarse_split=2, seed=42)
+    _run(oracle_lib, ps, U, per, dom, 2)
+    fine = [p for p in range(ps.npatch) if ps.level[p] == 1][0]
+    f = ps.active(U, fine)
+    mean = (f[:, 0::2, 0::2, 0::2] + f[:, 0::2, 0::2, 1::2] + f[:, 0::2, 1::2, 0::2] + f[:, 0::2, 1::2, 1::2]
+            + f[:, 1::2, 0::2, 0::2] + f[:, 1::2, 0::2, 1::2] + f[:, 1::2, 1::2, 0::2] + f[:, 1::2, 1::2, 1::2]) / 8
+    lo, n = ps.lo[fine] // 2, ps.n[fine] // 2
+    for q in range(ps.npatch):
+        if ps.level[q] != 0:
+            continue
+        a = ps.active(U, q)
+        qlo, qn = ps.lo[q], ps.n[q]
+        l0 = np.maximum(lo, qlo)
+        h0 = np.minimum(lo + n, qlo + qn)
+        if np.any(h0 <= l0):
+            continue
+        got = a[:, l0[2] - qlo[2]:h0[2] - qlo[2], l0[1] - qlo[1]:h0[1] - qlo[1], l0[0] - qlo[0]:h0[0] - qlo[0]]
+        ref = mean[:, l0[2] - lo[2]:h0[2] - lo[2], l0[1] - lo[1]:h0[1] - lo[1], l0[0] - lo[0]:h0[0] - lo[0]]
+        assert np.allclose(got, ref, rtol=1e-15, atol=1e-15)
+
+
+def test_fine_patch_is_closer_to_fine_reference_than_coarse_run(oracle_lib):
+    """1D: a fine patch over the middle of the domain; after t = 0.05 its cells are closer
+    to an all-fine run than the all-coarse run's cells are."""
+    Nc = 64
+    ps, U, per, dom = W.two_level_box(Nc=Nc, fine_lo=(16, 0, 0), fine_n=(32, 1, 1), ndim=1, coarse_split=1,
+                                      seed=43, amp=0.3, vamp=0.5)
+    fine = [p for p in range(ps.npatch) if ps.level[p] == 1][0]
+    # all-fine and all-coarse references from the same level-1 field
+    psf, Uf, _, _ = W.two_level_box(Nc=Nc, fine_lo=(0, 0, 0), fine_n=(Nc, 1, 1), ndim=1, coarse_split=1, seed=43,
+                                    amp=0.3, vamp=0.5)
+    full = [p for p in range(psf.npatch) if psf.level[p] == 1][0]
+    ref_ps = W.make_patchset(1, [[2 * Nc, 1, 1]], 3, [W.BC_PERIODIC] * 6, gamma=ps.gamma, dx0=(0.5 / Nc, 1, 1))
+    ref = W.new_arena(ref_ps)
+    ref_ps.active(ref, 0)[...] = psf.active(Uf, full)
+    crs_ps = W.make_patchset(1, [[Nc, 1, 1]], 3, [W.BC_PERIODIC] * 6, gamma=ps.gamma, dx0=(1.0 / Nc, 1, 1))
+    crs = W.new_arena(crs_ps)
+    crs_ps.active(crs, 0)[...] = ps.active(U, 0)
+    a = oracle_lib.AmrOracle(ps, periodic=per, domain=dom)
+    oref, ocrs = oracle_lib.Oracle(ref_ps), oracle_lib.Oracle(crs_ps)
+    t = 0.0
+    while t < 0.05:
+        dt0 = min(a.cfl_dt0(U, 0.4), ocrs.cfl_dt(crs, 0.4), 2 * oref.cfl_dt(ref, 0.4), 0.05 - t)
+        a.advance(U, dt0)
+        ocrs.rk2_step(crs, dt0)
+        oref.rk2_step(ref, dt0 / 2)
+        oref.rk2_step(ref, dt0 / 2)
+        t += dt0
+    r = ref_ps.active(ref, 0)[0, 0, 0, 32:96]
+    comp = ps.active(U, fine)[0, 0, 0, :]
+    coarse = crs_ps.active(crs, 0)[0, 0, 0, 16:48]
+    coarse_on_fine = np.repeat(coarse, 2)
+    assert np.abs(comp - r).sum() < 0.5 * np.abs(coarse_on_fine - r).sum()
+
+
+def _ghost_cells(ps, U, p):
+    """(5, cells) values and level-index centres of patch p's face ghosts (two layers)."""
+    g = int(ps.ng[p])
+    v = ps.view(U, p)
+    vals, centres = [], []
+    n = ps.n[p]
+    for d in range(ps.ndim):
+        for side in (0, 1):
+            for layer in (1, 2):
+                idx = [slice(g, g + int(n[e])) if e < ps.ndim else slice(0, 1) for e in range(3)]
+                pos = (g - layer) if side == 0 else (g + int(n[d]) - 1 + layer)
+                idx[d] = slice(pos, pos + 1)
+                blk = v[:, idx[2], idx[1], idx[0]]
+                vals.append(blk.reshape(5, -1))
+                grids = np.meshgrid(*[np.arange(s.start, s.stop) - (g if e < ps.ndim else 0) + int(ps.lo[p, e])
+                                      for e, s in zip((2, 1, 0), (idx[2], idx[1], idx[0]))], indexing="ij")
+                centres.append(np.stack([grids[2].ravel(), grids[1].ravel(), grids[0].ravel()]))
+    return np.concatenate(vals, axis=1), np.concatenate(centres, axis=1)
+
+
+def test_prolongation_reproduces_linear_data(oracle_lib):
+    """Minmod-limited linear prolongation is exact for monotone linear coarse data: the fine
+    ghost cells hold the linear function at their centres."""
+    ps, U, per, dom = W.two_level_box(Nc=16, coarse_split=1, seed=44)
+    a = oracle_lib.AmrOracle(ps, periodic=0, domain=(0, 0, 0))
+    coef = np.array([[1.0, 0.02, -0.01, 0.015], [0.1, 0.01, 0.0, 0.0], [0.0, 0.0, 0.01, 0.0], [0.2, 0.0, 0.0, 0.0],
+                     [3.0, 0.03, 0.02, -0.01]])
+    ps.view(U, 0)[...] = np.nan
+    for p in range(ps.npatch):
+        if ps.level[p] != 0:
+            continue
+        g = int(ps.ng[p])
+        sz, sy, sx = ps.view(U, p).shape[1:]
+        z, y, x = np.meshgrid(np.arange(sz) - g + 0.5, np.arange(sy) - g + 0.5, np.arange(sx) - g + 0.5, indexing="ij")
+        for k in range(5):
+            ps.view(U, p)[k] = coef[k, 0] + coef[k, 1] * x + coef[k, 2] * y + coef[k, 3] * z
+    a.fill(U, 1, U, U, 0.0)
+    fine = [p for p in range(ps.npatch) if ps.level[p] == 1][0]
+    vals, cen = _ghost_cells(ps, U, fine)
+    xc = (cen + 0.5) / 2.0  # fine centres in coarse index units
+    for k in range(5):
+        ref = coef[k, 0] + coef[k, 1] * xc[0] + coef[k, 2] * xc[1] + coef[k, 3] * xc[2]
+        assert np.allclose(vals[k], ref, rtol=0, atol=1e-13), k
+
+
+def test_prolongation_time_interpolation(oracle_lib):
+    """Ghosts at time fraction alpha between two uniform coarse states take (1-alpha) old + alpha new."""
+    ps, U, per, dom = W.two_level_box(Nc=16, coarse_split=1, seed=45)
+    a = oracle_lib.AmrOracle(ps, periodic=0, domain=(0, 0, 0))
+    old, new = U.copy(), U.copy()
+    ps.view(old, 0)[...] = np.array([1.0, 0.2, -0.1, 0.3, 2.0]).reshape(5, 1, 1, 1)
+    ps.view(new, 0)[...] = np.array([3.0, 0.6, 0.5, -0.3, 6.0]).reshape(5, 1, 1, 1)
+    fine = [p for p in range(ps.npatch) if ps.level[p] == 1][0]
+    for alpha in (0.0, 0.25, 0.5, 1.0):
+        a.fill(U, 1, old, new, alpha)
+        vals, _ = _ghost_cells(ps, U, fine)
+        expect = (1 - alpha) * np.array([1.0, 0.2, -0.1, 0.3, 2.0]) + alpha * np.array([3.0, 0.6, 0.5, -0.3, 6.0])
+        assert np.allclose(vals, expect[:, None], rtol=0, atol=1e-15), alpha
+
+
+def test_prolongation_of_a_step_creates_no_new_extrema(oracle_lib):
+    """The minmod slope of a cell next to a jump is 0 (one one-sided difference vanishes),
+    so prolonged ghosts of a step function hold the two coarse values exactly."""
+    ps, U, per, dom = W.two_level_box(Nc=16, coarse_split=1, seed=46)
+    a = oracle_lib.AmrOracle(ps, periodic=0, domain=(0, 0, 0))
+    g = int(ps.ng[0])
+    sz, sy, sx = ps.view(U, 0).shape[1:]
+    x = np.arange(sx) - g
+    step = np.where(x < 8, 1.0, 2.0)  # jump at the fine patch's centre plane (coarse x = 8)
+    for k in range(5):
+        ps.view(U, 0)[k] = (1.0 + k) * step.reshape(1, 1, sx)
+    a.fill(U, 1, U, U, 0.0)
+    fine = [p for p in range(ps.npatch) if ps.level[p] == 1][0]
+    vals, _ = _ghost_cells(ps, U, fine)
+    for k in range(5):
+        assert set(np.unique(vals[k])) <= {1.0 + k, 2.0 * (1.0 + k)}, k
+
+
+def test_prolongation_limiter_takes_the_smaller_difference(oracle_lib):
+    """Convex increasing coarse data u_i = (i + 1/2)^2 along x: the two one-sided
+    differences 2i and 2i + 2 share a sign, and minmod takes the smaller, 2i; so a
+    fine child of coarse cell i at offset +-1/4 holds (i + 1/2)^2 +- i/2."""
+    ps, U, per, dom = W.two_level_box(Nc=16, coarse_split=1, seed=47)
+    a = oracle_lib.AmrOracle(ps, periodic=0, domain=(0, 0, 0))
+    g = int(ps.ng[0])
+    sz, sy, sx = ps.view(U, 0).shape[1:]
+    xc = np.arange(sx) - g + 0.5
+    fac = [(1.0 + k) * (-1.0) ** k for k in range(5)]  # increasing and decreasing data
+    for k in range(5):
+        ps.view(U, 0)[k] = fac[k] * (xc ** 2).reshape(1, 1, sx)
+    a.fill(U, 1, U, U, 0.0)
+    fine = [p for p in range(ps.npatch) if ps.level[p] == 1][0]
+    vals, cen = _ghost_cells(ps, U, fine)
+    i = cen[0] // 2
+    off = np.where(cen[0] % 2 == 1, 0.25, -0.25)
+    expect = (i + 0.5) ** 2 + off * 2 * i
+    for k in range(5):
+        assert np.allclose(vals[k], fac[k] * expect, rtol=0, atol=1e-12), k
