@@ -172,12 +172,13 @@ amr_status amr_table_status(amr_table* table, hipStream_t stream);
 /* Tile shape control (batched and plain forms share the kernels).
  * amr_table_num_tilings: number of compiled tile shapes.
  * amr_table_set_tiling: select shape `id` (0 <= id < num) and z-slab length
- *   zslab (>= 1; 0 = the shape's default); invalidates a captured graph.
- * amr_table_get_tiling: current id and zslab.
+ *   zslab (>= 1; 0 = automatic: the slab length that fills whole rounds of the
+ *   persistent launch); invalidates a captured graph.
+ * amr_table_get_tiling: current id and (resolved) zslab.
  * amr_table_tiling_shape: the (TX, TY) cells per tile of shape `id`. */
 int32_t amr_table_num_tilings(const amr_table* table);
 amr_status amr_table_set_tiling(amr_table* table, int32_t id, int32_t zslab);
-amr_status amr_table_get_tiling(const amr_table* table, int32_t* id, int32_t* zslab);
+amr_status amr_table_get_tiling(amr_table* table, int32_t* id, int32_t* zslab);
 amr_status amr_table_tiling_shape(const amr_table* table, int32_t id, int32_t* tx, int32_t* ty);
 
 /* Autotuner: time every (shape, zslab) candidate on the caller's data with

@@ -88,10 +88,46 @@ bool shape_valid(int ndim, int shape) {
   return ndim == 1 ? shape == 0 : shape != 0;
 }
 
-int default_zslab(const amr_table* t) { return t->ph.ndim == 3 ? 64 : 1; }
+int occupancy_grid(amr_table* t, int stage, int ntiles);
+
+// z-slab length that balances the persistent launch: per-tile time is taken as
+// proportional to its planes + 4 (the z prologue reads 4 planes); with T_xy column
+// blocks of the level scope and G resident workgroups, choose the slab count that
+// minimises rounds x (slab + 4).  Levels with enough tiles keep whole patches.
+int auto_zslab(amr_table* t, int level, int shape) {
+  if (t->ph.ndim != 3) return 1;
+  const int TX = SHAPE_TX[shape], TY = SHAPE_TY[shape];
+  int64_t txy = 0;
+  int nz = 1;
+  for (const PatchDev& P : t->pdev) {
+    if (level >= 0 && P.level != level) continue;
+    txy += (int64_t)((P.n[0] + TX - 1) / TX) * ((P.n[1] + TY - 1) / TY);
+    nz = std::max(nz, P.n[2]);
+  }
+  const int keep = t->shape;
+  t->shape = shape;
+  const int64_t G = occupancy_grid(t, 2, 1 << 30);
+  t->shape = keep;
+  if (txy >= 4 * G) return nz;
+  int64_t best = -1;
+  int bz = nz;
+  for (int ns = 1; ns <= std::max(1, nz / 8); ++ns) {
+    const int zs = (nz + ns - 1) / ns;
+    const int64_t rounds = (txy * ((nz + zs - 1) / zs) + G - 1) / G;
+    const int64_t c = rounds * (zs + 4);
+    if (best < 0 || c < best) {
+      best = c;
+      bz = zs;
+    }
+  }
+  return bz;
+}
+
+int default_zslab(const amr_table* t) { return t->ph.ndim == 3 ? 0 : 1; }  // 0 = auto_zslab
 
 // Tile list of the patches of `level` (-1 = all) for a shape and z-slab length.
 amr_status get_tiles(amr_table* t, int level, int shape, int zslab, TileSet** out) {
+  if (zslab == 0) zslab = auto_zslab(t, level, shape);
   auto key = std::make_tuple(level, shape, zslab);
   auto it = t->tiles.find(key);
   if (it != t->tiles.end()) {
@@ -107,7 +143,7 @@ amr_status get_tiles(amr_table* t, int level, int shape, int zslab, TileSet** ou
     const PatchDev& P = t->pdev[p];
     ts.first[p] = (int)list.size();
     if (level >= 0 && P.level != level) continue;
-    const int zs = zslab > 0 ? zslab : P.n[2];
+    const int zs = std::min(zslab, P.n[2]);
     for (int z0 = 0; z0 < P.n[2]; z0 += zs)
       for (int y0 = 0; y0 < P.n[1]; y0 += TY)
         for (int x0 = 0; x0 < P.n[0]; x0 += TX) {
@@ -179,6 +215,7 @@ Consts consts_of(const amr_table* t) {
 // Resident workgroups per CU of the stage kernel in use (queried once per
 // (precision, shape, stage), outside any graph capture).
 int occupancy_grid(amr_table* t, int stage, int ntiles) {
+  if (ntiles < 1) ntiles = 1;
   const int mixed = t->ph.precision == AMR_PREC_MIXED;
   int& per_cu = t->occ[mixed][t->shape][stage - 1];
   if (per_cu <= 0) {
@@ -601,15 +638,15 @@ int32_t amr_table_num_tilings(const amr_table* t) { return t ? NSHAPES : 0; }
 amr_status amr_table_set_tiling(amr_table* t, int32_t id, int32_t zslab) {
   if (!t || !shape_valid(ndim_of(t), id) || zslab < 0) return AMR_EINVAL;
   t->shape = id;
-  t->zslab = zslab == 0 ? default_zslab(t) : zslab;
+  t->zslab = t->ph.ndim == 3 ? zslab : 1;  // 0 = balanced automatic choice
   drop_graph(t);
   return AMR_OK;
 }
 
-amr_status amr_table_get_tiling(const amr_table* t, int32_t* id, int32_t* zslab) {
+amr_status amr_table_get_tiling(amr_table* t, int32_t* id, int32_t* zslab) {
   if (!t || !id || !zslab) return AMR_EINVAL;
   *id = t->shape;
-  *zslab = t->zslab;
+  *zslab = t->zslab == 0 ? auto_zslab(t, -1, t->shape) : t->zslab;
   return AMR_OK;
 }
 
@@ -633,6 +670,7 @@ amr_status amr_autotune(amr_table* t, const double* U, const double* dt_dev, int
     if (level < 0 || P.level == level) maxnz = std::max(maxnz, P.n[2]);
   std::vector<int> zs;
   if (t->ph.ndim == 3) {
+    zs.push_back(0);  // the balanced choice for each shape
     for (int z : {8, 16, 32, 64, 128})
       if (z < maxnz) zs.push_back(z);
     zs.push_back(maxnz);

@@ -269,4 +269,27 @@ __device__ __forceinline__ void riemann_flux(const RT qL[NVAR], const RT qR[NVAR
   }
 }
 
+// Riemann flux of a face whose normal is x (dir = 0) or y (dir = 1), the
+// direction being a per-lane value: y faces are evaluated in the x frame with
+// the x and y velocity components exchanged, then the two momentum fluxes are
+// exchanged back.  The arithmetic is that of riemann_flux<RT, dir>.
+template <typename RT>
+__device__ __forceinline__ void riemann_flux_xy(RT qL[NVAR], RT qR[NVAR], bool ydir, const FaceConsts<RT>& k,
+                                                int kind, RT F[NVAR]) {
+  if (ydir) {
+    RT t = qL[2];
+    qL[2] = qL[3];
+    qL[3] = t;
+    t = qR[2];
+    qR[2] = qR[3];
+    qR[3] = t;
+  }
+  riemann_flux<RT, 0>(qL, qR, k, kind, F);
+  if (ydir) {
+    const RT t = F[1];
+    F[1] = F[2];
+    F[2] = t;
+  }
+}
+
 }  // namespace amr

@@ -45,9 +45,10 @@ void stage_kernel(StageArgs a) {
   constexpr int RO = HASY ? 2 : 0;       // row offset of tile row 0
   constexpr int YR = HASY ? TY + 1 : 1;  // y-face rows
   constexpr int HMAX = HASY ? (4 * (TX + TY) + NT - 1) / NT : 1;  // halo cells per lane
-  __shared__ RT sP[2][NVAR][PR][TX + 4];                    // primitives of the plane (+ face halo)
-  __shared__ RT sXL[NVAR][TY][TX + 1], sXR[NVAR][TY][TX + 1];  // x-face states; sXL then holds F^x
-  __shared__ RT sYL[NVAR][YR][TX], sYR[NVAR][YR][TX];          // y-face states; sYL then holds F^y
+  // face slots: x faces first, slot row*(nxT+1) + f, then y faces, slot nfx + f*nxT + col
+  constexpr int NSLOT = TY * (TX + 1) + (HASY ? YR * TX : 0);
+  __shared__ RT sP[2][NVAR][PR][TX + 4];        // primitives of the plane (+ face halo)
+  __shared__ RT sFL[NVAR][NSLOT], sFR[NVAR][NSLOT];  // left/right face states; sFL then holds the flux
 
   const Consts C = a.c;
   const FaceConsts<RT> K{(RT)C.gamma, (RT)C.gm1, (RT)C.gg1};
@@ -178,30 +179,35 @@ void stage_kernel(StageArgs a) {
       }
       __syncthreads();  // (A) plane primitives ready; previous plane's fluxes consumed
 
-      // (1) slopes, once per cell: x for cells -1..nxT of every row, y for rows -1..nyT of every column
+      // (1) slopes, once per cell: x for cells -1..nxT of every row, y for rows -1..nyT of
+      // every column.  One code path for both: centre cell, neighbour stride, and the
+      // two face slots the cell's states go to (its low face's right state and its
+      // high face's left state).
       const int nsx = (nxT + 2) * nyT, nsy = hasy ? nxT * (nyT + 2) : 0;
+      const int nfx = (nxT + 1) * nyT, nfy = hasy ? nxT * (nyT + 1) : 0;
       for (int w = tid; w < nsx + nsy; w += NT) {
+        int pc, stride, slo, shi;  // LDS cell, stride to its neighbours, slots (-1: none)
         if (w < nsx) {
           const int row = idiv(w, r_x2), c = w - row * (nxT + 2) - 1;
-#pragma unroll
-          for (int v = 0; v < NVAR; ++v) {
-            const RT qm = sP[buf][v][row + RO][c + 1], q0 = sP[buf][v][row + RO][c + 2],
-                     qp = sP[buf][v][row + RO][c + 3];
-            const RT sg = plm_slope<RT>(qm, q0, qp, theta);
-            if (c >= 0) sXR[v][row][c] = madd(RT(-0.5), sg, q0);       // right state of face c
-            if (c < nxT) sXL[v][row][c + 1] = madd(RT(0.5), sg, q0);   // left state of face c+1
-          }
+          pc = (row + RO) * (TX + 4) + c + 2;
+          stride = 1;
+          slo = c >= 0 ? row * (nxT + 1) + c : -1;
+          shi = c < nxT ? row * (nxT + 1) + c + 1 : -1;
         } else {
           const int w2 = w - nsx;
           const int r = idiv(w2, r_x0) - 1, col = w2 - (r + 1) * nxT;
+          pc = (r + RO) * (TX + 4) + col + 2;
+          stride = TX + 4;
+          slo = r >= 0 ? nfx + r * nxT + col : -1;
+          shi = r < nyT ? nfx + (r + 1) * nxT + col : -1;
+        }
 #pragma unroll
-          for (int v = 0; v < NVAR; ++v) {
-            const RT qm = sP[buf][v][r + RO - 1][col + 2], q0 = sP[buf][v][r + RO][col + 2],
-                     qp = sP[buf][v][r + RO + 1][col + 2];
-            const RT sg = plm_slope<RT>(qm, q0, qp, theta);
-            if (r >= 0) sYR[v][r][col] = madd(RT(-0.5), sg, q0);
-            if (r < nyT) sYL[v][r + 1][col] = madd(RT(0.5), sg, q0);
-          }
+        for (int v = 0; v < NVAR; ++v) {
+          const RT* pl = &sP[buf][v][0][0];
+          const RT qm = pl[pc - stride], q0 = pl[pc], qp = pl[pc + stride];
+          const RT sg = plm_slope<RT>(qm, q0, qp, theta);
+          if (slo >= 0) sFR[v][slo] = madd(RT(-0.5), sg, q0);  // right state of the cell's low face
+          if (shi >= 0) sFL[v][shi] = madd(RT(0.5), sg, q0);   // left state of its high face
         }
       }
       __syncthreads();  // (B) face states ready
@@ -221,26 +227,14 @@ void stage_kernel(StageArgs a) {
         }
       }
 
-      // (2) every x- and y-face flux of the block, once: face f lies between tile cells f-1 and f
-      const int nfx = (nxT + 1) * nyT, nfy = hasy ? nxT * (nyT + 1) : 0;
+      // (2) every x- and y-face flux of the block, once, written over its left state
       for (int w = tid; w < nfx + nfy; w += NT) {
         RT qL[NVAR], qR[NVAR], F[NVAR];
-        if (w < nfx) {
-          const int row = idiv(w, r_x1), f = w - row * (nxT + 1);
 #pragma unroll
-          for (int v = 0; v < NVAR; ++v) { qL[v] = sXL[v][row][f]; qR[v] = sXR[v][row][f]; }
-          riemann_flux<RT, 0>(qL, qR, K, kind, F);
+        for (int v = 0; v < NVAR; ++v) { qL[v] = sFL[v][w]; qR[v] = sFR[v][w]; }
+        riemann_flux_xy<RT>(qL, qR, w >= nfx, K, kind, F);
 #pragma unroll
-          for (int v = 0; v < NVAR; ++v) sXL[v][row][f] = F[v];
-        } else {
-          const int w2 = w - nfx;
-          const int f = idiv(w2, r_x0), col = w2 - f * nxT;
-#pragma unroll
-          for (int v = 0; v < NVAR; ++v) { qL[v] = sYL[v][f][col]; qR[v] = sYR[v][f][col]; }
-          riemann_flux<RT, 1>(qL, qR, K, kind, F);
-#pragma unroll
-          for (int v = 0; v < NVAR; ++v) sYL[v][f][col] = F[v];
-        }
+        for (int v = 0; v < NVAR; ++v) sFL[v][w] = F[v];
       }
       // z-face flux F_{k+1/2} of this column from the register queue
       RT Fzp[NVAR], qn2[NVAR], sg1[NVAR];
@@ -260,16 +254,17 @@ void stage_kernel(StageArgs a) {
       // (3) L(U) in the order x, y, z, then the TVD-RK2 stage combine
       if (act) {
         double L[NVAR];
+        const int sx = cy * (nxT + 1) + cx, sy = nfx + cy * nxT + cx;
 #pragma unroll
         for (int v = 0; v < NVAR; ++v) {
-          const double d = (double)sXL[v][cy][cx + 1] - (double)sXL[v][cy][cx];
+          const double d = (double)sFL[v][sx + 1] - (double)sFL[v][sx];
           if constexpr (FAST) L[v] = -d * P.rdx[0];
           else L[v] = 0.0 - d / P.dx[0];
         }
         if (hasy) {
 #pragma unroll
           for (int v = 0; v < NVAR; ++v) {
-            const double d = (double)sYL[v][cy + 1][cx] - (double)sYL[v][cy][cx];
+            const double d = (double)sFL[v][sy + nxT] - (double)sFL[v][sy];
             if constexpr (FAST) L[v] = fma(-d, P.rdx[1], L[v]);
             else L[v] = L[v] - d / P.dx[1];
           }
