@@ -89,6 +89,10 @@ enum { AMR_EXEC_PLAIN = 0, AMR_EXEC_BATCHED = 1 };
 #define AMR_STEP_TIMED 0x2u   /* enqueue this step eagerly (same kernels, same launch
                                  shapes as the batched graph) with HIP events around each
                                  stage kernel; read them with amr_table_last_stage_ms */
+#define AMR_STEP_SUBSTEP1 0x4u /* hierarchies: this level step is the second of the two
+                                 its parent level's step contains (its prolonged ghosts
+                                 take the parent's state at times 1/2 and 1 of that step,
+                                 instead of 0 and 1/2) */
 
 typedef struct {
   int32_t level;    /* refinement level, 0 = root; cell width dx0[d] / 2^level          */
@@ -160,9 +164,26 @@ amr_status amr_hydro_rk2_step(amr_table* table, double* U, const double* dt_dev,
                               hipStream_t stream);
 
 /* Coarse/fine flux correction and restriction for `coarse_level` (Berger &
- * Colella refluxing, Sec. 3).  Returns AMR_ESTATE for tables without a
- * coarse/fine interface at that level. */
+ * Colella refluxing; the paper's hierarchy, Sec. 3, is Berger & Colella AMR):
+ * every coarse cell next to a level coarse_level+1 patch and not covered by one
+ * replaces its own interface flux by the average of the fine fluxes recorded over
+ * the fine level's two steps, U_c += s (R_c - <R_f>) / dx_c (R = dt/2 per RK2
+ * stage, s = +1 where the interface is the cell's high face); then every covered
+ * coarse cell becomes the mean of its 2^ndim children.  Call after the coarse
+ * level's step and its children's two steps.  AMR_ESTATE if the level has no
+ * children or has not stepped. */
 amr_status amr_flux_correct(amr_table* table, double* U, int32_t coarse_level, hipStream_t stream);
+
+/* One root step of the whole hierarchy (factor-2 refinement in space and time,
+ * Sec. 3): level l advances with dt0 / 2^l; after a level's step its children take
+ * two steps, whose EXTERNAL ghosts not held by a sibling are prolonged
+ * (conservative, minmod-limited linear) from the parent interpolated linearly in
+ * time, then the level is flux-corrected and restricted.  dt0 is read from
+ * dt0_dev[0] (e.g. amr_cfl_dt with level -1).  flags must be 0.  For a
+ * single-level table this is amr_hydro_rk2_step of all patches.  Batched tables
+ * replay the whole root step from one captured HIP graph.  Asynchronous. */
+amr_status amr_hydro_advance(amr_table* table, double* U, const double* dt0_dev, uint32_t flags,
+                             hipStream_t stream);
 
 /* Wait for `stream`, then return AMR_EUNPHYSICAL if any kernel latched an
  * unphysical state since the table was created or last cleared, else AMR_OK.

@@ -25,11 +25,12 @@ AMR_PREC_FP64, AMR_PREC_MIXED = 0, 1
 AMR_EXEC_PLAIN, AMR_EXEC_BATCHED = 0, 1
 AMR_STEP_FUSE_DT = 0x1
 AMR_STEP_TIMED = 0x2
+AMR_STEP_SUBSTEP1 = 0x4
 
 EXPORTED = ("amr_patch_table_create", "amr_patch_table_destroy", "amr_table_arena_elems", "amr_cfl_dt",
             "amr_hydro_rk2_step", "amr_flux_correct", "amr_table_status", "amr_table_num_tilings",
             "amr_table_set_tiling", "amr_table_get_tiling", "amr_table_tiling_shape", "amr_autotune",
-            "amr_table_last_stage_ms", "amr_status_string")
+            "amr_table_last_stage_ms", "amr_hydro_advance", "amr_status_string")
 
 
 class amr_patch_desc(C.Structure):
@@ -69,6 +70,7 @@ def lib():
         L.amr_cfl_dt.argtypes = [vp, vp, C.c_double, i32, vp, dp, vp]
         L.amr_hydro_rk2_step.argtypes = [vp, vp, vp, i32, C.c_uint32, vp]
         L.amr_flux_correct.argtypes = [vp, vp, i32, vp]
+        L.amr_hydro_advance.argtypes = [vp, vp, vp, C.c_uint32, vp]
         L.amr_table_status.argtypes = [vp, vp]
         L.amr_table_num_tilings.argtypes = [vp]
         L.amr_table_set_tiling.argtypes = [vp, i32, i32]
@@ -176,6 +178,11 @@ def amr_flux_correct(h, U, coarse_level, stream=None):
     return _check(lib().amr_flux_correct(h, _ptr(U), int(coarse_level), _stream(stream)), "amr_flux_correct")
 
 
+def amr_hydro_advance(h, U, dt0_dev, flags=0, stream=None):
+    return _check(lib().amr_hydro_advance(h, _ptr(U), _ptr(dt0_dev), int(flags), _stream(stream)),
+                  "amr_hydro_advance")
+
+
 def amr_table_status(h, stream=None):
     return lib().amr_table_status(h, _stream(stream))
 
@@ -238,6 +245,12 @@ class Table:
         if dt is not None:
             self.dt.fill_(float(dt))
         amr_hydro_rk2_step(self.h, U, self.dt, level, flags)
+
+    def advance(self, U, dt0=None):
+        """One subcycled root step of the hierarchy (dt0 from the last cfl_dt unless given)."""
+        if dt0 is not None:
+            self.dt.fill_(float(dt0))
+        amr_hydro_advance(self.h, U, self.dt)
 
     def status(self):
         return amr_table_status(self.h)

@@ -14,6 +14,7 @@
 #include <map>
 #include <new>
 #include <tuple>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/amr_hydro.h"
@@ -67,6 +68,25 @@ struct amr_table {
   int occ[2][NSHAPES][2] = {};  // resident stage workgroups per CU
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // AMR_STEP_TIMED: before/between/after the stages
   bool timed_valid = false;
+  // ---- hierarchy (levels > 0 present): coarse/fine coupling plans, see build_hierarchy
+  std::vector<char> has_kids;                   // per level: a finer level exists
+  double* snap = nullptr;                       // U^n of levels with children (same layout as U)
+  double* reg = nullptr;                        // fine-face flux registers
+  double* dtl = nullptr;                        // per-level dt of the subcycled root step
+  std::vector<int64_t> reg_first, reg_len;      // per level, for clearing
+  ProlongOp* prol_d = nullptr;
+  std::vector<int> prol_first, prol_count;      // per destination level
+  PhysOp* phys_d = nullptr;
+  std::vector<int> phys_first, phys_count;      // per level with children
+  FixOp* fix_d = nullptr;
+  std::vector<std::vector<std::pair<int, int>>> fix_colors;  // per coarse level: (first, count) per color
+  RestrictOp* rst_d = nullptr;
+  std::vector<int> rst_first, rst_count;        // per coarse level
+  int64_t* snap_d = nullptr;                    // (offset, length) pairs
+  std::vector<int> snap_first, snap_count;      // per level
+  std::vector<int64_t> snap_maxlen;
+  std::vector<const double*> last_dt;           // dt pointer of each level's last step
+  GraphCache gadv;                              // captured root step (batched form)
 };
 
 #define HIPCHECK(x)                                     \
@@ -226,61 +246,138 @@ int occupancy_grid(amr_table* t, int stage, int ntiles) {
   return g >= 8 ? g / 8 * 8 : g;  // a multiple of the XCD count (tile list interleave)
 }
 
-// Enqueue the EXTERNAL ghost fill of arena A for the patches of `level`.
-amr_status enqueue_ghosts(amr_table* t, double* A, int level, hipStream_t s) {
-  if (t->nops == 0) return AMR_OK;
-  int first, count;
-  if (level < 0) {
-    first = 0;
-    count = t->nops;
-  } else {
-    first = t->ops_level_first[level];
-    count = t->ops_level_count[level];
+// Enqueue the EXTERNAL ghost fill of arena A for the patches of `level`: sibling
+// copies, then (levels > 0) prolongation from the coarse level interpolated in time
+// between its snapshot and its state in U at fraction alpha.
+amr_status enqueue_ghosts(amr_table* t, double* A, const double* U, int level, double alpha, hipStream_t s) {
+  if (t->nops > 0) {
+    int first, count;
+    if (level < 0) {
+      first = 0;
+      count = t->nops;
+    } else {
+      first = t->ops_level_first[level];
+      count = t->ops_level_count[level];
+    }
+    if (count > 0)
+      HIPCHECK(launch_copy_ghosts(std::min(count, 8 * t->ncu), s, t->ops_d + first, count, t->pdev_d, A));
   }
-  if (count == 0) return AMR_OK;
-  HIPCHECK(launch_copy_ghosts(std::min(count, 8 * t->ncu), s, t->ops_d + first, count, t->pdev_d, A));
+  if (level > 0 && t->prol_count[level] > 0) {
+    const int first = t->prol_first[level], count = t->prol_count[level];
+    HIPCHECK(launch_prolong(std::min(count, 8 * t->ncu), s, t->prol_d + first, count, t->pdev_d, A, t->snap, U, alpha,
+                            t->ph.ndim));
+  }
   return AMR_OK;
 }
 
-// Enqueue one RK2 step (both stages) on stream s; with `ev`, record ev[0] before
-// stage 1's launches, ev[1] between the stages and ev[2] after stage 2's.
+// One stage kernel launch (or one per patch in the plain form) over `level`.
+amr_status enqueue_stage(amr_table* t, TileSet* ts, int stage, const double* V, const double* U0, double* out,
+                         const double* dt, bool fuse, bool rec, hipStream_t s) {
+  const int mixed = t->ph.precision == AMR_PREC_MIXED;
+  StageArgs a{};
+  a.V = V;
+  a.U0 = U0;
+  a.out = out;
+  a.dt = dt;
+  a.patches = t->pdev_d;
+  a.flag = t->flag_d;
+  a.smax = (stage == 2 && fuse) ? t->fused_d : nullptr;
+  a.reg = rec ? t->reg : nullptr;
+  a.c = consts_of(t);
+  if (t->ph.exec == AMR_EXEC_BATCHED) {
+    a.tiles = ts->d;
+    a.ntiles = ts->n;
+    HIPCHECK(launch_stage(mixed, t->shape, stage, occupancy_grid(t, stage, ts->n), s, a));
+  } else {
+    for (size_t p = 0; p < t->pdev.size(); ++p) {
+      if (ts->count[p] == 0) continue;
+      a.tiles = ts->d + ts->n + ts->first[p];
+      a.ntiles = ts->count[p];
+      HIPCHECK(launch_stage(mixed, t->shape, stage, ts->count[p], s, a));
+    }
+  }
+  return AMR_OK;
+}
+
+// Enqueue one RK2 step (both stages) of `level` on stream s.  `substep` (0 or 1) is
+// the step's position inside its parent level's step: the coarse data of its
+// prolonged ghosts is taken at parent-time fractions substep/2 (stage 1 input) and
+// (substep+1)/2 (stage 2 input).  A level with children also writes its physical
+// ghosts into storage, keeps U^n (the snapshot its children interpolate from),
+// refills U^{n+1}'s ghosts and clears its children's registers.  With `ev`, record
+// ev[0] before stage 1, ev[1] between the stages and ev[2] after stage 2.
 amr_status enqueue_step(amr_table* t, double* U, const double* dt, int level, uint32_t flags, hipStream_t s,
-                        hipEvent_t* ev = nullptr) {
+                        hipEvent_t* ev = nullptr, int substep = 0) {
   TileSet* ts = nullptr;
   amr_status st = get_tiles(t, level, t->shape, t->zslab, &ts);
   if (st != AMR_OK) return st;
   if (ts->n == 0) return AMR_OK;
-  const int mixed = t->ph.precision == AMR_PREC_MIXED;
   const bool fuse = (flags & AMR_STEP_FUSE_DT) != 0;
+  const bool kids = level >= 0 && t->has_kids[level];
+  const bool rec = level > 0 && t->reg != nullptr;
+  const double a1 = 0.5 * substep, a2 = 0.5 * (substep + 1);
   if (fuse) HIPCHECK(launch_fill_u64(s, t->fused_d, MAX_LEVELS + 1, 0ull));
-  for (int stage = 1; stage <= 2; ++stage) {
-    double* V = stage == 1 ? U : t->U1;
-    st = enqueue_ghosts(t, V, level, s);
+  st = enqueue_ghosts(t, U, U, level, a1, s);
+  if (st != AMR_OK) return st;
+  if (kids) {
+    if (t->phys_count[level] > 0)
+      HIPCHECK(launch_phys(std::min(t->phys_count[level], 8 * t->ncu), s, t->phys_d + t->phys_first[level],
+                           t->phys_count[level], t->pdev_d, U));
+    HIPCHECK(launch_copy_ranges(s, t->snap_d + 2 * t->snap_first[level], t->snap_count[level],
+                                t->snap_maxlen[level], U, t->snap));
+  }
+  if (ev) HIPCHECK(hipEventRecord(ev[0], s));
+  st = enqueue_stage(t, ts, 1, U, nullptr, t->U1, dt, fuse, rec, s);
+  if (st != AMR_OK) return st;
+  st = enqueue_ghosts(t, t->U1, U, level, a2, s);
+  if (st != AMR_OK) return st;
+  if (ev) HIPCHECK(hipEventRecord(ev[1], s));
+  st = enqueue_stage(t, ts, 2, t->U1, U, U, dt, fuse, rec, s);
+  if (st != AMR_OK) return st;
+  if (ev) HIPCHECK(hipEventRecord(ev[2], s));
+  if (kids) {
+    st = enqueue_ghosts(t, U, U, level, a2, s);
     if (st != AMR_OK) return st;
-    if (ev) HIPCHECK(hipEventRecord(ev[stage - 1], s));
-    StageArgs a{};
-    a.V = V;
-    a.U0 = stage == 2 ? U : nullptr;
-    a.out = stage == 1 ? t->U1 : U;
-    a.dt = dt;
-    a.patches = t->pdev_d;
-    a.flag = t->flag_d;
-    a.smax = (stage == 2 && fuse) ? t->fused_d : nullptr;
-    a.c = consts_of(t);
-    if (t->ph.exec == AMR_EXEC_BATCHED) {
-      a.tiles = ts->d;
-      a.ntiles = ts->n;
-      HIPCHECK(launch_stage(mixed, t->shape, stage, occupancy_grid(t, stage, ts->n), s, a));
-    } else {
-      for (size_t p = 0; p < t->pdev.size(); ++p) {
-        if (ts->count[p] == 0) continue;
-        a.tiles = ts->d + ts->n + ts->first[p];
-        a.ntiles = ts->count[p];
-        HIPCHECK(launch_stage(mixed, t->shape, stage, ts->count[p], s, a));
-      }
+    if (t->phys_count[level] > 0)
+      HIPCHECK(launch_phys(std::min(t->phys_count[level], 8 * t->ncu), s, t->phys_d + t->phys_first[level],
+                           t->phys_count[level], t->pdev_d, U));
+    const int64_t len = t->reg_len[level + 1];
+    if (len > 0) {
+      for (int64_t o = 0; o < len; o += (int64_t)1 << 30)
+        HIPCHECK(launch_fill_u64(s, reinterpret_cast<unsigned long long*>(t->reg + t->reg_first[level + 1] + o),
+                                 (int)std::min<int64_t>(len - o, (int64_t)1 << 30), 0ull));
     }
   }
-  if (ev) HIPCHECK(hipEventRecord(ev[2], s));
+  if (level >= 0) t->last_dt[level] = dt;
+  return AMR_OK;
+}
+
+// Refluxing of `l` against level l+1, then restriction of the covered cells.
+amr_status enqueue_correct(amr_table* t, double* U, int l, hipStream_t s) {
+  const int mixed = t->ph.precision == AMR_PREC_MIXED;
+  for (const auto& fc : t->fix_colors[l])
+    if (fc.second > 0)
+      HIPCHECK(launch_flux_fix(mixed, std::min(fc.second, 8 * t->ncu), s, t->fix_d + fc.first, fc.second, t->pdev_d,
+                               U, t->snap, t->U1, t->reg, t->last_dt[l], consts_of(t), t->flag_d));
+  if (t->rst_count[l] > 0)
+    HIPCHECK(launch_restrict(std::min(t->rst_count[l], 8 * t->ncu), s, t->rst_d + t->rst_first[l], t->rst_count[l],
+                             t->pdev_d, U, t->ph.ndim));
+  return AMR_OK;
+}
+
+// The subcycled root step: level l steps once, then (if it has children) level
+// l+1 steps twice with half the time step, then level l is corrected.
+amr_status enqueue_advance(amr_table* t, double* U, int l, int substep, hipStream_t s) {
+  amr_status st = enqueue_step(t, U, t->dtl + l, l, 0, s, nullptr, substep);
+  if (st != AMR_OK) return st;
+  if (l < t->max_level && t->has_kids[l]) {
+    for (int k = 0; k < 2; ++k) {
+      st = enqueue_advance(t, U, l + 1, k, s);
+      if (st != AMR_OK) return st;
+    }
+    st = enqueue_correct(t, U, l, s);
+    if (st != AMR_OK) return st;
+  }
   return AMR_OK;
 }
 
@@ -288,6 +385,9 @@ void drop_graph(amr_table* t) {
   if (t->gc.exec) (void)hipGraphExecDestroy(t->gc.exec);
   if (t->gc.graph) (void)hipGraphDestroy(t->gc.graph);
   t->gc = GraphCache{};
+  if (t->gadv.exec) (void)hipGraphExecDestroy(t->gadv.exec);
+  if (t->gadv.graph) (void)hipGraphDestroy(t->gadv.graph);
+  t->gadv = GraphCache{};
 }
 
 amr_status validate(const amr_patch_desc* P, int32_t np, const amr_physics* ph) {
@@ -330,9 +430,11 @@ amr_status validate(const amr_patch_desc* P, int32_t np, const amr_physics* ph) 
   return AMR_OK;
 }
 
-// Same-level copy plan for EXTERNAL faces (sibling ghosts; periodic root
-// domain wrap).  Fails with AMR_EINVAL if a needed ghost cell has no source.
-amr_status build_ghost_plan(amr_table* t, std::vector<CopyOp>& ops) {
+// EXTERNAL ghost plan: each ghost cell (two layers, the cross region) is copied
+// from the same-level patch that holds it as an active cell (periodic root domain
+// wrap applied) or, on levels > 0, prolonged from the level-1 patch holding its
+// coarse cell.  Fails with AMR_EINVAL if a ghost cell has no source.
+amr_status build_ghost_plan(amr_table* t, std::vector<CopyOp>& ops, std::vector<ProlongOp>& pops) {
   const int nd = t->ph.ndim;
   const int np = (int)t->desc.size();
   const int layers = 2;  // the PLM stencil reads two ghost layers
@@ -357,7 +459,16 @@ amr_status build_ghost_plan(amr_table* t, std::vector<CopyOp>& ops) {
             else if (glo >= dom) wrap[e] = -dom;
           }
         }
-        int64_t need = (int64_t)bsz[0] * bsz[1] * bsz[2], got = 0;
+        // coverage map of the box, x fastest
+        std::vector<char> cov((size_t)bsz[0] * bsz[1] * bsz[2], 0);
+        auto mark = [&](const int lo[3], const int sz[3]) {  // box in p-local coordinates
+          for (int k = 0; k < sz[2]; ++k)
+            for (int j = 0; j < sz[1]; ++j)
+              for (int i = 0; i < sz[0]; ++i) {
+                const int x = lo[0] + i - blo[0], y = lo[1] + j - blo[1], z = lo[2] + k - blo[2];
+                cov[((size_t)z * bsz[1] + y) * bsz[0] + x]++;
+              }
+        };
         for (int q = 0; q < np; ++q) {
           const amr_patch_desc& Q = t->desc[q];
           if (Q.level != D.level) continue;
@@ -384,10 +495,68 @@ amr_status build_ghost_plan(amr_table* t, std::vector<CopyOp>& ops) {
             op.sh[e] = D.lo[e] + wrap[e] - Q.lo[e];
           }
           if (empty) continue;
-          got += (int64_t)op.sz[0] * op.sz[1] * op.sz[2];
+          mark(op.lo, op.sz);
           ops.push_back(op);
         }
-        if (got != need) return AMR_EINVAL;  // uncovered or doubly covered ghost cells
+        if (D.level > 0) {
+          for (int q = 0; q < np; ++q) {
+            const amr_patch_desc& Q = t->desc[q];
+            if (Q.level != D.level - 1) continue;
+            int ilo[3], isz[3];  // intersection with the refined coarse patch, p-local
+            bool empty = false;
+            for (int e = 0; e < 3; ++e) {
+              if (e >= nd) {
+                ilo[e] = 0;
+                isz[e] = 1;
+                continue;
+              }
+              const int glo = D.lo[e] + blo[e] + wrap[e], ghi = glo + bsz[e];
+              const int lo = std::max(glo, 2 * Q.lo[e]), hi = std::min(ghi, 2 * (Q.lo[e] + Q.n[e]));
+              if (hi <= lo) {
+                empty = true;
+                break;
+              }
+              ilo[e] = lo - D.lo[e] - wrap[e];
+              isz[e] = hi - lo;
+            }
+            if (empty) continue;
+            // rows (x runs) of cells not held by a sibling
+            for (int k = 0; k < isz[2]; ++k)
+              for (int j = 0; j < isz[1]; ++j) {
+                int i = 0;
+                while (i < isz[0]) {
+                  auto covered = [&](int ii) {
+                    const int x = ilo[0] + ii - blo[0], y = ilo[1] + j - blo[1], z = ilo[2] + k - blo[2];
+                    return cov[((size_t)z * bsz[1] + y) * bsz[0] + x] != 0;
+                  };
+                  if (covered(i)) {
+                    ++i;
+                    continue;
+                  }
+                  int i1 = i;
+                  while (i1 < isz[0] && !covered(i1)) ++i1;
+                  ProlongOp op{};
+                  op.dst = p;
+                  op.src = q;
+                  op.lo[0] = ilo[0] + i;
+                  op.lo[1] = ilo[1] + j;
+                  op.lo[2] = ilo[2] + k;
+                  op.sz[0] = i1 - i;
+                  op.sz[1] = 1;
+                  op.sz[2] = 1;
+                  for (int e = 0; e < 3; ++e) {
+                    op.foff[e] = e < nd ? D.lo[e] + wrap[e] : 0;
+                    op.clo[e] = e < nd ? Q.lo[e] : 0;
+                  }
+                  pops.push_back(op);
+                  mark(op.lo, op.sz);
+                  i = i1;
+                }
+              }
+          }
+        }
+        for (char c : cov)
+          if (c != 1) return AMR_EINVAL;  // a ghost cell without (or with two) sources
       }
   }
   std::stable_sort(ops.begin(), ops.end(),
@@ -399,6 +568,234 @@ amr_status build_ghost_plan(amr_table* t, std::vector<CopyOp>& ops) {
     t->ops_level_first[l] = i;
     t->ops_level_count[l]++;
   }
+  std::stable_sort(pops.begin(), pops.end(),
+                   [&](const ProlongOp& a, const ProlongOp& b) { return t->desc[a.dst].level < t->desc[b.dst].level; });
+  t->prol_first.assign(MAX_LEVELS, 0);
+  t->prol_count.assign(MAX_LEVELS, 0);
+  for (int i = (int)pops.size() - 1; i >= 0; --i) {
+    const int l = t->desc[pops[i].dst].level;
+    t->prol_first[l] = i;
+    t->prol_count[l]++;
+  }
+  return AMR_OK;
+}
+
+// Coarse/fine coupling plans of the hierarchy: registers, physical-ghost fills and
+// snapshots of levels with children, refluxing ops (coloured so that ops sharing a
+// coarse cell run in plan order, one colour after another) and restriction ops.
+struct HierPlan {
+  std::vector<PhysOp> phys;
+  std::vector<FixOp> fix;
+  std::vector<int> fix_color;
+  std::vector<RestrictOp> rst;
+  std::vector<int64_t> snap;  // (offset, length) pairs
+  int64_t nreg = 0;
+};
+
+amr_status build_hierarchy(amr_table* t, HierPlan& H) {
+  const int nd = t->ph.ndim;
+  const int np = (int)t->desc.size();
+  const int L = t->max_level + 1;
+  t->has_kids.assign(MAX_LEVELS, 0);
+  for (const auto& D : t->desc)
+    if (D.level > 0) t->has_kids[D.level - 1] = 1;
+  // level > 0 patches start and end on coarse cell boundaries
+  for (const auto& D : t->desc)
+    if (D.level > 0)
+      for (int e = 0; e < nd; ++e)
+        if ((D.lo[e] & 1) || (D.n[e] & 1)) return AMR_EINVAL;
+  // registers, level by level
+  t->reg_first.assign(MAX_LEVELS, 0);
+  t->reg_len.assign(MAX_LEVELS, 0);
+  for (int l = 1; l < L; ++l) {
+    t->reg_first[l] = H.nreg;
+    for (int p = 0; p < np; ++p) {
+      const auto& D = t->desc[p];
+      if (D.level != l) continue;
+      for (int d = 0; d < nd; ++d)
+        for (int side = 0; side < 2; ++side) {
+          if (D.bc[2 * d + side] != AMR_BC_EXTERNAL) continue;
+          int64_t area = 1;
+          for (int e = 0; e < 3; ++e)
+            if (e != d) area *= D.n[e];
+          t->pdev[p].reg[2 * d + side] = H.nreg;
+          H.nreg += 5 * area;
+        }
+    }
+    t->reg_len[l] = H.nreg - t->reg_first[l];
+  }
+  // physical ghosts and snapshots of levels with children
+  t->phys_first.assign(MAX_LEVELS, 0);
+  t->phys_count.assign(MAX_LEVELS, 0);
+  t->snap_first.assign(MAX_LEVELS, 0);
+  t->snap_count.assign(MAX_LEVELS, 0);
+  t->snap_maxlen.assign(MAX_LEVELS, 0);
+  for (int l = 0; l < L; ++l) {
+    if (!t->has_kids[l]) continue;
+    t->phys_first[l] = (int)H.phys.size();
+    t->snap_first[l] = (int)H.snap.size() / 2;
+    for (int p = 0; p < np; ++p) {
+      const auto& D = t->desc[p];
+      if (D.level != l) continue;
+      const PatchDev& P = t->pdev[p];
+      H.snap.push_back(P.off);
+      H.snap.push_back(5 * P.S);
+      t->snap_maxlen[l] = std::max<int64_t>(t->snap_maxlen[l], 5 * P.S);
+      for (int d = 0; d < nd; ++d)
+        for (int side = 0; side < 2; ++side) {
+          if (D.bc[2 * d + side] == AMR_BC_EXTERNAL) continue;
+          PhysOp op{};
+          op.patch = p;
+          for (int e = 0; e < 3; ++e) {
+            op.lo[e] = 0;
+            op.sz[e] = D.n[e];
+          }
+          op.lo[d] = side == 0 ? -2 : D.n[d];
+          op.sz[d] = 2;
+          H.phys.push_back(op);
+        }
+    }
+    t->phys_count[l] = (int)H.phys.size() - t->phys_first[l];
+    t->snap_count[l] = (int)H.snap.size() / 2 - t->snap_first[l];
+  }
+  // coarse cells (level l coordinates) under a level l+1 patch
+  auto key3 = [](int x, int y, int z) { return ((int64_t)z << 42) ^ ((int64_t)y << 21) ^ (int64_t)x; };
+  std::vector<std::unordered_set<int64_t>> cov(L);
+  for (const auto& F : t->desc) {
+    if (F.level == 0) continue;
+    int lo[3], hi[3];
+    for (int e = 0; e < 3; ++e) {
+      lo[e] = e < nd ? F.lo[e] / 2 : 0;
+      hi[e] = e < nd ? (F.lo[e] + F.n[e]) / 2 : 1;
+    }
+    for (int z = lo[2]; z < hi[2]; ++z)
+      for (int y = lo[1]; y < hi[1]; ++y)
+        for (int x = lo[0]; x < hi[0]; ++x) cov[F.level - 1].insert(key3(x, y, z));
+  }
+  auto covered = [&](int l, const int c[3]) { return cov[l].count(key3(c[0], c[1], c[2])) != 0; };
+  // refluxing and restriction ops, coarse level by coarse level
+  t->fix_colors.assign(MAX_LEVELS, {});
+  t->rst_first.assign(MAX_LEVELS, 0);
+  t->rst_count.assign(MAX_LEVELS, 0);
+  std::vector<FixOp> fixall;
+  std::vector<int> colall;
+  for (int l = 0; l + 1 < L; ++l) {
+    std::map<std::pair<int, int64_t>, int> last_color;  // (coarse patch, cell) -> colour of its last op
+    std::vector<FixOp> fl;
+    std::vector<int> cl;
+    for (int p = 0; p < np; ++p) {
+      const auto& F = t->desc[p];
+      if (F.level != l + 1) continue;
+      for (int d = 0; d < nd; ++d)
+        for (int side = 0; side < 2; ++side) {
+          if (F.bc[2 * d + side] != AMR_BC_EXTERNAL) continue;
+          const int cf = (F.lo[d] + (side ? F.n[d] : 0)) / 2;
+          int Cd = side == 0 ? cf - 1 : cf;
+          if ((t->ph.periodic >> d) & 1) {
+            const int dom = t->ph.domain[d] << l;
+            Cd = ((Cd % dom) + dom) % dom;
+          }
+          int flo[3], fhi[3];  // coarse footprint (level l coordinates)
+          for (int e = 0; e < 3; ++e) {
+            flo[e] = e < nd ? F.lo[e] / 2 : 0;
+            fhi[e] = e < nd ? (F.lo[e] + F.n[e]) / 2 : 1;
+          }
+          flo[d] = Cd;
+          fhi[d] = Cd + 1;
+          for (int q = 0; q < np; ++q) {
+            const auto& Q = t->desc[q];
+            if (Q.level != l) continue;
+            int lo[3], hi[3];
+            bool empty = false;
+            for (int e = 0; e < 3; ++e) {
+              lo[e] = e < nd ? std::max(flo[e], Q.lo[e]) : 0;
+              hi[e] = e < nd ? std::min(fhi[e], Q.lo[e] + Q.n[e]) : 1;
+              if (hi[e] <= lo[e]) empty = true;
+            }
+            if (empty) continue;
+            // x runs of uncovered cells
+            for (int z = lo[2]; z < hi[2]; ++z)
+              for (int y = lo[1]; y < hi[1]; ++y) {
+                int x = lo[0];
+                while (x < hi[0]) {
+                  int c3[3] = {x, y, z};
+                  if (covered(l, c3)) {
+                    ++x;
+                    continue;
+                  }
+                  int x1 = x;
+                  while (x1 < hi[0]) {
+                    int c4[3] = {x1, y, z};
+                    if (covered(l, c4)) break;
+                    ++x1;
+                  }
+                  FixOp op{};
+                  op.fine = p;
+                  op.coarse = q;
+                  op.d = d;
+                  op.side = side;
+                  op.lo[0] = x - Q.lo[0];
+                  op.lo[1] = y - (nd > 1 ? Q.lo[1] : 0);
+                  op.lo[2] = z - (nd > 2 ? Q.lo[2] : 0);
+                  op.sz[0] = x1 - x;
+                  op.sz[1] = 1;
+                  op.sz[2] = 1;
+                  for (int e = 0; e < 3; ++e) op.fo[e] = e < nd ? 2 * Q.lo[e] - F.lo[e] : 0;
+                  int color = 0;
+                  for (int xx = x; xx < x1; ++xx) {
+                    const int64_t key = ((int64_t)z * 65536 + y) * 65536 + xx;
+                    auto it = last_color.find({q, key});
+                    if (it != last_color.end()) color = std::max(color, it->second + 1);
+                  }
+                  for (int xx = x; xx < x1; ++xx) last_color[{q, ((int64_t)z * 65536 + y) * 65536 + xx}] = color;
+                  fl.push_back(op);
+                  cl.push_back(color);
+                  x = x1;
+                }
+              }
+          }
+        }
+    }
+    // order by colour (stable: plan order within a colour)
+    int ncol = 0;
+    for (int c : cl) ncol = std::max(ncol, c + 1);
+    for (int c = 0; c < ncol; ++c) {
+      const int first = (int)fixall.size();
+      for (size_t i = 0; i < fl.size(); ++i)
+        if (cl[i] == c) fixall.push_back(fl[i]);
+      t->fix_colors[l].push_back({first, (int)fixall.size() - first});
+    }
+    // restriction
+    t->rst_first[l] = (int)H.rst.size();
+    for (int p = 0; p < np; ++p) {
+      const auto& F = t->desc[p];
+      if (F.level != l + 1) continue;
+      for (int q = 0; q < np; ++q) {
+        const auto& Q = t->desc[q];
+        if (Q.level != l) continue;
+        RestrictOp op{};
+        op.fine = p;
+        op.coarse = q;
+        bool empty = false;
+        for (int e = 0; e < 3; ++e) {
+          if (e >= nd) {
+            op.lo[e] = 0;
+            op.sz[e] = 1;
+            op.fo[e] = 0;
+            continue;
+          }
+          const int lo = std::max(F.lo[e] / 2, Q.lo[e]), hi = std::min((F.lo[e] + F.n[e]) / 2, Q.lo[e] + Q.n[e]);
+          if (hi <= lo) empty = true;
+          op.lo[e] = lo - Q.lo[e];
+          op.sz[e] = hi - lo;
+          op.fo[e] = 2 * Q.lo[e] - F.lo[e];
+        }
+        if (!empty) H.rst.push_back(op);
+      }
+    }
+    t->rst_count[l] = (int)H.rst.size() - t->rst_first[l];
+  }
+  H.fix = fixall;
   return AMR_OK;
 }
 
@@ -443,17 +840,24 @@ amr_status amr_patch_table_create(const amr_patch_desc* patches, int32_t npatch,
       S *= P.s[d];
     }
     P.S = S;
-    for (int f = 0; f < 6; ++f) P.bc[f] = D.bc[f];
+    for (int f = 0; f < 6; ++f) {
+      P.bc[f] = D.bc[f];
+      P.reg[f] = -1;
+    }
     t->pdev.push_back(P);
     t->arena = std::max(t->arena, D.offset + 5 * S);
     t->max_level = std::max(t->max_level, D.level);
   }
   std::vector<CopyOp> ops;
-  st = build_ghost_plan(t, ops);
+  std::vector<ProlongOp> pops;
+  HierPlan H;
+  st = build_ghost_plan(t, ops, pops);
+  if (st == AMR_OK) st = build_hierarchy(t, H);
   if (st != AMR_OK) {
     delete t;
     return st;
   }
+  t->last_dt.assign(MAX_LEVELS, nullptr);
   auto fail = [&](amr_status s) {
     amr_patch_table_destroy(t);
     return s;
@@ -473,6 +877,31 @@ amr_status amr_patch_table_create(const amr_patch_desc* patches, int32_t npatch,
     return fail(AMR_EHIP);
   if (t->nops > 0 && hipMemcpyAsync(t->ops_d, ops.data(), sizeof(CopyOp) * ops.size(), hipMemcpyHostToDevice,
                                     stream) != hipSuccess)
+    return fail(AMR_EHIP);
+  // hierarchy plans
+  auto upload = [&](auto** dst, const auto& v) -> bool {
+    if (v.empty()) return true;
+    using T = typename std::remove_reference<decltype(v)>::type::value_type;
+    if (hipMalloc(dst, sizeof(T) * v.size()) != hipSuccess) return false;
+    return hipMemcpyAsync(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, stream) == hipSuccess;
+  };
+  if (!upload(&t->prol_d, pops) || !upload(&t->phys_d, H.phys) || !upload(&t->fix_d, H.fix) ||
+      !upload(&t->rst_d, H.rst) || !upload(&t->snap_d, H.snap))
+    return fail(AMR_ENOMEM);
+  if (t->max_level > 0) {
+    if (hipMalloc(&t->snap, sizeof(double) * (size_t)t->arena) != hipSuccess) return fail(AMR_ENOMEM);
+    if (hipMalloc(&t->dtl, sizeof(double) * MAX_LEVELS) != hipSuccess) return fail(AMR_ENOMEM);
+    if (H.nreg > 0) {
+      if (hipMalloc(&t->reg, sizeof(double) * (size_t)H.nreg) != hipSuccess) return fail(AMR_ENOMEM);
+      for (int64_t o = 0; o < H.nreg; o += (int64_t)1 << 30)
+        if (launch_fill_u64(stream, reinterpret_cast<unsigned long long*>(t->reg + o),
+                            (int)std::min<int64_t>(H.nreg - o, (int64_t)1 << 30), 0ull) != hipSuccess)
+          return fail(AMR_EHIP);
+    }
+  }
+  // the patch copy carries the register offsets
+  if (hipMemcpyAsync(t->pdev_d, t->pdev.data(), sizeof(PatchDev) * t->pdev.size(), hipMemcpyHostToDevice,
+                     stream) != hipSuccess)
     return fail(AMR_EHIP);
   if (launch_fill_i32(stream, t->flag_d, 1, 0) != hipSuccess) return fail(AMR_EHIP);
   if (launch_fill_u64(stream, t->fused_d, MAX_LEVELS + 1, 0ull) != hipSuccess) return fail(AMR_EHIP);
@@ -496,6 +925,9 @@ amr_status amr_patch_table_destroy(amr_table* t) {
   if (t->smax_d) (void)hipFree(t->smax_d);
   if (t->fused_d) (void)hipFree(t->fused_d);
   if (t->ops_d) (void)hipFree(t->ops_d);
+  for (void* q : {(void*)t->snap, (void*)t->reg, (void*)t->dtl, (void*)t->prol_d, (void*)t->phys_d, (void*)t->fix_d,
+                  (void*)t->rst_d, (void*)t->snap_d})
+    if (q) (void)hipFree(q);
   if (t->cap_stream) (void)hipStreamDestroy(t->cap_stream);
   for (auto& e : t->ev)
     if (e) (void)hipEventDestroy(e);
@@ -507,14 +939,17 @@ int64_t amr_table_arena_elems(const amr_table* t) { return t ? t->arena : -1; }
 
 amr_status amr_hydro_rk2_step(amr_table* t, double* U, const double* dt_dev, int32_t level, uint32_t flags,
                               hipStream_t stream) {
-  if (!t || !U || !dt_dev || level < -1 || level > t->max_level || (flags & ~(AMR_STEP_FUSE_DT | AMR_STEP_TIMED)))
+  if (!t || !U || !dt_dev || level < -1 || level > t->max_level ||
+      (flags & ~(AMR_STEP_FUSE_DT | AMR_STEP_TIMED | AMR_STEP_SUBSTEP1)))
     return AMR_EINVAL;
+  if (t->max_level > 0 && (level < 0 || (flags & AMR_STEP_FUSE_DT))) return AMR_EINVAL;
   const bool fuse = (flags & AMR_STEP_FUSE_DT) != 0;
+  const int substep = (flags & AMR_STEP_SUBSTEP1) ? 1 : 0;
   if (flags & AMR_STEP_TIMED) {
     for (auto& e : t->ev)
       if (!e) HIPCHECK(hipEventCreate(&e));
     t->timed_valid = false;
-    amr_status st = enqueue_step(t, U, dt_dev, level, flags & AMR_STEP_FUSE_DT, stream, t->ev);
+    amr_status st = enqueue_step(t, U, dt_dev, level, flags & AMR_STEP_FUSE_DT, stream, t->ev, substep);
     if (st != AMR_OK) return st;
     t->timed_valid = true;
   } else if (t->ph.exec == AMR_EXEC_BATCHED) {
@@ -529,7 +964,7 @@ amr_status amr_hydro_rk2_step(amr_table* t, double* U, const double* dt_dev, int
       occupancy_grid(t, 1, ts->n);
       occupancy_grid(t, 2, ts->n);
       HIPCHECK(hipStreamBeginCapture(t->cap_stream, hipStreamCaptureModeThreadLocal));
-      st = enqueue_step(t, U, dt_dev, level, flags, t->cap_stream);
+      st = enqueue_step(t, U, dt_dev, level, flags, t->cap_stream, nullptr, substep);
       hipGraph_t graph = nullptr;
       hipError_t e = hipStreamEndCapture(t->cap_stream, &graph);
       if (st != AMR_OK) {
@@ -553,7 +988,7 @@ amr_status amr_hydro_rk2_step(amr_table* t, double* U, const double* dt_dev, int
     }
     HIPCHECK(hipGraphLaunch(g.exec, stream));
   } else {
-    amr_status st = enqueue_step(t, U, dt_dev, level, flags, stream);
+    amr_status st = enqueue_step(t, U, dt_dev, level, flags, stream, nullptr, substep);
     if (st != AMR_OK) return st;
   }
   if (fuse) {
@@ -608,7 +1043,57 @@ amr_status amr_cfl_dt(amr_table* t, const double* U, double cfl, int32_t level, 
 
 amr_status amr_flux_correct(amr_table* t, double* U, int32_t coarse_level, hipStream_t stream) {
   if (!t || !U || coarse_level < 0 || coarse_level > t->max_level) return AMR_EINVAL;
-  return AMR_ESTATE;  // no coarse/fine interface in this table
+  if (!t->has_kids[coarse_level] || !t->last_dt[coarse_level]) return AMR_ESTATE;
+  return enqueue_correct(t, U, coarse_level, stream);
+}
+
+amr_status amr_hydro_advance(amr_table* t, double* U, const double* dt0_dev, uint32_t flags, hipStream_t stream) {
+  if (!t || !U || !dt0_dev || flags != 0) return AMR_EINVAL;
+  auto enqueue_all = [&](hipStream_t s) -> amr_status {
+    HIPCHECK(launch_scale_dt(s, dt0_dev, t->dtl ? t->dtl : nullptr, t->max_level + 1));
+    return enqueue_advance(t, U, 0, 0, s);
+  };
+  if (t->max_level == 0) {  // no hierarchy: one step of the root level with dt0
+    return amr_hydro_rk2_step(t, U, dt0_dev, -1, 0, stream);
+  }
+  for (int l = 0; l <= t->max_level; ++l) {  // tile lists and occupancy before any capture
+    TileSet* ts = nullptr;
+    amr_status st = get_tiles(t, l, t->shape, t->zslab, &ts);
+    if (st != AMR_OK) return st;
+    occupancy_grid(t, 1, ts->n);
+    occupancy_grid(t, 2, ts->n);
+  }
+  if (t->ph.exec == AMR_EXEC_BATCHED) {
+    GraphCache& g = t->gadv;
+    if (!(g.exec && g.U == U && g.dt == dt0_dev && g.shape == t->shape && g.zslab == t->zslab)) {
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+      if (g.graph) (void)hipGraphDestroy(g.graph);
+      g = GraphCache{};
+      HIPCHECK(hipStreamBeginCapture(t->cap_stream, hipStreamCaptureModeThreadLocal));
+      amr_status st = enqueue_all(t->cap_stream);
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamEndCapture(t->cap_stream, &graph);
+      if (st != AMR_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+      }
+      if (e != hipSuccess) return AMR_EHIP;
+      hipGraphExec_t exec = nullptr;
+      if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return AMR_EHIP;
+      }
+      g.exec = exec;
+      g.graph = graph;
+      g.U = U;
+      g.dt = dt0_dev;
+      g.shape = t->shape;
+      g.zslab = t->zslab;
+    }
+    HIPCHECK(hipGraphLaunch(g.exec, stream));
+    return AMR_OK;
+  }
+  return enqueue_all(stream);
 }
 
 amr_status amr_table_status(amr_table* t, hipStream_t stream) {

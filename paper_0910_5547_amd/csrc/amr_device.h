@@ -39,6 +39,7 @@ struct PatchDev {
   int pad;
   double dx[3];  // cell widths at this level
   double rdx[3]; // 1/dx (mixed path)
+  int64_t reg[6];  // fine-face flux register of each face (element offset), -1 = none
 };
 
 // One unit of stage-kernel work: a TX x TY column block of one patch, marched
@@ -52,6 +53,39 @@ struct Tile {
 struct CopyOp {
   int dst, src;
   int lo[3], sz[3], sh[3];
+  int pad;
+};
+
+// Coarse -> fine ghost fill: dst ghost cells in box [lo, lo+sz) (dst-local) are
+// prolonged from coarse patch src.  A dst-local cell x has fine level coordinate
+// x + foff (foff = dst lo + periodic wrap, so it lies in the root domain), coarse
+// level coordinate (x + foff) >> 1 and src-local coarse coordinate that minus clo.
+struct ProlongOp {
+  int dst, src;
+  int lo[3], sz[3], foff[3], clo[3];
+};
+
+// Physical boundary ghosts written into storage: box [lo, lo+sz) of patch `patch`.
+struct PhysOp {
+  int patch, pad;
+  int lo[3], sz[3];
+};
+
+// Refluxing of coarse cells [lo, lo+sz) (coarse-local) of patch `coarse` across
+// the face (d, side) of fine patch `fine` (side 0: the fine patch's low face,
+// which is the high face of these coarse cells).  The fine face cells under
+// coarse cell x (coarse-local, other dimensions) start at fine-local 2 x + fo.
+struct FixOp {
+  int fine, coarse, d, side;
+  int lo[3], sz[3], fo[3];
+  int pad;
+};
+
+// Restriction of coarse cells [lo, lo+sz) (coarse-local) of `coarse` from `fine`:
+// the children of coarse-local x start at fine-local 2 x + fo.
+struct RestrictOp {
+  int fine, coarse;
+  int lo[3], sz[3], fo[3];
   int pad;
 };
 
@@ -196,6 +230,13 @@ __device__ __forceinline__ double minmod3(double a, double b, double c) {
   const double cc = __longlong_as_double((long long)((unsigned long long)__double_as_longlong(c) ^ sa));
   const double m = fmax(fmin(fabs(a), fmin(bb, cc)), 0.0);
   return __longlong_as_double((long long)((unsigned long long)__double_as_longlong(m) | sa));
+}
+
+// Two-argument minmod, the limiter of the coarse -> fine prolongation slopes.
+__device__ __forceinline__ double minmod2(double a, double b) {
+  if (a > 0 && b > 0) return a < b ? a : b;
+  if (a < 0 && b < 0) return a > b ? a : b;
+  return 0.0;
 }
 
 // PLM limited slope of the middle of three cells (Sec. 4 with theta):

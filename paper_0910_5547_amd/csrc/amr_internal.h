@@ -18,6 +18,7 @@ struct StageArgs {
   int pad;
   int* flag;                     // unphysical-state latch
   unsigned long long* smax;      // stage 2: per-level max signal speed of U^{n+1}, or nullptr
+  double* reg;                   // fine-face flux registers (+= dt/2 F on recorded faces), or nullptr
   Consts c;
 };
 
@@ -56,6 +57,18 @@ hipError_t launch_cfl_finalize(hipStream_t s, const unsigned long long* smax, in
 hipError_t launch_copy_ghosts(int grid, hipStream_t s, const CopyOp* ops, int nops, const PatchDev* p, double* A);
 hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, int n, unsigned long long v);
 hipError_t launch_fill_i32(hipStream_t s, int* p, int n, int v);
+
+hipError_t launch_prolong(int grid, hipStream_t s, const ProlongOp* ops, int nops, const PatchDev* p, double* A,
+                          const double* Cold, const double* Cnew, double alpha, int ndim);
+hipError_t launch_phys(int grid, hipStream_t s, const PhysOp* ops, int nops, const PatchDev* p, double* A);
+hipError_t launch_copy_ranges(hipStream_t s, const int64_t* ranges, int nr, int64_t maxlen, const double* src,
+                              double* dst);
+hipError_t launch_flux_fix(int mixed, int grid, hipStream_t s, const FixOp* ops, int nops, const PatchDev* p,
+                           double* U, const double* S1, const double* S2, const double* reg, const double* dtc,
+                           const Consts& C, int* flag);
+hipError_t launch_restrict(int grid, hipStream_t s, const RestrictOp* ops, int nops, const PatchDev* p, double* U,
+                           int ndim);
+hipError_t launch_scale_dt(hipStream_t s, const double* dt0, double* dtl, int nlev);
 
 // Compiled tile shapes (TX x TY lanes = 256); shape 0 is the 1D shape.
 constexpr int NSHAPES = 5;

@@ -108,6 +108,20 @@ void stage_kernel(StageArgs a) {
       }
       riemann_flux<RT, 2>(qL, qR, K, kind, Fzm);
     }
+    // fine-face flux registers (Berger-Colella refluxing): faces on this patch's
+    // boundary whose flux the coarse level must later see, dt/2 per stage
+    const double hdt = 0.5 * dt;
+    const bool rec = a.reg != nullptr && P.level > 0;
+    const bool rec_xy = rec && ((T.x0 == 0 && P.reg[0] >= 0) || (T.x0 + nxT == P.n[0] && P.reg[1] >= 0) ||
+                                (hasy && T.y0 == 0 && P.reg[2] >= 0) ||
+                                (hasy && T.y0 + nyT == P.n[1] && P.reg[3] >= 0));
+    if (hasz && act && rec && T.z0 == 0 && P.reg[4] >= 0) {
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) {
+        double* r = a.reg + P.reg[4] + ((int64_t)v * P.n[1] + j) * P.n[0] + i;
+        *r = *r + hdt * (double)Fzm[v];
+      }
+    }
 
     // Face halo of every plane: x halo = cols -2,-1,nxT,nxT+1 of every row, y halo =
     // rows -2,-1,nyT,nyT+1 of every column.  Lane tid owns halo cells tid + s*NT; their
@@ -235,6 +249,35 @@ void stage_kernel(StageArgs a) {
         riemann_flux_xy<RT>(qL, qR, w >= nfx, K, kind, F);
 #pragma unroll
         for (int v = 0; v < NVAR; ++v) sFL[v][w] = F[v];
+        if (rec_xy) {
+          int64_t base = -1, stride = 0;
+          // (constant indices into P: a runtime index would move P to scratch memory)
+          if (w < nfx) {
+            const int row = idiv(w, r_x1), f = w - row * (nxT + 1);
+            const int gi = T.x0 + f, gj = T.y0 + row;
+            const int64_t rg = gi == 0 ? P.reg[0] : (gi == P.n[0] ? P.reg[1] : -1);
+            if (rg >= 0) {
+              base = rg + (int64_t)k * P.n[1] + gj;
+              stride = (int64_t)P.n[2] * P.n[1];
+            }
+          } else {
+            const int w2 = w - nfx;
+            const int f = idiv(w2, r_x0), col = w2 - f * nxT;
+            const int gj = T.y0 + f, gi = T.x0 + col;
+            const int64_t rg = gj == 0 ? P.reg[2] : (gj == P.n[1] ? P.reg[3] : -1);
+            if (rg >= 0) {
+              base = rg + (int64_t)k * P.n[0] + gi;
+              stride = (int64_t)P.n[2] * P.n[0];
+            }
+          }
+          if (base >= 0) {
+#pragma unroll
+            for (int v = 0; v < NVAR; ++v) {
+              double* r = a.reg + base + v * stride;
+              *r = *r + hdt * (double)F[v];
+            }
+          }
+        }
       }
       // z-face flux F_{k+1/2} of this column from the register queue
       RT Fzp[NVAR], qn2[NVAR], sg1[NVAR];
@@ -248,6 +291,13 @@ void stage_kernel(StageArgs a) {
           qR[v] = madd(RT(-0.5), sg1[v], qz1[v]);
         }
         riemann_flux<RT, 2>(qL, qR, K, kind, Fzp);
+        if (rec && k == P.n[2] - 1 && P.reg[5] >= 0) {
+#pragma unroll
+          for (int v = 0; v < NVAR; ++v) {
+            double* r = a.reg + P.reg[5] + ((int64_t)v * P.n[1] + j) * P.n[0] + i;
+            *r = *r + hdt * (double)Fzp[v];
+          }
+        }
       }
       __syncthreads();  // (C) fluxes ready
 
@@ -367,6 +417,12 @@ __global__ __launch_bounds__(NT) void copy_ghosts(const CopyOp* __restrict__ ops
   }
 }
 
+// dt_l = dt0 / 2^l: factor-2 subcycling of a block-structured hierarchy.
+__global__ void scale_dt(const double* dt0, double* dtl, int nlev) {
+  const int l = threadIdx.x;
+  if (l < nlev) dtl[l] = ldexp(dt0[0], -l);
+}
+
 // Graph-safe clears (no memset nodes in captured work).
 __global__ void fill_u64(unsigned long long* p, int n, unsigned long long v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -443,6 +499,10 @@ hipError_t launch_copy_ghosts(int grid, hipStream_t s, const CopyOp* ops, int no
 }
 hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, int n, unsigned long long v) {
   hipLaunchKernelGGL(fill_u64, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_scale_dt(hipStream_t s, const double* dt0, double* dtl, int nlev) {
+  hipLaunchKernelGGL(scale_dt, dim3(1), dim3(64), 0, s, dt0, dtl, nlev);
   return hipGetLastError();
 }
 hipError_t launch_fill_i32(hipStream_t s, int* p, int n, int v) {

@@ -380,3 +380,60 @@ def composite_totals(ps, U):
                 mask[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = False
         tot += vol * np.array([math.fsum(a[k][mask].ravel()) for k in range(5)])
     return tot
+
+
+def nested_box(Nc=16, boxes=((4, 12), (12, 20)), ng=3, gamma=5.0 / 3.0, theta=1.0, seed=48, ndim=3, amp=0.2,
+               vamp=0.4):
+    """A periodic root box of Nc^ndim cells with a chain of nested refined patches.
+
+    boxes[i] = (lo, hi): level i+1 patch covering level-i cells [lo, hi) in every
+    active dimension (hi - lo even).  The state is a smooth periodic field given on
+    the finest grid of the whole domain; coarser cells are means of their children.
+    The root level is one patch with EXTERNAL faces (periodic root domain).
+    Returns (PatchSet, U, periodic_mask, domain).
+    """
+    nlev = len(boxes) + 1
+    Nf = Nc << (nlev - 1)
+    rng = np.random.default_rng(seed)
+    shape_f = tuple(Nf if d < ndim else 1 for d in (2, 1, 0))
+    xs = [(np.arange(Nf if d < ndim else 1) + 0.5) / Nf for d in range(3)]
+    Z, Y, X = np.meshgrid(xs[2], xs[1], xs[0], indexing="ij")
+
+    def field():
+        tot = np.zeros(shape_f)
+        for _ in range(3):
+            k = rng.integers(-2, 3, size=3)
+            k[ndim:] = 0
+            if not k.any():
+                k[0] = 1
+            tot += np.sin(2 * np.pi * (k[0] * X + k[1] * Y + k[2] * Z) + rng.uniform(0, 2 * np.pi))
+        return tot / 3.0
+
+    rho = 1.0 + amp * field()
+    vel = [vamp * field() if d < ndim else np.zeros(shape_f) for d in range(3)]
+    pr = 1.0 + amp * field()
+    fields = [conserved(rho, vel[0], vel[1], vel[2], pr, gamma)]  # finest first
+    for _ in range(nlev - 1):
+        Uc = fields[-1]
+        for ax in range(ndim):
+            axis = 3 - ax
+            s0 = [slice(None)] * 4
+            s1 = [slice(None)] * 4
+            s0[axis] = slice(0, None, 2)
+            s1[axis] = slice(1, None, 2)
+            Uc = Uc[tuple(s0)] + Uc[tuple(s1)]
+        fields.append(Uc / float(2 ** ndim))
+    fields = fields[::-1]  # level 0 first
+    los, ns, levels = [[0, 0, 0]], [[Nc if d < ndim else 1 for d in range(3)]], [0]
+    for i, (lo, hi) in enumerate(boxes):
+        los.append([2 * lo if d < ndim else 0 for d in range(3)])
+        ns.append([2 * (hi - lo) if d < ndim else 1 for d in range(3)])
+        levels.append(i + 1)
+    dx0 = tuple(1.0 / Nc if d < ndim else 1.0 for d in range(3))
+    ps = make_patchset(ndim, ns, ng, [BC_EXTERNAL] * 6, level=levels, lo=los, gamma=gamma, theta=theta, dx0=dx0)
+    U = new_arena(ps)
+    for p in range(ps.npatch):
+        lo, n = ps.lo[p], ps.n[p]
+        src = fields[int(ps.level[p])]
+        ps.active(U, p)[...] = src[:, lo[2]:lo[2] + n[2], lo[1]:lo[1] + n[1], lo[0]:lo[0] + n[0]]
+    return ps, U, (1 << ndim) - 1, tuple(Nc if d < ndim else 0 for d in range(3))

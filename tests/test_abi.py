@@ -39,7 +39,7 @@ def test_every_declared_entry_point_is_exported(amr):
                          check=True).stdout
     exported = set(re.findall(r" T (amr_\w+)", out))
     assert set(names) <= exported, set(names) - exported
-    assert set(names) == set(amr.EXPORTED)
+    assert set(names) == set(amr.EXPORTED), set(names) ^ set(amr.EXPORTED)
     for n in names:
         getattr(amr.lib(), n)
 
@@ -139,3 +139,19 @@ def test_workload_generators_are_seeded():
     assert np.array_equal(ps.n, ps2.n) and np.array_equal(U, U2, equal_nan=True)
     g = W.grf((16, 16, 16), 20, 1, 4)
     assert abs(g.mean()) < 1e-12 and abs(np.sqrt((g * g).mean()) - 1) < 1e-12
+
+
+def test_malformed_hierarchies_are_rejected(amr):
+    # a level-1 patch that starts on an odd fine index (not on a coarse cell boundary)
+    ps, U, per, dom = W.two_level_box(Nc=16, coarse_split=1)
+    descs = amr.descriptors(ps)
+    descs[1].lo[0] += 1
+    ph = amr.physics(ps, periodic=per, domain=dom)
+    h = C.c_void_p()
+    assert amr.lib().amr_patch_table_create(descs, len(descs), C.byref(ph), None, C.byref(h)) == amr.AMR_EINVAL
+    # a level-1 patch with no level-0 patch under its ghosts
+    ps = W.make_patchset(3, [[8, 8, 8], [8, 8, 8]], 2, [W.BC_EXTERNAL] * 6, level=[0, 1],
+                         lo=[[0, 0, 0], [40, 40, 40]])
+    descs = amr.descriptors(ps)
+    ph = amr.physics(ps, periodic=7, domain=(8, 8, 8))
+    assert amr.lib().amr_patch_table_create(descs, len(descs), C.byref(ph), None, C.byref(h)) == amr.AMR_EINVAL

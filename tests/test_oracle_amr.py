@@ -205,3 +205,13 @@ def test_prolongation_limiter_takes_the_smaller_difference(oracle_lib):
     expect = (i + 0.5) ** 2 + off * 2 * i
     for k in range(5):
         assert np.allclose(vals[k], fac[k] * expect, rtol=0, atol=1e-12), k
+
+
+def test_three_levels_conserve(oracle_lib):
+    ps, U, per, dom = W.nested_box(Nc=16, boxes=((4, 12), (10, 14)), seed=49)
+    t0 = W.composite_totals(ps, U)
+    scale = W.composite_totals(ps, np.abs(U))
+    _run(oracle_lib, ps, U, per, dom, 3)
+    t1 = W.composite_totals(ps, U)
+    live = scale > 0
+    assert np.all(np.abs(t1 - t0)[live] <= 1e-13 * scale[live])
