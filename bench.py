@@ -37,6 +37,77 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_traffic.json")
+COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read + 1 GiB written
+
+
+def kernel_source_sha():
+    """Hash of the HIP sources: a traffic measurement is only valid for the kernels it was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    cdir = os.path.join(ROOT, "paper_0910_5547_amd", "csrc")
+    for f in sorted(os.listdir(cdir)):
+        with open(os.path.join(cdir, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(workload, form, cells):
+    """Measured HBM bytes per stage launch (average of the two stages), or None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = t.get("entries", {}).get(f"{workload}/{form}")
+    if not e or e.get("kernel_source_sha") != kernel_source_sha() or e.get("cells") != cells:
+        return None
+    return e["hbm_bytes_per_launch"]
+
+
+def summarize_pmc(fetch_csv, write_csv, workload, form, cells):
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) into HBM
+    bytes per stage launch, each counter scaled by what it reads for the 1 GiB copy."""
+    import csv
+    import statistics
+
+    def per_kernel(path, counter):
+        vals = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return vals
+    fetch, write = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    copy_f = [v for k, vs in fetch.items() if "copy" in k.lower() or "elementwise" in k.lower() for v in vs]
+    copy_w = [v for k, vs in write.items() if "copy" in k.lower() or "elementwise" in k.lower() for v in vs]
+    big_f = max(copy_f)
+    big_w = max(copy_w)
+    sf = COPY_BYTES / (big_f * 1024.0)
+    sw = COPY_BYTES / (big_w * 1024.0)
+    out = {}
+    for k in fetch:
+        if "stage_kernel" not in k:
+            continue
+        f = statistics.median(fetch[k]) * 1024.0 * sf
+        w = statistics.median(write.get(k, [0.0])) * 1024.0 * sw
+        out[k] = {"fetch_bytes": f, "write_bytes": w}
+    per_launch = sum(v["fetch_bytes"] + v["write_bytes"] for v in out.values()) / max(1, len(out))
+    entry = {"kernel_source_sha": kernel_source_sha(), "cells": cells, "hbm_bytes_per_launch": per_launch,
+             "algorithmic_bytes_per_launch": BYTES_PER_CELL_STEP * cells / 2, "copy_scale_fetch": sf,
+             "copy_scale_write": sw, "kernels": out}
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        t = {"what": "HBM bytes per stage-kernel launch from rocprofv3 FETCH_SIZE/WRITE_SIZE, scaled by a 1 GiB copy",
+             "entries": {}}
+    t["entries"][f"{workload}/{form}"] = entry
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(t, fh, indent=1)
+    return entry
+
+
 def make_workload(name):
     from paper_0910_5547_amd import workloads as W
     if name == "box256":
@@ -140,7 +211,20 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="run the library's autotuner per form first (default: the library's default tiling)")
     ap.add_argument("--forms", default="plain_fp64,batched_fp64,batched_mixed")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 1 GiB device copy (counter calibration for --summarize-pmc)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the traffic summary from two rocprofv3 --pmc counter_collection CSVs and exit")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        from paper_0910_5547_amd import workloads as W
+        cells = {"box256": 256 ** 3}.get(args.workload)
+        if cells is None:
+            cells = make_workload(args.workload)[0].active_cells()
+        form = args.forms.split(",")[-1]
+        e = summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, form, cells)
+        print(json.dumps(e, indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding of the patch table is a design note, not built)", file=sys.stderr)
@@ -153,6 +237,13 @@ def main():
     torch.cuda.set_device(0)
     A.lib()
 
+    if args.calibrate_copy:
+        a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     t0 = time.time()
     ps, U, desc = make_workload(args.workload)
     cells = ps.active_cells()
@@ -196,7 +287,7 @@ def main():
         "forms": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"], "hbm_frac": v["hbm_frac_step"],
                       "stage_ms": v["stage_ms"], "tiling": v["tiling"]} for k, v in res.items()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_for(args.workload, main_form, cells),
                      "kernel": f"stage_kernel ({main_form}), 2 launches/step, {BYTES_STAGE[0]}+{BYTES_STAGE[1]} "
                                f"B/cell, avg {sum(stage_ms) / 2:.4f} ms/launch"},
     }

@@ -5,12 +5,12 @@
 // columns of one patch and marches it through the planes z0..z1-1 of its tile:
 //   * the z direction lives in registers: each lane keeps, for its own column,
 //     the primitives of planes z and z+1, the limited z-slope of plane z and the
-//     z-face flux F_{z-1/2}, and loads plane z+2 per step (so every cell of the
-//     column is read from HBM once per stage; the re-read of the cell for the
-//     update two planes later is served by L2);
+//     z-face flux F_{z-1/2}, and loads plane z+2 per step, so every cell of the
+//     column is read from HBM once per stage (its conserved state waits in a
+//     lane-private LDS ring until the update two planes later);
 //   * the x-y plane lives in LDS: the primitives of plane z for the block plus
-//     a 2-cell face halo (no corners: the MOL stencil is a cross, Sec. 4),
-//     double-buffered across planes.  Per plane: (1) every cell's limited
+//     a 2-cell face halo (no corners: the MOL stencil is a cross, Sec. 4).
+//     Per plane: (1) every cell's limited
 //     slope in x and y is computed once and turned into the two face states it
 //     contributes (q - sigma/2 on its low face, q + sigma/2 on its high face);
 //     (2) every x- and y-face flux of the block is computed once, by one lane,
@@ -35,7 +35,8 @@ namespace amr {
 
 // Occupancy target: three 256-lane workgroups per CU for the FP32-reconstruction
 // instantiations (<= 168 VGPRs), two for FP64 (LDS-bound at two per CU anyway).
-template <typename RT, int TX, int TY, int STAGE>
+// REC: record fine-face fluxes into the refluxing registers (patches of levels > 0).
+template <typename RT, int TX, int TY, int STAGE, bool REC>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Fast<RT>::value ? 3 : 2)))
 void stage_kernel(StageArgs a) {
   static_assert(TX * TY == NT, "one lane per column of the tile");
@@ -47,8 +48,13 @@ void stage_kernel(StageArgs a) {
   constexpr int HMAX = HASY ? (4 * (TX + TY) + NT - 1) / NT : 1;  // halo cells per lane
   // face slots: x faces first, slot row*(nxT+1) + f, then y faces, slot nfx + f*nxT + col
   constexpr int NSLOT = TY * (TX + 1) + (HASY ? YR * TX : 0);
-  __shared__ RT sP[2][NVAR][PR][TX + 4];        // primitives of the plane (+ face halo)
+  __shared__ RT sP[1][NVAR][PR][TX + 4];        // primitives of the plane (+ face halo)
   __shared__ RT sFL[NVAR][NSLOT], sFR[NVAR][NSLOT];  // left/right face states; sFL then holds the flux
+  // conserved state of this lane's cell in planes k and k+1 (3D), for the update:
+  // lane-private, kept in LDS rather than registers or a second read (FP32
+  // instantiations; the FP64 ones re-read the cell, their LDS budget being spent)
+  constexpr bool RING = FAST;
+  __shared__ double sV[RING ? 2 : 1][NVAR][RING ? NT : 1];
 
   const Consts C = a.c;
   const FaceConsts<RT> K{(RT)C.gamma, (RT)C.gm1, (RT)C.gg1};
@@ -59,7 +65,7 @@ void stage_kernel(StageArgs a) {
   const double dt = *a.dt;
   int bad = 0;
   double smax = 0.0;
-  int buf = 0;
+  constexpr int buf = 0;
 
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const Tile T = a.tiles[t];
@@ -96,8 +102,16 @@ void stage_kernel(StageArgs a) {
       bad |= cons2prim<RT>(u, C, qb);
       load_col(T.z0, u);
       bad |= cons2prim<RT>(u, C, qz);
+      if constexpr (RING) {
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) sV[T.z0 & 1][v][tid] = u[v];
+      }
       load_col(T.z0 + 1, u);
       bad |= cons2prim<RT>(u, C, qz1);
+      if constexpr (RING) {
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) sV[(T.z0 + 1) & 1][v][tid] = u[v];
+      }
       RT qL[NVAR], qR[NVAR];
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) {
@@ -111,11 +125,11 @@ void stage_kernel(StageArgs a) {
     // fine-face flux registers (Berger-Colella refluxing): faces on this patch's
     // boundary whose flux the coarse level must later see, dt/2 per stage
     const double hdt = 0.5 * dt;
-    const bool rec = a.reg != nullptr && P.level > 0;
+    const bool rec = REC && P.level > 0;
     const bool rec_xy = rec && ((T.x0 == 0 && P.reg[0] >= 0) || (T.x0 + nxT == P.n[0] && P.reg[1] >= 0) ||
                                 (hasy && T.y0 == 0 && P.reg[2] >= 0) ||
                                 (hasy && T.y0 + nyT == P.n[1] && P.reg[3] >= 0));
-    if (hasz && act && rec && T.z0 == 0 && P.reg[4] >= 0) {
+    if (REC && hasz && act && rec && T.z0 == 0 && P.reg[4] >= 0) {
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) {
         double* r = a.reg + P.reg[4] + ((int64_t)v * P.n[1] + j) * P.n[0] + i;
@@ -226,15 +240,20 @@ void stage_kernel(StageArgs a) {
       }
       __syncthreads();  // (B) face states ready
 
-      // the stage input and (stage 2) U^n of this cell, for the update: read here so
-      // the face pass hides the latency (the stage input was read two planes ago and
-      // is normally still in L2)
+      // the stage input (3D: from the lane's LDS ring; else re-read, just loaded) and
+      // (stage 2) U^n of this cell, for the update: read here so the face pass hides
+      // the latency
       double Vc[NVAR], U0c[NVAR];
       const int64_t ecell = col0 + (int64_t)k * pstride;
       if (act) {
         const int64_t e = ecell;
+        if (RING && hasz) {
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) Vc[v] = a.V[e + v * P.S];
+          for (int v = 0; v < NVAR; ++v) Vc[v] = sV[k & 1][v][tid];
+        } else {
+#pragma unroll
+          for (int v = 0; v < NVAR; ++v) Vc[v] = a.V[e + v * P.S];
+        }
         if (STAGE == 2) {
 #pragma unroll
           for (int v = 0; v < NVAR; ++v) U0c[v] = a.U0[e + v * P.S];
@@ -249,7 +268,7 @@ void stage_kernel(StageArgs a) {
         riemann_flux_xy<RT>(qL, qR, w >= nfx, K, kind, F);
 #pragma unroll
         for (int v = 0; v < NVAR; ++v) sFL[v][w] = F[v];
-        if (rec_xy) {
+        if (REC && rec_xy) {
           int64_t base = -1, stride = 0;
           // (constant indices into P: a runtime index would move P to scratch memory)
           if (w < nfx) {
@@ -291,7 +310,7 @@ void stage_kernel(StageArgs a) {
           qR[v] = madd(RT(-0.5), sg1[v], qz1[v]);
         }
         riemann_flux<RT, 2>(qL, qR, K, kind, Fzp);
-        if (rec && k == P.n[2] - 1 && P.reg[5] >= 0) {
+        if (REC && rec && k == P.n[2] - 1 && P.reg[5] >= 0) {
 #pragma unroll
           for (int v = 0; v < NVAR; ++v) {
             double* r = a.reg + P.reg[5] + ((int64_t)v * P.n[1] + j) * P.n[0] + i;
@@ -325,6 +344,7 @@ void stage_kernel(StageArgs a) {
             const double d = (double)Fzp[v] - (double)Fzm[v];
             if constexpr (FAST) L[v] = fma(-d, P.rdx[2], L[v]);
             else L[v] = L[v] - d / P.dx[2];
+            if constexpr (RING) sV[k & 1][v][tid] = Vn2[v];  // plane k+2 takes plane k's slot
             qz[v] = qz1[v];
             qz1[v] = qn2[v];
             sgz[v] = sg1[v];
@@ -344,7 +364,6 @@ void stage_kernel(StageArgs a) {
         }
         if (STAGE == 2 && a.smax != nullptr) smax = fmax(smax, cell_speed<FAST>(un, C, P, bad));
       }
-      buf ^= 1;
     }
     if (STAGE == 2 && a.smax != nullptr) {  // fused next-dt reduction, per level
       block_max_to(a.smax + P.level, smax);
@@ -434,21 +453,26 @@ __global__ void fill_i32(int* p, int n, int v) {
 }
 
 // ------------------------------------------------------------------ launchers
-template <typename RT, int TX, int TY>
-static hipError_t launch_stage_t(int stage, dim3 grid, hipStream_t s, const StageArgs& a) {
-  if (stage == 1) hipLaunchKernelGGL((stage_kernel<RT, TX, TY, 1>), grid, dim3(NT), 0, s, a);
-  else hipLaunchKernelGGL((stage_kernel<RT, TX, TY, 2>), grid, dim3(NT), 0, s, a);
+template <typename RT, int TX, int TY, int STAGE>
+static hipError_t launch_stage_t(dim3 grid, hipStream_t s, const StageArgs& a) {
+  if (a.reg) hipLaunchKernelGGL((stage_kernel<RT, TX, TY, STAGE, true>), grid, dim3(NT), 0, s, a);
+  else hipLaunchKernelGGL((stage_kernel<RT, TX, TY, STAGE, false>), grid, dim3(NT), 0, s, a);
   return hipGetLastError();
+}
+
+template <typename RT, int TX, int TY>
+static hipError_t launch_stage_s(int stage, dim3 grid, hipStream_t s, const StageArgs& a) {
+  return stage == 1 ? launch_stage_t<RT, TX, TY, 1>(grid, s, a) : launch_stage_t<RT, TX, TY, 2>(grid, s, a);
 }
 
 template <typename RT>
 static hipError_t launch_stage_rt(int shape, int stage, dim3 grid, hipStream_t s, const StageArgs& a) {
   switch (shape) {
-    case 0: return launch_stage_t<RT, 256, 1>(stage, grid, s, a);
-    case 1: return launch_stage_t<RT, 32, 8>(stage, grid, s, a);
-    case 2: return launch_stage_t<RT, 64, 4>(stage, grid, s, a);
-    case 3: return launch_stage_t<RT, 16, 16>(stage, grid, s, a);
-    case 4: return launch_stage_t<RT, 128, 2>(stage, grid, s, a);
+    case 0: return launch_stage_s<RT, 256, 1>(stage, grid, s, a);
+    case 1: return launch_stage_s<RT, 32, 8>(stage, grid, s, a);
+    case 2: return launch_stage_s<RT, 64, 4>(stage, grid, s, a);
+    case 3: return launch_stage_s<RT, 16, 16>(stage, grid, s, a);
+    case 4: return launch_stage_s<RT, 128, 2>(stage, grid, s, a);
     default: return hipErrorInvalidValue;
   }
 }
@@ -458,10 +482,11 @@ hipError_t launch_stage(int mixed, int shape, int stage, int grid, hipStream_t s
   return launch_stage_rt<double>(shape, stage, dim3(grid), s, a);
 }
 
+// The non-recording instantiation (the occupancy of both is the same resource class).
 const void* stage_kernel_ptr(int mixed, int shape, int stage) {
 #define AMR_KP(RT, TX, TY)                                                                          \
-  (stage == 1 ? reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, 1>)                         \
-              : reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, 2>))
+  (stage == 1 ? reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, 1, false>)                  \
+              : reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, 2, false>))
   if (mixed) {
     switch (shape) {
       case 0: return AMR_KP(float, 256, 1);
