@@ -219,13 +219,12 @@ class AmrOracle:
         return rec[base:base + size].reshape(5, n[b], n[a], n[d] + 1)
 
     def _patch_at(self, level, C3):
-        ps = self.ps
-        for q in range(ps.npatch):
-            if ps.level[q] != level:
-                continue
-            if all(ps.lo[q, e] <= C3[e] < ps.lo[q, e] + ps.n[q, e] for e in range(ps.ndim)):
-                return q
-        return -1
+        """The patch of `level` whose active box holds cell C3, or -1."""
+        ps, nd = self.ps, self.ps.ndim
+        c = np.asarray(C3[:nd])
+        inside = (ps.level == level) & np.all((ps.lo[:, :nd] <= c) & (c < ps.lo[:, :nd] + ps.n[:, :nd]), axis=1)
+        hits = np.nonzero(inside)[0]
+        return int(hits[0]) if len(hits) else -1
 
     def _wrap(self, level, e, x):
         if (self.periodic >> e) & 1:
@@ -235,13 +234,10 @@ class AmrOracle:
 
     def _covered(self, level, C3):
         """True if coarse cell C3 (level) lies under a patch of level + 1."""
-        ps = self.ps
-        for q in range(ps.npatch):
-            if ps.level[q] != level + 1:
-                continue
-            if all(ps.lo[q, e] <= 2 * C3[e] < ps.lo[q, e] + ps.n[q, e] for e in range(ps.ndim)):
-                return True
-        return False
+        ps, nd = self.ps, self.ps.ndim
+        c = 2 * np.asarray(C3[:nd])
+        inside = (ps.level == level + 1) & np.all((ps.lo[:, :nd] <= c) & (c < ps.lo[:, :nd] + ps.n[:, :nd]), axis=1)
+        return bool(inside.any())
 
     def correct(self, U, l):
         """Berger-Colella refluxing of level l against its children."""

@@ -365,19 +365,24 @@ def composite_totals(ps, U):
     by a finer patch), each cell weighted by its volume."""
     nd = ps.ndim
     tot = np.zeros(5)
+    lo = ps.lo.astype(np.int64)
+    hi = lo + ps.n.astype(np.int64)
     for p in range(ps.npatch):
         l = int(ps.level[p])
         vol = np.prod([ps.dx0[d] / 2 ** l for d in range(nd)])
-        a = ps.active(U, p).copy()
+        a = ps.active(U, p)
         mask = np.ones(a.shape[1:], bool)
-        for q in range(ps.npatch):
-            if ps.level[q] != l + 1:
-                continue
-            lo = [max(int(ps.lo[q, d]) // 2, int(ps.lo[p, d])) - int(ps.lo[p, d]) if d < nd else 0 for d in range(3)]
-            hi = [min((int(ps.lo[q, d]) + int(ps.n[q, d])) // 2, int(ps.lo[p, d]) + int(ps.n[p, d])) - int(ps.lo[p, d])
-                  if d < nd else 1 for d in range(3)]
-            if all(hi[d] > lo[d] for d in range(3)):
-                mask[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = False
+        fine = np.nonzero(ps.level == l + 1)[0]
+        if len(fine):
+            flo = lo[fine] // 2
+            fhi = hi[fine] // 2
+            olo = np.maximum(flo, lo[p])
+            ohi = np.minimum(fhi, hi[p])
+            hit = np.all((ohi[:, :nd] > olo[:, :nd]), axis=1)
+            for q in np.nonzero(hit)[0]:
+                sl = [slice(int(olo[q, d] - lo[p, d]), int(ohi[q, d] - lo[p, d])) if d < nd else slice(None)
+                      for d in range(3)]
+                mask[sl[2], sl[1], sl[0]] = False
         tot += vol * np.array([math.fsum(a[k][mask].ravel()) for k in range(5)])
     return tot
 
@@ -437,3 +442,238 @@ def nested_box(Nc=16, boxes=((4, 12), (12, 20)), ng=3, gamma=5.0 / 3.0, theta=1.
         src = fields[int(ps.level[p])]
         ps.active(U, p)[...] = src[:, lo[2]:lo[2] + n[2], lo[1]:lo[1] + n[1], lo[0]:lo[0] + n[0]]
     return ps, U, (1 << ndim) - 1, tuple(Nc if d < ndim else 0 for d in range(3))
+
+
+# ---------------------------------------------------------------- Sedov-Taylor blast
+class SedovSolution:
+    """Self-similar point explosion in a uniform gas (Sedov 1959), spherical.
+
+    Parametric closed form in the similarity variable V (velocity v = 2 r V / (5 t)),
+    running from V = 2/(gamma+1) at the shock (xi = r/R = 1) to V -> 1/gamma at
+    the centre:
+      xi^5 = [(g+1)V/2]^-2 [(g+1)(5-(3g-1)V)/(7-g)]^n1 [(g+1)(gV-1)/(g-1)]^n2
+      rho/rho1 = (g+1)/(g-1) [(g+1)(gV-1)/(g-1)]^n3 [(g+1)(5-(3g-1)V)/(7-g)]^n4
+                 [(g+1)(1-V)/(g-1)]^n5
+      c^2 = (4 r^2 / 25 t^2) g (g-1) (1-V) V^2 / (2 (gV-1)),  p = rho c^2 / g
+    with n1 = -(13g^2-7g+12)/((3g-1)(2g+1)), n2 = 5(g-1)/(2g+1), n3 = 3/(2g+1),
+    n4 = -n1/(2-g), n5 = -2/(2-g).  The shock radius is R = xi0 (E t^2/rho1)^(1/5)
+    with xi0^5 = 25 / (16 pi I), I = int_0^1 (rho/rho1) xi^4 (V^2/2 + Z/(g(g-1))) dxi.
+    """
+
+    def __init__(self, gamma=5.0 / 3.0, npts=40000):
+        g = gamma
+        self.gamma = g
+        n1 = -(13 * g * g - 7 * g + 12) / ((3 * g - 1) * (2 * g + 1))
+        n2 = 5 * (g - 1) / (2 * g + 1)
+        n3 = 3 / (2 * g + 1)
+        n4 = -n1 / (2 - g)
+        n5 = -2 / (2 - g)
+        Vs, Vc = 2 / (g + 1), 1 / g
+        u = np.linspace(0.0, 1.0, npts + 1)[1:]
+        V = Vc + (Vs - Vc) * np.maximum(u ** 6, 1e-12)  # dense towards the centre (V > 1/gamma)
+        a = (g + 1) * V / 2
+        b = (g + 1) * (5 - (3 * g - 1) * V) / (7 - g)
+        c = (g + 1) * (g * V - 1) / (g - 1)
+        d = (g + 1) * (1 - V) / (g - 1)
+        xi = (a ** -2 * b ** n1 * c ** n2) ** 0.2
+        G = (g + 1) / (g - 1) * c ** n3 * b ** n4 * d ** n5
+        Z = g * (g - 1) * (1 - V) * V * V / (2 * (g * V - 1))
+        order = np.argsort(xi)
+        self.xi, self.G, self.V, self.Z = xi[order], G[order], V[order], Z[order]
+        f = self.G * self.xi ** 4 * (self.V ** 2 / 2 + self.Z / (g * (g - 1)))
+        xs = np.concatenate([[0.0], self.xi])
+        fs = np.concatenate([[0.0], f])
+        self.I = float(np.trapezoid(fs, xs))
+        self.xi0 = (25.0 / (16.0 * np.pi * self.I)) ** 0.2
+
+    def radius(self, E, t, rho1=1.0):
+        return self.xi0 * (E * t * t / rho1) ** 0.2
+
+    def state(self, r, E, t, rho1=1.0, p1=1e-5, rho_floor=0.0):
+        """(rho, radial velocity, p) at radii r (array), ambient outside the shock."""
+        R = self.radius(E, t, rho1)
+        r = np.asarray(r, np.float64)
+        xi = r / R
+        inside = xi < 1.0
+        xq = np.clip(xi, self.xi[0], 1.0)
+        G = np.interp(xq, self.xi, self.G)
+        V = np.interp(xq, self.xi, self.V)
+        Z = np.interp(xq, self.xi, self.Z)
+        rho = np.where(inside, rho1 * G, rho1)
+        vel = np.where(inside, 2 * r / (5 * t) * V, 0.0)
+        c2 = 4 * r * r / (25 * t * t) * Z
+        p = np.where(inside, np.maximum(rho1 * G * c2 / self.gamma, p1), p1)
+        if rho_floor > 0:
+            rho = np.maximum(rho, rho_floor)
+        return rho, vel, p
+
+
+# Floors on recovered primitives for the Sedov set-up (ambient specific internal energy is
+# 1.5e-5).  A fixed hierarchy lets the Mach > 1000 shock cross coarse/fine interfaces,
+# where prolongation and refluxing can leave a cell with negative internal energy; the
+# floor keeps the wave speeds and fluxes of such a cell defined, as pressure floors do
+# in production AMR codes.  Floors never modify U.
+SEDOV_FLOORS = dict(rho_floor=1e-6, e_floor=1e-9)
+
+
+def sedov_hierarchy(root=64, levels=6, t=0.05, E_octant=1.0, gamma=5.0 / 3.0, eps=0.3, ng=3, rho_floor=1e-2,
+                    p1=1e-5, block=32, brick=8, samples=2, with_state=True):
+    """Octant Sedov blast on [0,1]^3 (blast at the corner origin), root^3 cells plus
+    `levels` levels of factor-2 refinement placed by a density-gradient criterion on
+    the analytic profile at time t (E = E_octant in the octant, i.e. 8 E_octant in the
+    full sphere; rho = 1, p = p1 ambient; density floored at rho_floor).
+
+    Level l+1 is built from level l: a covered level-l cell is flagged where the
+    largest relative density jump to a face neighbour, |d rho| / min rho, exceeds
+    eps; fine 8^3 bricks holding children of flagged cells (dilated by one cell) are
+    kept if their footprint, dilated by one coarse cell, is covered by level l (proper
+    nesting: ghost cells and their prolongation stencils stay on level l).  Kept
+    bricks are grouped into aligned 32^3 blocks; a block's patch is the bounding box
+    of its bricks (8..32 cells per dimension), split into 16^3 sub-blocks or single
+    bricks where the box would break the nesting.  Faces on x=0, y=0, z=0 reflect,
+    far faces are outflow, faces between patches are EXTERNAL.
+    Returns (PatchSet, U or None, periodic=0, domain).
+    """
+    sol = SedovSolution(gamma)
+    E = 8.0 * E_octant
+
+    def rho_at(x, y, z):
+        r = np.sqrt(x * x + y * y + z * z)
+        return sol.state(r, E, t, 1.0, p1, rho_floor)[0]
+
+    def nested(cov, lo, hi, N):
+        """Fine box [lo, hi) of level l+1 (cells): its footprint dilated by one coarse cell,
+        clipped to the domain, lies in level-l coverage (a set of level-l bricks)."""
+        clo = [max(lo[d] // 2 - 1, 0) for d in range(3)]
+        chi = [min((hi[d] + 1) // 2 + 1, N) for d in range(3)]
+        for bk in range(clo[2] // brick, (chi[2] - 1) // brick + 1):
+            for bj in range(clo[1] // brick, (chi[1] - 1) // brick + 1):
+                for bi in range(clo[0] // brick, (chi[0] - 1) // brick + 1):
+                    if (bi, bj, bk) not in cov:
+                        return False
+        return True
+
+    nb_root = root // brick
+    bricks = [set((i, j, k) for i in range(nb_root) for j in range(nb_root) for k in range(nb_root))]
+    boxes = [[((0, 0, 0), (root, root, root))]]
+    per = block // brick
+    for l in range(levels):
+        N = root << l
+        dx = 1.0 / N
+        cov = bricks[l]
+        cand = set()
+        for (bi, bj, bk) in cov:
+            ii = (np.arange(-1, brick + 1) + bi * brick + 0.5) * dx
+            jj = (np.arange(-1, brick + 1) + bj * brick + 0.5) * dx
+            kk = (np.arange(-1, brick + 1) + bk * brick + 0.5) * dx
+            Zc, Yc, Xc = np.meshgrid(kk, jj, ii, indexing="ij")
+            rho = rho_at(Xc, Yc, Zc)
+            c = rho[1:-1, 1:-1, 1:-1]
+            jump = np.zeros_like(c)
+            for sl in ((slice(2, None), slice(1, -1), slice(1, -1)), (slice(0, -2), slice(1, -1), slice(1, -1)),
+                       (slice(1, -1), slice(2, None), slice(1, -1)), (slice(1, -1), slice(0, -2), slice(1, -1)),
+                       (slice(1, -1), slice(1, -1), slice(2, None)), (slice(1, -1), slice(1, -1), slice(0, -2))):
+                nbv = rho[sl]
+                jump = np.maximum(jump, np.abs(nbv - c) / np.minimum(nbv, c))
+            fk, fj, fi = np.nonzero(jump > eps)
+            if len(fi) == 0:
+                continue
+            ci = np.concatenate([fi + d for d in (-1, 0, 1)]) + bi * brick
+            cj = np.concatenate([fj + d for d in (-1, 0, 1)]) + bj * brick
+            ck = np.concatenate([fk + d for d in (-1, 0, 1)]) + bk * brick
+            for a in range(3):  # dilation by one cell along each axis (cross), then to fine bricks
+                arrs = [fi + bi * brick, fj + bj * brick, fk + bk * brick]
+                for dd in (-1, 0, 1):
+                    q = [x.copy() for x in arrs]
+                    q[a] = q[a] + dd
+                    ok = (q[0] >= 0) & (q[1] >= 0) & (q[2] >= 0) & (q[0] < N) & (q[1] < N) & (q[2] < N)
+                    for x, y, z in zip(q[0][ok], q[1][ok], q[2][ok]):
+                        cand.add(((2 * x) // brick, (2 * y) // brick, (2 * z) // brick))
+            del ci, cj, ck
+        Nf = N * 2
+        keep = set(b for b in cand
+                   if nested(cov, [b[d] * brick for d in range(3)], [(b[d] + 1) * brick for d in range(3)], N))
+        # patches of level l+1
+        groups = {}
+        for b in keep:
+            groups.setdefault((b[0] // per, b[1] // per, b[2] // per), []).append(b)
+        lvl_boxes, lvl_bricks = [], set()
+
+        def emit(bs):
+            arr = np.array(bs)
+            lo = tuple(int(x) for x in arr.min(axis=0) * brick)
+            hi = tuple(int(x) for x in (arr.max(axis=0) + 1) * brick)
+            if nested(cov, lo, hi, N):
+                lvl_boxes.append((lo, hi))
+                for bk in range(lo[2] // brick, hi[2] // brick):
+                    for bj in range(lo[1] // brick, hi[1] // brick):
+                        for bi in range(lo[0] // brick, hi[0] // brick):
+                            lvl_bricks.add((bi, bj, bk))
+                return True
+            return False
+
+        for key in sorted(groups):
+            bs = groups[key]
+            if emit(bs):
+                continue
+            sub = {}
+            for b in bs:
+                sub.setdefault(tuple((b[d] % per) // (per // 2) for d in range(3)), []).append(b)
+            for sk in sorted(sub):
+                if not emit(sub[sk]):
+                    for b in sorted(sub[sk]):
+                        emit([b])
+        if not lvl_boxes:
+            break
+        del Nf
+        bricks.append(lvl_bricks)
+        boxes.append(sorted(lvl_boxes))
+    # root patches: 2x2x2 blocks of (root/2)^3
+    h = root // 2
+    los, ns, lvls = [], [], []
+    for k in range(2):
+        for j in range(2):
+            for i in range(2):
+                los.append([i * h, j * h, k * h])
+                ns.append([h, h, h])
+                lvls.append(0)
+    for l in range(1, len(boxes)):
+        for lo, hi in boxes[l]:
+            los.append(list(lo))
+            ns.append([hi[d] - lo[d] for d in range(3)])
+            lvls.append(l)
+    los = np.array(los, np.int32)
+    ns = np.array(ns, np.int32)
+    lvls = np.array(lvls, np.int32)
+    bcs = np.full((len(lvls), 6), BC_EXTERNAL, np.int32)
+    for p in range(len(lvls)):
+        N = root << int(lvls[p])
+        for d in range(3):
+            if los[p, d] == 0:
+                bcs[p, 2 * d] = BC_REFLECT
+            if los[p, d] + ns[p, d] == N:
+                bcs[p, 2 * d + 1] = BC_OUTFLOW
+    ps = make_patchset(3, ns, ng, bcs, level=lvls, lo=los, gamma=gamma, theta=1.0, dx0=(1.0 / root,) * 3)
+    if not with_state:
+        return ps, None, 0, (root, root, root)
+    U = new_arena(ps)
+    offs = (np.arange(samples) + 0.5) / samples - 0.5
+    for p in range(ps.npatch):
+        l = int(ps.level[p])
+        dx = 1.0 / (root << l)
+        n = ps.n[p]
+        lo = ps.lo[p]
+        acc = np.zeros((5, n[2], n[1], n[0]))
+        for oz in offs:
+            for oy in offs:
+                for ox in offs:
+                    x = (lo[0] + np.arange(n[0]) + 0.5 + ox) * dx
+                    y = (lo[1] + np.arange(n[1]) + 0.5 + oy) * dx
+                    z = (lo[2] + np.arange(n[2]) + 0.5 + oz) * dx
+                    Zc, Yc, Xc = np.meshgrid(z, y, x, indexing="ij")
+                    r = np.sqrt(Xc * Xc + Yc * Yc + Zc * Zc)
+                    rho, vr, pr = sol.state(r, E, t, 1.0, p1, rho_floor)
+                    rs = np.maximum(r, 1e-300)
+                    acc += conserved(rho, vr * Xc / rs, vr * Yc / rs, vr * Zc / rs, pr, gamma)
+        ps.active(U, p)[...] = acc / samples ** 3
+    return ps, U, 0, (root, root, root)
