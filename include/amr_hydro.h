@@ -159,7 +159,16 @@ amr_status amr_cfl_dt(amr_table* table, const double* U, double cfl, int32_t lev
  * U^{n+1} = U^n/2 + (U^(1) + dt L(U^(1)))/2 written over U^n.  dt is read from
  * dt_dev[0] on the device when the step runs (so a captured step replays with
  * new values).  EXTERNAL ghosts of the stage input are filled before each
- * stage.  flags: AMR_STEP_*.  Asynchronous. */
+ * stage.  flags: AMR_STEP_*.  Asynchronous.
+ * Tables with several levels: `level` must name one level (-1 and
+ * AMR_STEP_FUSE_DT give AMR_EINVAL).  Such a step is one node of the subcycled
+ * recursion amr_hydro_advance runs: the patches of a level > 0 record their
+ * coarse/fine face fluxes into the flux registers, a level with children keeps
+ * U^n as the snapshot its children's ghosts interpolate from and clears their
+ * registers, and AMR_STEP_SUBSTEP1 marks the second of a parent step's two
+ * substeps.  A driver of its own calls, for level l: this step, then (if l has
+ * children) the same recursion for l+1 twice (the second with
+ * AMR_STEP_SUBSTEP1), then amr_flux_correct(l); dt_dev[0] = dt0 / 2^l. */
 amr_status amr_hydro_rk2_step(amr_table* table, double* U, const double* dt_dev, int32_t level, uint32_t flags,
                               hipStream_t stream);
 

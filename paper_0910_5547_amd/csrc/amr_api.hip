@@ -39,6 +39,11 @@ struct GraphCache {
   uint32_t flags = 0;
 };
 
+// A work list: its workgroups' segment ranges start at blk_d + blk_base.
+struct WorkList {
+  int blk_base = 0, nblk = 0;
+};
+
 }  // namespace
 
 struct amr_table {
@@ -87,6 +92,12 @@ struct amr_table {
   std::vector<int64_t> snap_maxlen;
   std::vector<const double*> last_dt;           // dt pointer of each level's last step
   GraphCache gadv;                              // captured root step (batched form)
+  // cell-granular work lists of the box-op kernels (see Seg): per level, and for
+  // the refluxing ops per coarse level and colour
+  Seg* segs_d = nullptr;
+  int* blk_d = nullptr;
+  std::vector<WorkList> w_copy, w_prol, w_phys, w_rst;
+  std::vector<std::vector<WorkList>> w_fix;
 };
 
 #define HIPCHECK(x)                                     \
@@ -249,24 +260,16 @@ int occupancy_grid(amr_table* t, int stage, int ntiles) {
 // Enqueue the EXTERNAL ghost fill of arena A for the patches of `level`: sibling
 // copies, then (levels > 0) prolongation from the coarse level interpolated in time
 // between its snapshot and its state in U at fraction alpha.
+Work work_of(const amr_table* t, const WorkList& w) { return Work{t->segs_d, t->blk_d + w.blk_base, w.nblk, 0}; }
+
 amr_status enqueue_ghosts(amr_table* t, double* A, const double* U, int level, double alpha, hipStream_t s) {
-  if (t->nops > 0) {
-    int first, count;
-    if (level < 0) {
-      first = 0;
-      count = t->nops;
-    } else {
-      first = t->ops_level_first[level];
-      count = t->ops_level_count[level];
-    }
-    if (count > 0)
-      HIPCHECK(launch_copy_ghosts(std::min(count, 8 * t->ncu), s, t->ops_d + first, count, t->pdev_d, A));
-  }
-  if (level > 0 && t->prol_count[level] > 0) {
-    const int first = t->prol_first[level], count = t->prol_count[level];
-    HIPCHECK(launch_prolong(std::min(count, 8 * t->ncu), s, t->prol_d + first, count, t->pdev_d, A, t->snap, U, alpha,
-                            t->ph.ndim));
-  }
+  const int l0 = level < 0 ? 0 : level, l1 = level < 0 ? t->max_level : level;
+  for (int l = l0; l <= l1; ++l)
+    if (t->w_copy[l].nblk > 0)
+      HIPCHECK(launch_copy_ghosts(s, t->ops_d + t->ops_level_first[l], work_of(t, t->w_copy[l]), t->pdev_d, A));
+  if (level > 0 && t->w_prol[level].nblk > 0)
+    HIPCHECK(launch_prolong(s, t->prol_d + t->prol_first[level], work_of(t, t->w_prol[level]), t->pdev_d, A, t->snap,
+                            U, alpha, t->ph.ndim));
   return AMR_OK;
 }
 
@@ -320,9 +323,8 @@ amr_status enqueue_step(amr_table* t, double* U, const double* dt, int level, ui
   st = enqueue_ghosts(t, U, U, level, a1, s);
   if (st != AMR_OK) return st;
   if (kids) {
-    if (t->phys_count[level] > 0)
-      HIPCHECK(launch_phys(std::min(t->phys_count[level], 8 * t->ncu), s, t->phys_d + t->phys_first[level],
-                           t->phys_count[level], t->pdev_d, U));
+    if (t->w_phys[level].nblk > 0)
+      HIPCHECK(launch_phys(s, t->phys_d + t->phys_first[level], work_of(t, t->w_phys[level]), t->pdev_d, U));
     HIPCHECK(launch_copy_ranges(s, t->snap_d + 2 * t->snap_first[level], t->snap_count[level],
                                 t->snap_maxlen[level], U, t->snap));
   }
@@ -338,9 +340,8 @@ amr_status enqueue_step(amr_table* t, double* U, const double* dt, int level, ui
   if (kids) {
     st = enqueue_ghosts(t, U, U, level, a2, s);
     if (st != AMR_OK) return st;
-    if (t->phys_count[level] > 0)
-      HIPCHECK(launch_phys(std::min(t->phys_count[level], 8 * t->ncu), s, t->phys_d + t->phys_first[level],
-                           t->phys_count[level], t->pdev_d, U));
+    if (t->w_phys[level].nblk > 0)
+      HIPCHECK(launch_phys(s, t->phys_d + t->phys_first[level], work_of(t, t->w_phys[level]), t->pdev_d, U));
     const int64_t len = t->reg_len[level + 1];
     if (len > 0) {
       for (int64_t o = 0; o < len; o += (int64_t)1 << 30)
@@ -355,13 +356,12 @@ amr_status enqueue_step(amr_table* t, double* U, const double* dt, int level, ui
 // Refluxing of `l` against level l+1, then restriction of the covered cells.
 amr_status enqueue_correct(amr_table* t, double* U, int l, hipStream_t s) {
   const int mixed = t->ph.precision == AMR_PREC_MIXED;
-  for (const auto& fc : t->fix_colors[l])
-    if (fc.second > 0)
-      HIPCHECK(launch_flux_fix(mixed, std::min(fc.second, 8 * t->ncu), s, t->fix_d + fc.first, fc.second, t->pdev_d,
+  for (size_t c = 0; c < t->fix_colors[l].size(); ++c)
+    if (t->w_fix[l][c].nblk > 0)
+      HIPCHECK(launch_flux_fix(mixed, s, t->fix_d + t->fix_colors[l][c].first, work_of(t, t->w_fix[l][c]), t->pdev_d,
                                U, t->snap, t->U1, t->reg, t->last_dt[l], consts_of(t), t->flag_d));
-  if (t->rst_count[l] > 0)
-    HIPCHECK(launch_restrict(std::min(t->rst_count[l], 8 * t->ncu), s, t->rst_d + t->rst_first[l], t->rst_count[l],
-                             t->pdev_d, U, t->ph.ndim));
+  if (t->w_rst[l].nblk > 0)
+    HIPCHECK(launch_restrict(s, t->rst_d + t->rst_first[l], work_of(t, t->w_rst[l]), t->pdev_d, U, t->ph.ndim));
   return AMR_OK;
 }
 
@@ -434,6 +434,62 @@ amr_status validate(const amr_patch_desc* P, int32_t np, const amr_physics* ph) 
 // from the same-level patch that holds it as an active cell (periodic root domain
 // wrap applied) or, on levels > 0, prolonged from the level-1 patch holding its
 // coarse cell.  Fails with AMR_EINVAL if a ghost cell has no source.
+// Disjoint boxes covering the marked cells of an n[0] x n[1] x n[2] mask (x
+// fastest), greedily: from the first marked cell grow along x, then y, then z
+// while every cell of the grown box is marked; emit(lo, sz) per box.
+template <class Emit>
+void cover_boxes(const int n[3], std::vector<char>& m, Emit emit) {
+  auto at = [&](int x, int y, int z) -> char& { return m[((size_t)z * n[1] + y) * n[0] + x]; };
+  for (int z = 0; z < n[2]; ++z)
+    for (int y = 0; y < n[1]; ++y)
+      for (int x = 0; x < n[0]; ++x) {
+        if (!at(x, y, z)) continue;
+        int x1 = x;
+        while (x1 < n[0] && at(x1, y, z)) ++x1;
+        int y1 = y + 1;
+        for (; y1 < n[1]; ++y1) {
+          bool ok = true;
+          for (int i = x; i < x1 && ok; ++i) ok = at(i, y1, z) != 0;
+          if (!ok) break;
+        }
+        int z1 = z + 1;
+        for (; z1 < n[2]; ++z1) {
+          bool ok = true;
+          for (int j = y; j < y1 && ok; ++j)
+            for (int i = x; i < x1 && ok; ++i) ok = at(i, j, z1) != 0;
+          if (!ok) break;
+        }
+        for (int k = z; k < z1; ++k)
+          for (int j = y; j < y1; ++j)
+            for (int i = x; i < x1; ++i) at(i, j, k) = 0;
+        const int lo[3] = {x, y, z}, sz[3] = {x1 - x, y1 - y, z1 - z};
+        emit(lo, sz);
+      }
+}
+
+// Cell-granular work list of ops[0..count) (boxes of sz cells), appended to the
+// table-wide segment and workgroup arrays.
+template <class Op>
+WorkList add_work(std::vector<Seg>& segs, std::vector<int>& blk, const Op* ops, int count) {
+  WorkList w;
+  w.blk_base = (int)blk.size();
+  int64_t cum = 0;
+  for (int i = 0; i < count; ++i) {
+    const int64_t n = (int64_t)ops[i].sz[0] * ops[i].sz[1] * ops[i].sz[2];
+    for (int64_t c = 0; c < n;) {
+      const int lane0 = (int)(cum % NT);
+      if (lane0 == 0) blk.push_back((int)segs.size());  // first segment of a new workgroup
+      const int take = (int)std::min<int64_t>(n - c, NT - lane0);
+      segs.push_back(Seg{i, (int)c, lane0, take});
+      c += take;
+      cum += take;
+    }
+  }
+  w.nblk = (int)((cum + NT - 1) / NT);
+  blk.push_back((int)segs.size());  // end of the last workgroup's segments
+  return w;
+}
+
 amr_status build_ghost_plan(amr_table* t, std::vector<CopyOp>& ops, std::vector<ProlongOp>& pops) {
   const int nd = t->ph.ndim;
   const int np = (int)t->desc.size();
@@ -520,39 +576,27 @@ amr_status build_ghost_plan(amr_table* t, std::vector<CopyOp>& ops, std::vector<
               isz[e] = hi - lo;
             }
             if (empty) continue;
-            // rows (x runs) of cells not held by a sibling
+            // boxes of the cells not held by a sibling
+            std::vector<char> need((size_t)isz[0] * isz[1] * isz[2]);
             for (int k = 0; k < isz[2]; ++k)
-              for (int j = 0; j < isz[1]; ++j) {
-                int i = 0;
-                while (i < isz[0]) {
-                  auto covered = [&](int ii) {
-                    const int x = ilo[0] + ii - blo[0], y = ilo[1] + j - blo[1], z = ilo[2] + k - blo[2];
-                    return cov[((size_t)z * bsz[1] + y) * bsz[0] + x] != 0;
-                  };
-                  if (covered(i)) {
-                    ++i;
-                    continue;
-                  }
-                  int i1 = i;
-                  while (i1 < isz[0] && !covered(i1)) ++i1;
-                  ProlongOp op{};
-                  op.dst = p;
-                  op.src = q;
-                  op.lo[0] = ilo[0] + i;
-                  op.lo[1] = ilo[1] + j;
-                  op.lo[2] = ilo[2] + k;
-                  op.sz[0] = i1 - i;
-                  op.sz[1] = 1;
-                  op.sz[2] = 1;
-                  for (int e = 0; e < 3; ++e) {
-                    op.foff[e] = e < nd ? D.lo[e] + wrap[e] : 0;
-                    op.clo[e] = e < nd ? Q.lo[e] : 0;
-                  }
-                  pops.push_back(op);
-                  mark(op.lo, op.sz);
-                  i = i1;
+              for (int j = 0; j < isz[1]; ++j)
+                for (int i = 0; i < isz[0]; ++i) {
+                  const int x = ilo[0] + i - blo[0], y = ilo[1] + j - blo[1], z = ilo[2] + k - blo[2];
+                  need[((size_t)k * isz[1] + j) * isz[0] + i] = cov[((size_t)z * bsz[1] + y) * bsz[0] + x] == 0;
                 }
+            cover_boxes(isz, need, [&](const int lo[3], const int sz[3]) {
+              ProlongOp op{};
+              op.dst = p;
+              op.src = q;
+              for (int e = 0; e < 3; ++e) {
+                op.lo[e] = ilo[e] + lo[e];
+                op.sz[e] = sz[e];
+                op.foff[e] = e < nd ? D.lo[e] + wrap[e] : 0;
+                op.clo[e] = e < nd ? Q.lo[e] : 0;
               }
+              pops.push_back(op);
+              mark(op.lo, op.sz);
+            });
           }
         }
         for (char c : cov)
@@ -713,46 +757,42 @@ amr_status build_hierarchy(amr_table* t, HierPlan& H) {
               if (hi[e] <= lo[e]) empty = true;
             }
             if (empty) continue;
-            // x runs of uncovered cells
+            // boxes of uncovered cells; an op's colour exceeds that of every earlier
+            // op touching one of its cells
+            const int bsz[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
+            std::vector<char> need((size_t)bsz[0] * bsz[1] * bsz[2]);
             for (int z = lo[2]; z < hi[2]; ++z)
-              for (int y = lo[1]; y < hi[1]; ++y) {
-                int x = lo[0];
-                while (x < hi[0]) {
-                  int c3[3] = {x, y, z};
-                  if (covered(l, c3)) {
-                    ++x;
-                    continue;
-                  }
-                  int x1 = x;
-                  while (x1 < hi[0]) {
-                    int c4[3] = {x1, y, z};
-                    if (covered(l, c4)) break;
-                    ++x1;
-                  }
-                  FixOp op{};
-                  op.fine = p;
-                  op.coarse = q;
-                  op.d = d;
-                  op.side = side;
-                  op.lo[0] = x - Q.lo[0];
-                  op.lo[1] = y - (nd > 1 ? Q.lo[1] : 0);
-                  op.lo[2] = z - (nd > 2 ? Q.lo[2] : 0);
-                  op.sz[0] = x1 - x;
-                  op.sz[1] = 1;
-                  op.sz[2] = 1;
-                  for (int e = 0; e < 3; ++e) op.fo[e] = e < nd ? 2 * Q.lo[e] - F.lo[e] : 0;
-                  int color = 0;
-                  for (int xx = x; xx < x1; ++xx) {
-                    const int64_t key = ((int64_t)z * 65536 + y) * 65536 + xx;
-                    auto it = last_color.find({q, key});
+              for (int y = lo[1]; y < hi[1]; ++y)
+                for (int x = lo[0]; x < hi[0]; ++x) {
+                  const int c3[3] = {x, y, z};
+                  need[((size_t)(z - lo[2]) * bsz[1] + (y - lo[1])) * bsz[0] + (x - lo[0])] = !covered(l, c3);
+                }
+            cover_boxes(bsz, need, [&](const int blo[3], const int sz[3]) {
+              FixOp op{};
+              op.fine = p;
+              op.coarse = q;
+              op.d = d;
+              op.side = side;
+              for (int e = 0; e < 3; ++e) {
+                op.lo[e] = lo[e] + blo[e] - (e < nd ? Q.lo[e] : 0);
+                op.sz[e] = sz[e];
+                op.fo[e] = e < nd ? 2 * Q.lo[e] - F.lo[e] : 0;
+              }
+              auto key = [&](int x, int y, int z) { return ((int64_t)z * 65536 + y) * 65536 + x; };
+              int color = 0;
+              for (int z = 0; z < sz[2]; ++z)
+                for (int y = 0; y < sz[1]; ++y)
+                  for (int x = 0; x < sz[0]; ++x) {
+                    auto it = last_color.find({q, key(lo[0] + blo[0] + x, lo[1] + blo[1] + y, lo[2] + blo[2] + z)});
                     if (it != last_color.end()) color = std::max(color, it->second + 1);
                   }
-                  for (int xx = x; xx < x1; ++xx) last_color[{q, ((int64_t)z * 65536 + y) * 65536 + xx}] = color;
-                  fl.push_back(op);
-                  cl.push_back(color);
-                  x = x1;
-                }
-              }
+              for (int z = 0; z < sz[2]; ++z)
+                for (int y = 0; y < sz[1]; ++y)
+                  for (int x = 0; x < sz[0]; ++x)
+                    last_color[{q, key(lo[0] + blo[0] + x, lo[1] + blo[1] + y, lo[2] + blo[2] + z)}] = color;
+              fl.push_back(op);
+              cl.push_back(color);
+            });
           }
         }
     }
@@ -888,6 +928,24 @@ amr_status amr_patch_table_create(const amr_patch_desc* patches, int32_t npatch,
   if (!upload(&t->prol_d, pops) || !upload(&t->phys_d, H.phys) || !upload(&t->fix_d, H.fix) ||
       !upload(&t->rst_d, H.rst) || !upload(&t->snap_d, H.snap))
     return fail(AMR_ENOMEM);
+  // cell-granular work lists of every box-op launch
+  {
+    std::vector<Seg> segs;
+    std::vector<int> blk;
+    t->w_copy.assign(MAX_LEVELS, {});
+    t->w_prol.assign(MAX_LEVELS, {});
+    t->w_phys.assign(MAX_LEVELS, {});
+    t->w_rst.assign(MAX_LEVELS, {});
+    t->w_fix.assign(MAX_LEVELS, {});
+    for (int l = 0; l <= t->max_level; ++l) {
+      t->w_copy[l] = add_work(segs, blk, ops.data() + t->ops_level_first[l], t->ops_level_count[l]);
+      t->w_prol[l] = add_work(segs, blk, pops.data() + t->prol_first[l], t->prol_count[l]);
+      t->w_phys[l] = add_work(segs, blk, H.phys.data() + t->phys_first[l], t->phys_count[l]);
+      t->w_rst[l] = add_work(segs, blk, H.rst.data() + t->rst_first[l], t->rst_count[l]);
+      for (const auto& fc : t->fix_colors[l]) t->w_fix[l].push_back(add_work(segs, blk, H.fix.data() + fc.first, fc.second));
+    }
+    if (!upload(&t->segs_d, segs) || !upload(&t->blk_d, blk)) return fail(AMR_ENOMEM);
+  }
   if (t->max_level > 0) {
     if (hipMalloc(&t->snap, sizeof(double) * (size_t)t->arena) != hipSuccess) return fail(AMR_ENOMEM);
     if (hipMalloc(&t->dtl, sizeof(double) * MAX_LEVELS) != hipSuccess) return fail(AMR_ENOMEM);
@@ -926,7 +984,7 @@ amr_status amr_patch_table_destroy(amr_table* t) {
   if (t->fused_d) (void)hipFree(t->fused_d);
   if (t->ops_d) (void)hipFree(t->ops_d);
   for (void* q : {(void*)t->snap, (void*)t->reg, (void*)t->dtl, (void*)t->prol_d, (void*)t->phys_d, (void*)t->fix_d,
-                  (void*)t->rst_d, (void*)t->snap_d})
+                  (void*)t->rst_d, (void*)t->snap_d, (void*)t->segs_d, (void*)t->blk_d})
     if (q) (void)hipFree(q);
   if (t->cap_stream) (void)hipStreamDestroy(t->cap_stream);
   for (auto& e : t->ev)

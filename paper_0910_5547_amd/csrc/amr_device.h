@@ -89,6 +89,50 @@ struct RestrictOp {
   int pad;
 };
 
+// Cell-granular distribution of a list of box ops over 256-lane workgroups: the
+// cells of the ops, in list order, are numbered consecutively and workgroup b
+// takes cells [256 b, 256 b + 256), one per lane, so small boxes share a
+// workgroup instead of idling most of its lanes.  A segment is the part of one op
+// that falls in one workgroup.
+struct Seg {
+  int op;     // index in the op list
+  int cell0;  // the op's cell (x fastest in its box) held by lane `lane0`
+  int lane0;
+  int count;  // cells of the op in this workgroup
+};
+struct Work {
+  const Seg* segs;  // segments of every work list of the table
+  const int* blk;   // segments of workgroup b of this list: [blk[b], blk[b + 1])
+  int nblk;
+  int pad;
+};
+
+// The op index (or -1: no cell) and the cell within it of this lane.
+__device__ __forceinline__ int work_item(const Work& w, int& cell) {
+  int op = -1;
+  cell = 0;
+  const int lane = (int)threadIdx.x;
+  for (int s = w.blk[blockIdx.x]; s < w.blk[blockIdx.x + 1]; ++s) {
+    const Seg g = w.segs[s];
+    const int c = lane - g.lane0;
+    if (c >= 0 && c < g.count) {
+      op = g.op;
+      cell = g.cell0 + c;
+    }
+  }
+  return op;
+}
+
+// Cell c (x fastest) of a box of sz cells -> its offsets b inside the box.
+__device__ __forceinline__ void box_cell(const int sz[3], int c, int b[3]) {
+  const int plane = sz[0] * sz[1];
+  const int kk = c / plane, r = c - kk * plane;
+  const int jj = r / sz[0];
+  b[0] = r - jj * sz[0];
+  b[1] = jj;
+  b[2] = kk;
+}
+
 struct Consts {
   double gamma, gm1, gg1, theta, rho_floor, e_floor;  // gg1 = gamma (gamma - 1)
   int ndim, flux;
@@ -160,7 +204,11 @@ __device__ __forceinline__ bool cons2prim(const double u[NVAR], const Consts& c,
   const double rho = u[0];
   double vx, vy, vz, e;
   if constexpr (Fast<RT>::value) {
-    const double ri = 1.0 / rho;
+    // 1/rho: hardware reciprocal estimate and two Newton steps (each squares the
+    // relative error), in place of the correctly rounded division sequence
+    double ri = __builtin_amdgcn_rcp(rho);
+    ri = fma(ri, fma(-rho, ri, 1.0), ri);
+    ri = fma(ri, fma(-rho, ri, 1.0), ri);
     vx = u[1] * ri;
     vy = u[2] * ri;
     vz = u[3] * ri;
@@ -245,6 +293,30 @@ __device__ __forceinline__ double minmod2(double a, double b) {
 template <typename RT>
 __device__ __forceinline__ RT plm_slope(RT qm, RT q0, RT qp, RT theta) {
   return minmod3(theta * (q0 - qm), theta * (qp - q0), (qp - qm) * RT(0.5));
+}
+
+// Two-argument minmod in the same sign-bit form: sgn(a) max(0, min(|a|, sgn(a) b)).
+__device__ __forceinline__ float minmod_ab(float a, float b) {
+  const unsigned sa = __float_as_uint(a) & 0x80000000u;
+  const float m = fmaxf(fminf(fabsf(a), __uint_as_float(__float_as_uint(b) ^ sa)), 0.0f);
+  return __uint_as_float(__float_as_uint(m) | sa);
+}
+__device__ __forceinline__ double minmod_ab(double a, double b) {
+  const unsigned long long sa = (unsigned long long)__double_as_longlong(a) & 0x8000000000000000ull;
+  const double bb = __longlong_as_double((long long)((unsigned long long)__double_as_longlong(b) ^ sa));
+  const double m = fmax(fmin(fabs(a), bb), 0.0);
+  return __longlong_as_double((long long)((unsigned long long)__double_as_longlong(m) | sa));
+}
+
+// plm_slope with theta = 1 known at compile time (TH1).  The multiplications by
+// theta are then exact, and when the one-sided differences a, b agree in sign the
+// centred argument fl(fl(a + b)/2) is never below min(|a|, |b|) (rounding is
+// monotone, halving exact), so the three-argument minmod returns the same value
+// as the two-argument one, which skips three operations per variable.
+template <typename RT, bool TH1>
+__device__ __forceinline__ RT plm_slope_t(RT qm, RT q0, RT qp, RT theta) {
+  if constexpr (TH1) return minmod_ab(q0 - qm, qp - q0);
+  else return plm_slope<RT>(qm, q0, qp, theta);
 }
 
 template <typename RT>

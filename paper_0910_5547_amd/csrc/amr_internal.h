@@ -54,19 +54,19 @@ const void* stage_kernel_ptr(int mixed, int shape, int stage);
 hipError_t launch_cfl(int grid, hipStream_t s, const CflArgs& a);
 hipError_t launch_cfl_finalize(hipStream_t s, const unsigned long long* smax, int lmin, int lmax, int root,
                                double cfl, double* dt);
-hipError_t launch_copy_ghosts(int grid, hipStream_t s, const CopyOp* ops, int nops, const PatchDev* p, double* A);
+hipError_t launch_copy_ghosts(hipStream_t s, const CopyOp* ops, const Work& w, const PatchDev* p, double* A);
 hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, int n, unsigned long long v);
 hipError_t launch_fill_i32(hipStream_t s, int* p, int n, int v);
 
-hipError_t launch_prolong(int grid, hipStream_t s, const ProlongOp* ops, int nops, const PatchDev* p, double* A,
+hipError_t launch_prolong(hipStream_t s, const ProlongOp* ops, const Work& w, const PatchDev* p, double* A,
                           const double* Cold, const double* Cnew, double alpha, int ndim);
-hipError_t launch_phys(int grid, hipStream_t s, const PhysOp* ops, int nops, const PatchDev* p, double* A);
+hipError_t launch_phys(hipStream_t s, const PhysOp* ops, const Work& w, const PatchDev* p, double* A);
 hipError_t launch_copy_ranges(hipStream_t s, const int64_t* ranges, int nr, int64_t maxlen, const double* src,
                               double* dst);
-hipError_t launch_flux_fix(int mixed, int grid, hipStream_t s, const FixOp* ops, int nops, const PatchDev* p,
-                           double* U, const double* S1, const double* S2, const double* reg, const double* dtc,
-                           const Consts& C, int* flag);
-hipError_t launch_restrict(int grid, hipStream_t s, const RestrictOp* ops, int nops, const PatchDev* p, double* U,
+hipError_t launch_flux_fix(int mixed, hipStream_t s, const FixOp* ops, const Work& w, const PatchDev* p, double* U,
+                           const double* S1, const double* S2, const double* reg, const double* dtc, const Consts& C,
+                           int* flag);
+hipError_t launch_restrict(hipStream_t s, const RestrictOp* ops, const Work& w, const PatchDev* p, double* U,
                            int ndim);
 hipError_t launch_scale_dt(hipStream_t s, const double* dt0, double* dtl, int nlev);
 

@@ -36,7 +36,8 @@ namespace amr {
 // Occupancy target: three 256-lane workgroups per CU for the FP32-reconstruction
 // instantiations (<= 168 VGPRs), two for FP64 (LDS-bound at two per CU anyway).
 // REC: record fine-face fluxes into the refluxing registers (patches of levels > 0).
-template <typename RT, int TX, int TY, int STAGE, bool REC>
+// TH1: the limiter parameter is 1 (the two-argument minmod, see plm_slope_t).
+template <typename RT, int TX, int TY, int STAGE, bool REC, bool TH1>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Fast<RT>::value ? 3 : 2)))
 void stage_kernel(StageArgs a) {
   static_assert(TX * TY == NT, "one lane per column of the tile");
@@ -80,20 +81,29 @@ void stage_kernel(StageArgs a) {
     // the stride between planes; plane k of the column is at col0 + kk * pstride,
     // kk being k after the z boundary map (uniform across the workgroup)
     const int64_t pstride = (int64_t)P.s[0] * P.s[1];
-    const int64_t col0 = P.off + (int64_t)P.g[2] * pstride + (int64_t)(j + P.g[1]) * P.s[0] + (i + P.g[0]);
-    auto load_col = [&](int kz, double u[NVAR]) {
+    // (inactive lanes of a ragged tile point at the tile's last active column, so that
+    // every lane can issue the plane prefetch below unconditionally)
+    const int ic = min(i, P.n[0] - 1), jc = min(j, P.n[1] - 1);
+    const int64_t col0 = P.off + (int64_t)P.g[2] * pstride + (int64_t)(jc + P.g[1]) * P.s[0] + (ic + P.g[0]);
+    // The REFLECT sign flip of the normal momentum is applied where loaded values
+    // are used, not at the load: a flip right after the load would make the load
+    // wait for its data, and the prefetches below would stop hiding latency.
+    auto load_col_raw = [&](int kz, double u[NVAR]) -> bool {  // true: negate u[3]
       bool fz = false;
       const int kk = map_index(kz, P.n[2], P.bc[4], P.bc[5], fz);
       const int64_t e = col0 + (int64_t)kk * pstride;
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) u[v] = a.V[e + v * P.S];
-      if (fz) u[3] = -u[3];
+      return fz;
+    };
+    auto load_col = [&](int kz, double u[NVAR]) {
+      if (load_col_raw(kz, u)) u[3] = -u[3];
     };
 
     // z-direction register queue (3D only): primitives of planes k and k+1, the
     // z-slope of plane k and the flux F_{k-1/2}
     RT qz[NVAR], qz1[NVAR], sgz[NVAR], Fzm[NVAR];
-    if (hasz && act) {
+    if (hasz) {
       double u[NVAR];
       RT qa[NVAR], qb[NVAR];
       load_col(T.z0 - 2, u);
@@ -115,8 +125,8 @@ void stage_kernel(StageArgs a) {
       RT qL[NVAR], qR[NVAR];
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) {
-        const RT sa = plm_slope<RT>(qa[v], qb[v], qz[v], theta);
-        sgz[v] = plm_slope<RT>(qb[v], qz[v], qz1[v], theta);
+        const RT sa = plm_slope_t<RT, TH1>(qa[v], qb[v], qz[v], theta);
+        sgz[v] = plm_slope_t<RT, TH1>(qb[v], qz[v], qz1[v], theta);
         qL[v] = madd(RT(0.5), sa, qb[v]);
         qR[v] = madd(RT(-0.5), sgz[v], qz[v]);
       }
@@ -145,12 +155,10 @@ void stage_kernel(StageArgs a) {
     int hrow[HMAX], hcol[HMAX], hflip[HMAX];
     int64_t hbase[HMAX];  // element of the halo cell's source in plane 0 (boundary maps applied)
     double Hn[HMAX][NVAR];
-    auto load_halo = [&](int s, int kz, double u[NVAR]) {
+    auto load_halo = [&](int s, int kz, double u[NVAR]) {  // raw: hflip applied at use
       const int64_t e = hbase[s] + (int64_t)kz * pstride;
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) u[v] = a.V[e + v * P.S];
-      if (hflip[s] == 1) u[1] = -u[1];
-      if (hflip[s] == 2) u[2] = -u[2];
     };
 #pragma unroll
     for (int s = 0; s < HMAX; ++s) {
@@ -178,32 +186,49 @@ void stage_kernel(StageArgs a) {
     auto idiv = [](int w, float r) { return (int)(((float)w + 0.5f) * r); };
 
     for (int k = T.z0; k < T.z1; ++k) {
-      // this step's HBM read first: plane k+2 of the column
+      // this step's HBM read first: plane k+2 of the column in 3D (consumed by the z
+      // flux after the x-y work), plane k itself in 1D/2D.  Issued by every lane
+      // without a branch, so that nothing between here and the use waits for it.
       double Vn2[NVAR];
-      if (hasz && act) load_col(k + 2, Vn2);
+      const bool fz2 = load_col_raw(hasz ? k + 2 : k, Vn2);
       // halo of plane k (prefetched) into LDS, then prefetch the halo of plane k+1
 #pragma unroll
       for (int s = 0; s < HMAX; ++s) {
         if (tid + s * NT < nhx + nhy) {
           RT q[NVAR];
+          if (hflip[s] == 1) Hn[s][1] = -Hn[s][1];
+          if (hflip[s] == 2) Hn[s][2] = -Hn[s][2];
           bad |= cons2prim<RT>(Hn[s], C, q);
 #pragma unroll
           for (int v = 0; v < NVAR; ++v) sP[buf][v][hrow[s] + RO][hcol[s] + 2] = q[v];
           if (k + 1 < T.z1) load_halo(s, k + 1, Hn[s]);
         }
       }
-      if (act) {
+      // (every lane computes; inactive lanes of ragged tiles hold a copy of an active
+      // column and only skip the shared and global writes: a branch around loads or
+      // their uses would leave loads pending on one path, and the next iteration would
+      // wait for all memory at its first prefetch)
+      {
         RT qc[NVAR];
         if (hasz) {
 #pragma unroll
           for (int v = 0; v < NVAR; ++v) qc[v] = qz[v];
         } else {
-          double u[NVAR];
-          load_col(k, u);
-          bad |= cons2prim<RT>(u, C, qc);
-        }
+          // (the empty asm keeps this use inside the 1D/2D branch: hoisted above it, the
+          // conversion would make 3D wait here for its plane k+2 prefetch)
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) sP[buf][v][cy + RO][cx + 2] = qc[v];
+          for (int v = 0; v < NVAR; ++v) asm volatile("" : "+v"(Vn2[v]));
+          if (fz2) Vn2[3] = -Vn2[3];
+          bad |= cons2prim<RT>(Vn2, C, qc);
+          if constexpr (RING) {
+#pragma unroll
+            for (int v = 0; v < NVAR; ++v) sV[k & 1][v][tid] = Vn2[v];
+          }
+        }
+        if (act) {
+#pragma unroll
+          for (int v = 0; v < NVAR; ++v) sP[buf][v][cy + RO][cx + 2] = qc[v];
+        }
       }
       __syncthreads();  // (A) plane primitives ready; previous plane's fluxes consumed
 
@@ -233,21 +258,21 @@ void stage_kernel(StageArgs a) {
         for (int v = 0; v < NVAR; ++v) {
           const RT* pl = &sP[buf][v][0][0];
           const RT qm = pl[pc - stride], q0 = pl[pc], qp = pl[pc + stride];
-          const RT sg = plm_slope<RT>(qm, q0, qp, theta);
+          const RT sg = plm_slope_t<RT, TH1>(qm, q0, qp, theta);
           if (slo >= 0) sFR[v][slo] = madd(RT(-0.5), sg, q0);  // right state of the cell's low face
           if (shi >= 0) sFL[v][shi] = madd(RT(0.5), sg, q0);   // left state of its high face
         }
       }
       __syncthreads();  // (B) face states ready
 
-      // the stage input (3D: from the lane's LDS ring; else re-read, just loaded) and
+      // the stage input (from the lane's LDS ring; FP64 instantiations re-read it) and
       // (stage 2) U^n of this cell, for the update: read here so the face pass hides
       // the latency
       double Vc[NVAR], U0c[NVAR];
       const int64_t ecell = col0 + (int64_t)k * pstride;
-      if (act) {
+      {
         const int64_t e = ecell;
-        if (RING && hasz) {
+        if constexpr (RING) {
 #pragma unroll
           for (int v = 0; v < NVAR; ++v) Vc[v] = sV[k & 1][v][tid];
         } else {
@@ -300,17 +325,18 @@ void stage_kernel(StageArgs a) {
       }
       // z-face flux F_{k+1/2} of this column from the register queue
       RT Fzp[NVAR], qn2[NVAR], sg1[NVAR];
-      if (hasz && act) {
+      if (hasz) {
         RT qL[NVAR], qR[NVAR];
+        if (fz2) Vn2[3] = -Vn2[3];
         bad |= cons2prim<RT>(Vn2, C, qn2);
 #pragma unroll
         for (int v = 0; v < NVAR; ++v) {
-          sg1[v] = plm_slope<RT>(qz[v], qz1[v], qn2[v], theta);
+          sg1[v] = plm_slope_t<RT, TH1>(qz[v], qz1[v], qn2[v], theta);
           qL[v] = madd(RT(0.5), sgz[v], qz[v]);
           qR[v] = madd(RT(-0.5), sg1[v], qz1[v]);
         }
         riemann_flux<RT, 2>(qL, qR, K, kind, Fzp);
-        if (REC && rec && k == P.n[2] - 1 && P.reg[5] >= 0) {
+        if (REC && act && rec && k == P.n[2] - 1 && P.reg[5] >= 0) {
 #pragma unroll
           for (int v = 0; v < NVAR; ++v) {
             double* r = a.reg + P.reg[5] + ((int64_t)v * P.n[1] + j) * P.n[0] + i;
@@ -321,7 +347,7 @@ void stage_kernel(StageArgs a) {
       __syncthreads();  // (C) fluxes ready
 
       // (3) L(U) in the order x, y, z, then the TVD-RK2 stage combine
-      if (act) {
+      {
         double L[NVAR];
         const int sx = cy * (nxT + 1) + cx, sy = nfx + cy * nxT + cx;
 #pragma unroll
@@ -360,9 +386,12 @@ void stage_kernel(StageArgs a) {
           if constexpr (FAST) u1 = fma(dt, L[v], Vc[v]);
           else u1 = Vc[v] + dt * L[v];
           un[v] = (STAGE == 1) ? u1 : 0.5 * U0c[v] + 0.5 * u1;
-          a.out[e + v * P.S] = un[v];
         }
-        if (STAGE == 2 && a.smax != nullptr) smax = fmax(smax, cell_speed<FAST>(un, C, P, bad));
+        if (act) {
+#pragma unroll
+          for (int v = 0; v < NVAR; ++v) a.out[e + v * P.S] = un[v];
+          if (STAGE == 2 && a.smax != nullptr) smax = fmax(smax, cell_speed<FAST>(un, C, P, bad));
+        }
       }
     }
     if (STAGE == 2 && a.smax != nullptr) {  // fused next-dt reduction, per level
@@ -417,23 +446,22 @@ __global__ void cfl_finalize(const unsigned long long* smax, int lmin, int lmax,
 }
 
 // ------------------------------------------------------------------ ghosts
-// Same-level EXTERNAL ghost fill: one workgroup per copy op.
-__global__ __launch_bounds__(NT) void copy_ghosts(const CopyOp* __restrict__ ops, int nops,
+// Same-level EXTERNAL ghost fill, one ghost cell per lane.
+__global__ __launch_bounds__(NT) void copy_ghosts(const CopyOp* __restrict__ ops, Work w,
                                                   const PatchDev* __restrict__ patches, double* A) {
-  for (int o = blockIdx.x; o < nops; o += gridDim.x) {
-    const CopyOp op = ops[o];
-    const PatchDev D = patches[op.dst], S = patches[op.src];
-    const int n = op.sz[0] * op.sz[1] * op.sz[2];
-    for (int c = threadIdx.x; c < n; c += NT) {
-      const int kk = c / (op.sz[0] * op.sz[1]), r = c - kk * op.sz[0] * op.sz[1];
-      const int jj = r / op.sz[0], ii = r - jj * op.sz[0];
-      const int i = op.lo[0] + ii, j = op.lo[1] + jj, k = op.lo[2] + kk;
-      const int64_t ed = cell_elem(D, i, j, k);
-      const int64_t es = cell_elem(S, i + op.sh[0], j + op.sh[1], k + op.sh[2]);
+  int c;
+  const int o = work_item(w, c);
+  if (o < 0) return;
+  const CopyOp op = ops[o];
+  const PatchDev& D = patches[op.dst];
+  const PatchDev& S = patches[op.src];
+  int b[3];
+  box_cell(op.sz, c, b);
+  const int i = op.lo[0] + b[0], j = op.lo[1] + b[1], k = op.lo[2] + b[2];
+  const int64_t ed = cell_elem(D, i, j, k);
+  const int64_t es = cell_elem(S, i + op.sh[0], j + op.sh[1], k + op.sh[2]);
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) A[ed + v * D.S] = A[es + v * S.S];
-    }
-  }
+  for (int v = 0; v < NVAR; ++v) A[ed + v * D.S] = A[es + v * S.S];
 }
 
 // dt_l = dt0 / 2^l: factor-2 subcycling of a block-structured hierarchy.
@@ -455,8 +483,14 @@ __global__ void fill_i32(int* p, int n, int v) {
 // ------------------------------------------------------------------ launchers
 template <typename RT, int TX, int TY, int STAGE>
 static hipError_t launch_stage_t(dim3 grid, hipStream_t s, const StageArgs& a) {
-  if (a.reg) hipLaunchKernelGGL((stage_kernel<RT, TX, TY, STAGE, true>), grid, dim3(NT), 0, s, a);
-  else hipLaunchKernelGGL((stage_kernel<RT, TX, TY, STAGE, false>), grid, dim3(NT), 0, s, a);
+  const bool th1 = a.c.theta == 1.0;
+  if (a.reg) {
+    if (th1) hipLaunchKernelGGL((stage_kernel<RT, TX, TY, STAGE, true, true>), grid, dim3(NT), 0, s, a);
+    else hipLaunchKernelGGL((stage_kernel<RT, TX, TY, STAGE, true, false>), grid, dim3(NT), 0, s, a);
+  } else {
+    if (th1) hipLaunchKernelGGL((stage_kernel<RT, TX, TY, STAGE, false, true>), grid, dim3(NT), 0, s, a);
+    else hipLaunchKernelGGL((stage_kernel<RT, TX, TY, STAGE, false, false>), grid, dim3(NT), 0, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -482,11 +516,11 @@ hipError_t launch_stage(int mixed, int shape, int stage, int grid, hipStream_t s
   return launch_stage_rt<double>(shape, stage, dim3(grid), s, a);
 }
 
-// The non-recording instantiation (the occupancy of both is the same resource class).
+// The non-recording, theta = 1 instantiation (the others share its resource class).
 const void* stage_kernel_ptr(int mixed, int shape, int stage) {
 #define AMR_KP(RT, TX, TY)                                                                          \
-  (stage == 1 ? reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, 1, false>)                  \
-              : reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, 2, false>))
+  (stage == 1 ? reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, 1, false, true>)            \
+              : reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, 2, false, true>))
   if (mixed) {
     switch (shape) {
       case 0: return AMR_KP(float, 256, 1);
@@ -518,8 +552,8 @@ hipError_t launch_cfl_finalize(hipStream_t s, const unsigned long long* smax, in
   hipLaunchKernelGGL(cfl_finalize, dim3(1), dim3(64), 0, s, smax, lmin, lmax, root, cfl, dt);
   return hipGetLastError();
 }
-hipError_t launch_copy_ghosts(int grid, hipStream_t s, const CopyOp* ops, int nops, const PatchDev* p, double* A) {
-  hipLaunchKernelGGL(copy_ghosts, dim3(grid), dim3(NT), 0, s, ops, nops, p, A);
+hipError_t launch_copy_ghosts(hipStream_t s, const CopyOp* ops, const Work& w, const PatchDev* p, double* A) {
+  hipLaunchKernelGGL(copy_ghosts, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, A);
   return hipGetLastError();
 }
 hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, int n, unsigned long long v) {

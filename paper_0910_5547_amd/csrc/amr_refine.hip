@@ -10,19 +10,12 @@
 //                    swaps its own interface flux (recomputed bit for bit from the
 //                    two saved stage inputs) for the fine registers' average;
 //   restrict_cells   covered coarse cells <- mean of their 2^d children.
-// Each op is a box; one workgroup per op, lanes over its cells.
+// Each op is a box of cells; a work list spreads the cells of all ops of a launch
+// over the workgroups' lanes, one cell per lane.
 #include "amr_device.h"
 #include "amr_internal.h"
 
 namespace amr {
-
-__device__ __forceinline__ void box_cell(const int sz[3], int c, int out[3]) {
-  const int kk = c / (sz[0] * sz[1]), r = c - kk * sz[0] * sz[1];
-  const int jj = r / sz[0];
-  out[0] = r - jj * sz[0];
-  out[1] = jj;
-  out[2] = kk;
-}
 
 __device__ __forceinline__ int64_t stride_of(const PatchDev& P, int d) {
   return d == 0 ? 1 : (d == 1 ? (int64_t)P.s[0] : (int64_t)P.s[0] * P.s[1]);
@@ -39,62 +32,60 @@ __device__ __forceinline__ double at_time(const double* Cold, const double* Cnew
 // Fine ghost cell = u(C) + sum_d (+-1/4) minmod(u(C+e_d) - u(C), u(C) - u(C-e_d)),
 // u the time-interpolated coarse state, C the coarse cell holding the fine cell,
 // + for the upper child along d.  The 2^d children of C average to u(C).
-__global__ __launch_bounds__(NT) void prolong_ghosts(const ProlongOp* __restrict__ ops, int nops,
+__global__ __launch_bounds__(NT) void prolong_ghosts(const ProlongOp* __restrict__ ops, Work w,
                                                      const PatchDev* __restrict__ patches, double* A,
                                                      const double* Cold, const double* Cnew, double alpha,
                                                      int ndim) {
-  for (int o = blockIdx.x; o < nops; o += gridDim.x) {
-    const ProlongOp op = ops[o];
-    const PatchDev D = patches[op.dst], Q = patches[op.src];
-    const int n = op.sz[0] * op.sz[1] * op.sz[2];
-    for (int c = threadIdx.x; c < n; c += NT) {
-      int b[3];
-      box_cell(op.sz, c, b);
-      const int loc[3] = {op.lo[0] + b[0], op.lo[1] + b[1], op.lo[2] + b[2]};
-      int L[3] = {0, 0, 0}, cq[3] = {0, 0, 0};
-      for (int d = 0; d < ndim; ++d) {
-        L[d] = loc[d] + op.foff[d];
-        cq[d] = (L[d] >> 1) - op.clo[d];
-      }
-      const int64_t ed = cell_elem(D, loc[0], loc[1], loc[2]);
-      const int64_t e0 = cell_elem(Q, cq[0], cq[1], cq[2]);
+  int c;
+  const int o = work_item(w, c);
+  if (o < 0) return;
+  const ProlongOp op = ops[o];
+  const PatchDev& D = patches[op.dst];
+  const PatchDev& Q = patches[op.src];
+  int b[3];
+  box_cell(op.sz, c, b);
+  const int loc[3] = {op.lo[0] + b[0], op.lo[1] + b[1], op.lo[2] + b[2]};
+  int L[3] = {0, 0, 0}, cq[3] = {0, 0, 0};
+  for (int d = 0; d < ndim; ++d) {
+    L[d] = loc[d] + op.foff[d];
+    cq[d] = (L[d] >> 1) - op.clo[d];
+  }
+  const int64_t ed = cell_elem(D, loc[0], loc[1], loc[2]);
+  const int64_t e0 = cell_elem(Q, cq[0], cq[1], cq[2]);
+  const int64_t DS = D.S, QS = Q.S;
+  const int64_t qs[3] = {1, (int64_t)Q.s[0], (int64_t)Q.s[0] * Q.s[1]};
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) {
-        const int64_t ev = e0 + v * Q.S;
-        const double u0 = at_time(Cold, Cnew, alpha, ev);
-        double val = u0;
-        for (int d = 0; d < ndim; ++d) {
-          const int64_t st = stride_of(Q, d);
-          const double up = at_time(Cold, Cnew, alpha, ev + st);
-          const double um = at_time(Cold, Cnew, alpha, ev - st);
-          const double sg = minmod2(up - u0, u0 - um);
-          const double sgn = (L[d] & 1) ? 0.25 : -0.25;
-          val = val + sgn * sg;
-        }
-        A[ed + v * D.S] = val;
-      }
+  for (int v = 0; v < NVAR; ++v) {
+    const int64_t ev = e0 + v * QS;
+    const double u0 = at_time(Cold, Cnew, alpha, ev);
+    double val = u0;
+    for (int d = 0; d < ndim; ++d) {
+      const double up = at_time(Cold, Cnew, alpha, ev + qs[d]);
+      const double um = at_time(Cold, Cnew, alpha, ev - qs[d]);
+      const double sg = minmod2(up - u0, u0 - um);
+      const double sgn = (L[d] & 1) ? 0.25 : -0.25;
+      val = val + sgn * sg;
     }
+    A[ed + v * DS] = val;
   }
 }
 
 // ---------------------------------------------------------------- physical ghosts
-__global__ __launch_bounds__(NT) void fill_phys_ghosts(const PhysOp* __restrict__ ops, int nops,
+__global__ __launch_bounds__(NT) void fill_phys_ghosts(const PhysOp* __restrict__ ops, Work w,
                                                        const PatchDev* __restrict__ patches, double* A) {
-  for (int o = blockIdx.x; o < nops; o += gridDim.x) {
-    const PhysOp op = ops[o];
-    const PatchDev P = patches[op.patch];
-    const int n = op.sz[0] * op.sz[1] * op.sz[2];
-    for (int c = threadIdx.x; c < n; c += NT) {
-      int b[3];
-      box_cell(op.sz, c, b);
-      const int i = op.lo[0] + b[0], j = op.lo[1] + b[1], k = op.lo[2] + b[2];
-      double u[NVAR];
-      load_cons(A, P, i, j, k, u);  // the boundary condition's index map
-      const int64_t e = cell_elem(P, i, j, k);
+  int c;
+  const int o = work_item(w, c);
+  if (o < 0) return;
+  const PhysOp op = ops[o];
+  const PatchDev& P = patches[op.patch];
+  int b[3];
+  box_cell(op.sz, c, b);
+  const int i = op.lo[0] + b[0], j = op.lo[1] + b[1], k = op.lo[2] + b[2];
+  double u[NVAR];
+  load_cons(A, P, i, j, k, u);  // the boundary condition's index map
+  const int64_t e = cell_elem(P, i, j, k);
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) A[e + v * P.S] = u[v];
-    }
-  }
+  for (int v = 0; v < NVAR; ++v) A[e + v * P.S] = u[v];
 }
 
 // ---------------------------------------------------------------- snapshot
@@ -125,10 +116,13 @@ __device__ void coarse_face_flux(const double* S, const PatchDev& Q, int d, int 
     bad |= cons2prim<RT>(u, C, q[m]) ? 1 : 0;
   }
   RT qL[NVAR], qR[NVAR];
+  const bool th1 = C.theta == 1.0;  // the stage kernel's limiter form (same values)
 #pragma unroll
   for (int v = 0; v < NVAR; ++v) {
-    const RT s1 = plm_slope<RT>(q[0][v], q[1][v], q[2][v], theta);
-    const RT s2 = plm_slope<RT>(q[1][v], q[2][v], q[3][v], theta);
+    const RT s1 = th1 ? plm_slope_t<RT, true>(q[0][v], q[1][v], q[2][v], theta)
+                      : plm_slope_t<RT, false>(q[0][v], q[1][v], q[2][v], theta);
+    const RT s2 = th1 ? plm_slope_t<RT, true>(q[1][v], q[2][v], q[3][v], theta)
+                      : plm_slope_t<RT, false>(q[1][v], q[2][v], q[3][v], theta);
     qL[v] = madd(RT(0.5), s1, q[1][v]);
     qR[v] = madd(RT(-0.5), s2, q[2][v]);
   }
@@ -141,91 +135,92 @@ __device__ void coarse_face_flux(const double* S, const PatchDev& Q, int d, int 
 // 2^(ndim-1) fine faces under it; s = +1 where the interface is the coarse cell's
 // high face (side 0), -1 where it is its low face.
 template <typename RT>
-__global__ __launch_bounds__(NT) void flux_fix(const FixOp* __restrict__ ops, int nops,
+__global__ __launch_bounds__(NT) void flux_fix(const FixOp* __restrict__ ops, Work w,
                                                const PatchDev* __restrict__ patches, double* U,
                                                const double* S1, const double* S2, const double* __restrict__ reg,
                                                const double* dtc_ptr, Consts C, int* flag) {
+  int c;
+  const int o = work_item(w, c);
+  if (o < 0) return;
   const double dtc = *dtc_ptr;
   int bad = 0;
-  for (int o = blockIdx.x; o < nops; o += gridDim.x) {
-    const FixOp op = ops[o];
-    const PatchDev Q = patches[op.coarse], P = patches[op.fine];
-    const int d = op.d, face = 2 * d + op.side;
-    const int n = op.sz[0] * op.sz[1] * op.sz[2];
-    for (int c = threadIdx.x; c < n; c += NT) {
-      int b[3];
-      box_cell(op.sz, c, b);
-      const int cc[3] = {op.lo[0] + b[0], op.lo[1] + b[1], op.lo[2] + b[2]};
-      const int fl = cc[d] + (op.side == 0 ? 1 : 0);
-      RT F1[NVAR], F2[NVAR];
-      coarse_face_flux<RT>(S1, Q, d, fl, cc, C, F1, bad);
-      coarse_face_flux<RT>(S2, Q, d, fl, cc, C, F2, bad);
-      // fine faces under this coarse face: 2 per active tangential dimension, summed
-      // with dimension (d+2)%3 outer and (d+1)%3 inner; the register of a face is
-      // laid out [v][upper tangential dim][lower tangential dim]
-      const int da = (d + 1) % 3, db = (d + 2) % 3;
-      const int tlo = da < db ? da : db;
-      const int na = da < C.ndim ? 2 : 1, nb = db < C.ndim ? 2 : 1;
-      const int fa0 = da < C.ndim ? 2 * cc[da] + op.fo[da] : 0;
-      const int fb0 = db < C.ndim ? 2 * cc[db] + op.fo[db] : 0;
-      const int64_t st_a = da == tlo ? 1 : (int64_t)P.n[tlo];
-      const int64_t st_b = db == tlo ? 1 : (int64_t)P.n[tlo];
-      const int64_t rs_v = (int64_t)P.n[da] * P.n[db];
-      const int64_t e = cell_elem(Q, cc[0], cc[1], cc[2]);
-      const double sgn = op.side == 0 ? 1.0 : -1.0;
+  const FixOp op = ops[o];
+  const PatchDev& Q = patches[op.coarse];
+  const PatchDev& P = patches[op.fine];
+  const int d = op.d, face = 2 * d + op.side;
+  int b[3];
+  box_cell(op.sz, c, b);
+  const int cc[3] = {op.lo[0] + b[0], op.lo[1] + b[1], op.lo[2] + b[2]};
+  const int fl = cc[d] + (op.side == 0 ? 1 : 0);
+  RT F1[NVAR], F2[NVAR];
+  coarse_face_flux<RT>(S1, Q, d, fl, cc, C, F1, bad);
+  coarse_face_flux<RT>(S2, Q, d, fl, cc, C, F2, bad);
+  // fine faces under this coarse face: 2 per active tangential dimension, summed
+  // with dimension (d+2)%3 outer and (d+1)%3 inner; the register of a face is
+  // laid out [v][upper tangential dim][lower tangential dim]
+  const int da = (d + 1) % 3, db = (d + 2) % 3;
+  const int tlo = da < db ? da : db;
+  const int na = da < C.ndim ? 2 : 1, nb = db < C.ndim ? 2 : 1;
+  const int fa0 = da < C.ndim ? 2 * cc[da] + op.fo[da] : 0;
+  const int fb0 = db < C.ndim ? 2 * cc[db] + op.fo[db] : 0;
+  const int64_t st_a = da == tlo ? 1 : (int64_t)P.n[tlo];
+  const int64_t st_b = db == tlo ? 1 : (int64_t)P.n[tlo];
+  const int64_t rs_v = (int64_t)P.n[da] * P.n[db];
+  // (constant indices into P: a runtime index would move it to scratch memory)
+  const int64_t rbase = face == 0 ? P.reg[0] : face == 1 ? P.reg[1] : face == 2 ? P.reg[2]
+                      : face == 3 ? P.reg[3] : face == 4 ? P.reg[4] : P.reg[5];
+  const int64_t e = cell_elem(Q, cc[0], cc[1], cc[2]);
+  const double sgn = op.side == 0 ? 1.0 : -1.0;
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) {
-        double Rf = 0.0;
-        for (int yb = 0; yb < nb; ++yb)
-          for (int xa = 0; xa < na; ++xa)
-            Rf = Rf + reg[P.reg[face] + v * rs_v + (int64_t)(fb0 + yb) * st_b + (int64_t)(fa0 + xa) * st_a];
-        Rf = Rf / (double)(na * nb);
-        double Rc = 0.5 * dtc * (double)F1[v];
-        Rc = Rc + 0.5 * dtc * (double)F2[v];
-        double* u = U + e + v * Q.S;
-        *u = *u + sgn * (Rc - Rf) / Q.dx[d];
-      }
-    }
+  for (int v = 0; v < NVAR; ++v) {
+    double Rf = 0.0;
+    for (int yb = 0; yb < nb; ++yb)
+      for (int xa = 0; xa < na; ++xa)
+        Rf = Rf + reg[rbase + v * rs_v + (int64_t)(fb0 + yb) * st_b + (int64_t)(fa0 + xa) * st_a];
+    Rf = Rf / (double)(na * nb);
+    double Rc = 0.5 * dtc * (double)F1[v];
+    Rc = Rc + 0.5 * dtc * (double)F2[v];
+    double* u = U + e + v * Q.S;
+    *u = *u + sgn * (Rc - Rf) / Q.dx[d];
   }
   if (bad) atomicOr(flag, 1);
 }
 
 // ---------------------------------------------------------------- restriction
-__global__ __launch_bounds__(NT) void restrict_cells(const RestrictOp* __restrict__ ops, int nops,
+__global__ __launch_bounds__(NT) void restrict_cells(const RestrictOp* __restrict__ ops, Work w,
                                                      const PatchDev* __restrict__ patches, double* U, int ndim) {
-  for (int o = blockIdx.x; o < nops; o += gridDim.x) {
-    const RestrictOp op = ops[o];
-    const PatchDev Q = patches[op.coarse], P = patches[op.fine];
-    const int n = op.sz[0] * op.sz[1] * op.sz[2];
-    const int mz = ndim > 2 ? 2 : 1, my = ndim > 1 ? 2 : 1;
-    const double inv = (double)(1 << ndim);
-    for (int c = threadIdx.x; c < n; c += NT) {
-      int b[3];
-      box_cell(op.sz, c, b);
-      const int cc[3] = {op.lo[0] + b[0], op.lo[1] + b[1], op.lo[2] + b[2]};
-      int f0[3] = {0, 0, 0};
-      for (int d = 0; d < ndim; ++d) f0[d] = 2 * cc[d] + op.fo[d];
-      const int64_t e = cell_elem(Q, cc[0], cc[1], cc[2]);
+  int c;
+  const int o = work_item(w, c);
+  if (o < 0) return;
+  const RestrictOp op = ops[o];
+  const PatchDev& Q = patches[op.coarse];
+  const PatchDev& P = patches[op.fine];
+  const int mz = ndim > 2 ? 2 : 1, my = ndim > 1 ? 2 : 1;
+  const double inv = (double)(1 << ndim);
+  int b[3];
+  box_cell(op.sz, c, b);
+  const int cc[3] = {op.lo[0] + b[0], op.lo[1] + b[1], op.lo[2] + b[2]};
+  int f0[3] = {0, 0, 0};
+  for (int d = 0; d < ndim; ++d) f0[d] = 2 * cc[d] + op.fo[d];
+  const int64_t e = cell_elem(Q, cc[0], cc[1], cc[2]);
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) {
-        double acc = 0.0;
-        for (int dz = 0; dz < mz; ++dz)
-          for (int dy = 0; dy < my; ++dy)
-            for (int dx = 0; dx < 2; ++dx) acc = acc + U[cell_elem(P, f0[0] + dx, f0[1] + dy, f0[2] + dz) + v * P.S];
-        U[e + v * Q.S] = acc / inv;
-      }
-    }
+  for (int v = 0; v < NVAR; ++v) {
+    double acc = 0.0;
+    for (int dz = 0; dz < mz; ++dz)
+      for (int dy = 0; dy < my; ++dy)
+        for (int dx = 0; dx < 2; ++dx) acc = acc + U[cell_elem(P, f0[0] + dx, f0[1] + dy, f0[2] + dz) + v * P.S];
+    U[e + v * Q.S] = acc / inv;
   }
 }
 
 // ---------------------------------------------------------------- launchers
-hipError_t launch_prolong(int grid, hipStream_t s, const ProlongOp* ops, int nops, const PatchDev* p, double* A,
+hipError_t launch_prolong(hipStream_t s, const ProlongOp* ops, const Work& w, const PatchDev* p, double* A,
                           const double* Cold, const double* Cnew, double alpha, int ndim) {
-  hipLaunchKernelGGL(prolong_ghosts, dim3(grid), dim3(NT), 0, s, ops, nops, p, A, Cold, Cnew, alpha, ndim);
+  hipLaunchKernelGGL(prolong_ghosts, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, A, Cold, Cnew, alpha, ndim);
   return hipGetLastError();
 }
-hipError_t launch_phys(int grid, hipStream_t s, const PhysOp* ops, int nops, const PatchDev* p, double* A) {
-  hipLaunchKernelGGL(fill_phys_ghosts, dim3(grid), dim3(NT), 0, s, ops, nops, p, A);
+hipError_t launch_phys(hipStream_t s, const PhysOp* ops, const Work& w, const PatchDev* p, double* A) {
+  hipLaunchKernelGGL(fill_phys_ghosts, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, A);
   return hipGetLastError();
 }
 hipError_t launch_copy_ranges(hipStream_t s, const int64_t* ranges, int nr, int64_t maxlen, const double* src,
@@ -234,16 +229,16 @@ hipError_t launch_copy_ranges(hipStream_t s, const int64_t* ranges, int nr, int6
   hipLaunchKernelGGL(copy_ranges, dim3(std::max(gx, 1), std::min(nr, 65535)), dim3(NT), 0, s, ranges, nr, src, dst);
   return hipGetLastError();
 }
-hipError_t launch_flux_fix(int mixed, int grid, hipStream_t s, const FixOp* ops, int nops, const PatchDev* p,
-                           double* U, const double* S1, const double* S2, const double* reg, const double* dtc,
-                           const Consts& C, int* flag) {
-  if (mixed) hipLaunchKernelGGL(flux_fix<float>, dim3(grid), dim3(NT), 0, s, ops, nops, p, U, S1, S2, reg, dtc, C, flag);
-  else hipLaunchKernelGGL(flux_fix<double>, dim3(grid), dim3(NT), 0, s, ops, nops, p, U, S1, S2, reg, dtc, C, flag);
+hipError_t launch_flux_fix(int mixed, hipStream_t s, const FixOp* ops, const Work& w, const PatchDev* p, double* U,
+                           const double* S1, const double* S2, const double* reg, const double* dtc, const Consts& C,
+                           int* flag) {
+  if (mixed) hipLaunchKernelGGL(flux_fix<float>, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, U, S1, S2, reg, dtc, C, flag);
+  else hipLaunchKernelGGL(flux_fix<double>, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, U, S1, S2, reg, dtc, C, flag);
   return hipGetLastError();
 }
-hipError_t launch_restrict(int grid, hipStream_t s, const RestrictOp* ops, int nops, const PatchDev* p, double* U,
+hipError_t launch_restrict(hipStream_t s, const RestrictOp* ops, const Work& w, const PatchDev* p, double* U,
                            int ndim) {
-  hipLaunchKernelGGL(restrict_cells, dim3(grid), dim3(NT), 0, s, ops, nops, p, U, ndim);
+  hipLaunchKernelGGL(restrict_cells, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, U, ndim);
   return hipGetLastError();
 }
 

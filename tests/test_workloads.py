@@ -1,0 +1,98 @@
+"""CPU checks of the deep-AMR Sedov set-up (the generator both sides share): the
+similarity solution against published constants and closed forms, the sampled
+initial state's totals, and the structure of the refinement hierarchy (nesting,
+patch sizes, coverage of the flagged shock)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_0910_5547_amd import workloads as W
+
+
+@pytest.mark.parametrize("gamma,xi0", [(5.0 / 3.0, 1.1517), (1.4, 1.0328)])
+def test_sedov_constant(gamma, xi0):
+    # the spherical blast-wave constant xi0 tabulated in the Sedov literature
+    # (e.g. Kamm & Timmes 2007): 1.15167 for gamma = 5/3, 1.03275 for gamma = 1.4
+    assert abs(W.SedovSolution(gamma).xi0 - xi0) < 2e-3
+
+
+def test_sedov_shock_jump_is_rankine_hugoniot():
+    g = 5.0 / 3.0
+    sol = W.SedovSolution(g)
+    E, t = 8.0, 0.05
+    R = sol.radius(E, t)
+    assert abs(R - 0.5267) < 1e-3
+    rho, v, p = sol.state(np.array([R * (1 - 1e-9)]), E, t, 1.0, 0.0)
+    # strong-shock limit: rho2 = (g+1)/(g-1) rho1, v2 = 2/(g+1) Ds, p2 = 2/(g+1) rho1 Ds^2
+    Ds = 0.4 * R / t
+    assert abs(rho[0] - (g + 1) / (g - 1)) < 1e-3
+    assert abs(v[0] - 2 / (g + 1) * Ds) < 1e-3 * Ds
+    assert abs(p[0] - 2 / (g + 1) * Ds ** 2) < 1e-3 * Ds ** 2
+    rho_out, v_out, p_out = sol.state(np.array([R * 1.01]), E, t, 1.0, 1e-5)
+    assert rho_out[0] == 1.0 and v_out[0] == 0.0 and p_out[0] == 1e-5
+
+
+def test_sedov_energy_integral():
+    # E = int (rho v^2/2 + p/(g-1)) dV over the sphere equals the blast energy
+    g = 5.0 / 3.0
+    sol = W.SedovSolution(g)
+    E, t = 8.0, 0.05
+    R = sol.radius(E, t)
+    r = np.linspace(0.0, R, 200001)[1:-1]
+    rho, v, p = sol.state(r, E, t, 1.0, 0.0)
+    f = (0.5 * rho * v * v + p / (g - 1)) * 4 * math.pi * r * r
+    assert abs(np.trapezoid(f, r) / E - 1.0) < 2e-3
+
+
+@pytest.fixture(scope="module")
+def hierarchy():
+    ps, _, _, _ = W.sedov_hierarchy(with_state=False)
+    return ps
+
+
+def test_sedov_hierarchy_shape(hierarchy):
+    ps = hierarchy
+    assert int(ps.level.max()) == 6
+    assert 5400 <= ps.npatch <= 6600
+    assert np.all(ps.n % 8 == 0) and ps.n.min() >= 8 and ps.n.max() <= 32
+    assert np.all(ps.lo % 8 == 0)
+
+
+def test_sedov_hierarchy_is_properly_nested_and_disjoint(hierarchy):
+    ps = hierarchy
+    root = 64
+    for l in range(1, int(ps.level.max()) + 1):
+        N = root << (l - 1)
+        cov = np.zeros((N // 8,) * 3, bool)  # level l-1 coverage in 8^3 bricks
+        for p in np.nonzero(ps.level == l - 1)[0]:
+            b0, b1 = ps.lo[p] // 8, (ps.lo[p] + ps.n[p]) // 8
+            cov[b0[2]:b1[2], b0[1]:b1[1], b0[0]:b1[0]] = True
+        fine = np.zeros((2 * N // 8,) * 3, np.int32)
+        for p in np.nonzero(ps.level == l)[0]:
+            lo, hi = ps.lo[p], ps.lo[p] + ps.n[p]
+            b0, b1 = lo // 8, hi // 8
+            fine[b0[2]:b1[2], b0[1]:b1[1], b0[0]:b1[0]] += 1
+            # footprint grown by one coarse cell, clipped to the domain, lies on level l-1
+            c0 = np.maximum(lo // 2 - 1, 0)
+            c1 = np.minimum((hi + 1) // 2 + 1, N)
+            assert cov[c0[2] // 8:(c1[2] - 1) // 8 + 1, c0[1] // 8:(c1[1] - 1) // 8 + 1,
+                       c0[0] // 8:(c1[0] - 1) // 8 + 1].all(), (l, p)
+        assert fine.max() <= 1, l  # patches of one level do not overlap
+
+
+def test_sedov_hierarchy_refines_the_shock_on_level_one(hierarchy):
+    # every root cell the shock passes through (its centre within half a root
+    # diagonal of the sphere r = R, away from the walls) is covered by level 1
+    ps = hierarchy
+    R = W.SedovSolution().radius(8.0, 0.05)
+    root = 64
+    c = (np.arange(root) + 0.5) / root
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    near = np.abs(np.sqrt(X * X + Y * Y + Z * Z) - R) < 0.5 / root
+    cov = np.zeros((2 * root,) * 3, bool)
+    for p in np.nonzero(ps.level == 1)[0]:
+        lo, hi = ps.lo[p], ps.lo[p] + ps.n[p]
+        cov[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = True
+    covered = cov[::2, ::2, ::2]
+    assert covered[near].all()
