@@ -134,11 +134,13 @@ def make_workload(name):
     return ps, U, desc, kw
 
 
-def time_hierarchy(A, torch, ps, U, precision, exec_form, steps, warmup, kw):
+def time_hierarchy(A, torch, ps, U, precision, exec_form, steps, warmup, kw, shape=None):
     """Root steps of a subcycled hierarchy: CFL reduction (all levels) + amr_hydro_advance.
     The stage split is not measured here (a root step launches every level's stages);
     stage_ms halves the whole step."""
     T = A.Table(ps, precision=precision, exec_form=exec_form, **kw)
+    if shape is not None:
+        A.amr_table_set_tiling(T.h, shape, 0)
     Ud = T.upload(U)
     for _ in range(warmup):
         A.amr_cfl_dt(T.h, Ud, 0.8, -1, T.dt)
@@ -155,18 +157,21 @@ def time_hierarchy(A, torch, ps, U, precision, exec_form, steps, warmup, kw):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     status = T.status()
+    tiling = A.amr_table_get_tiling(T.h)
     T.close()
     if status != A.AMR_OK:
         raise SystemExit(f"unphysical state during the benchmark: {A.amr_status_string(status)}")
     ms = 1e3 * wall / steps
     return {"ms_per_step": ms, "event_ms_per_step": e0.elapsed_time(e1) / steps, "stage_ms": [ms / 2, ms / 2],
-            "tiling": [1, 0]}
+            "tiling": list(tiling)}
 
 
-def time_form(A, torch, ps, U, precision, exec_form, steps, warmup, kw, tune=True):
+def time_form(A, torch, ps, U, precision, exec_form, steps, warmup, kw, tune=True, shape=None):
     if int(ps.level.max()) > 0:
-        return time_hierarchy(A, torch, ps, U, precision, exec_form, steps, warmup, kw)
+        return time_hierarchy(A, torch, ps, U, precision, exec_form, steps, warmup, kw, shape)
     T = A.Table(ps, precision=precision, exec_form=exec_form, **kw)
+    if shape is not None:
+        A.amr_table_set_tiling(T.h, shape, 0)
     Ud = T.upload(U)
     T.cfl_dt(Ud, 0.8)
     if tune:
@@ -251,6 +256,8 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="run the library's autotuner per form first (default: the library's default tiling)")
     ap.add_argument("--forms", default="plain_fp64,batched_fp64,batched_mixed")
+    ap.add_argument("--shape", type=int, default=None,
+                    help="tile shape id (default: the library's choice for the workload; --tune overrides)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration for --summarize-pmc)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -301,7 +308,7 @@ def main():
             # one launch per patch, stage, level substep: ~10^5 launches per root step
             steps, warmup = min(steps, 2), min(warmup, 1)
         log(f"form {name} ({steps} steps)")
-        r = time_form(A, torch, ps, U, prec, exe, steps, warmup, kw, tune=args.tune)
+        r = time_form(A, torch, ps, U, prec, exe, steps, warmup, kw, tune=args.tune, shape=args.shape)
         r["steps"] = steps
         r["value"] = cells / (r["ms_per_step"] * 1e-3)
         r["hbm_frac_step"] = BYTES_PER_CELL_STEP * cells / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBPS

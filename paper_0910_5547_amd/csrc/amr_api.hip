@@ -137,7 +137,7 @@ int auto_zslab(amr_table* t, int level, int shape) {
   }
   const int keep = t->shape;
   t->shape = shape;
-  const int64_t G = occupancy_grid(t, 2, 1 << 30);
+  const int64_t G = (int64_t)occupancy_grid(t, 2, 1 << 30) * shape_tiles_per_wg(shape);  // tiles in flight
   t->shape = keep;
   if (txy >= 4 * G) return nz;
   int64_t best = -1;
@@ -155,6 +155,25 @@ int auto_zslab(amr_table* t, int level, int shape) {
 }
 
 int default_zslab(const amr_table* t) { return t->ph.ndim == 3 ? 0 : 1; }  // 0 = auto_zslab
+
+// Default tile shape: 32 x 8 workgroup tiles, unless small patches would leave
+// more than half of their lanes idle; then 8 x 8 wavefront tiles, which fill every
+// lane of patches whose x-y extents are multiples of 8 (their larger halo share
+// makes them slower where the workgroup tiles are at least half full).
+int default_shape(const amr_table* t) {
+  if (t->ph.ndim == 1) return 0;
+  auto lane_use = [&](int shape) {
+    const int TX = SHAPE_TX[shape], TY = SHAPE_TY[shape];
+    double cols = 0, lanes = 0;
+    for (const PatchDev& P : t->pdev) {
+      cols += (double)P.n[0] * P.n[1] * P.n[2];
+      lanes += (double)((P.n[0] + TX - 1) / TX) * ((P.n[1] + TY - 1) / TY) * TX * TY * P.n[2];
+    }
+    return cols / lanes;
+  };
+  const double u1 = lane_use(1), us = lane_use(SHAPE_SMALL);
+  return (u1 < 0.5 && us > u1) ? SHAPE_SMALL : 1;
+}
 
 // Tile list of the patches of `level` (-1 = all) for a shape and z-slab length.
 amr_status get_tiles(amr_table* t, int level, int shape, int zslab, TileSet** out) {
@@ -191,14 +210,15 @@ amr_status get_tiles(amr_table* t, int level, int shape, int zslab, TileSet** ou
   ts.n = (int)list.size();
   if (ts.n > 0) {
     // The batched form's persistent workgroup b runs on XCD b % 8 (the dispatcher
-    // deals workgroups round-robin over the 8 XCDs) and walks positions b, b+G, ...
-    // (G, the grid, is a multiple of 8).  Split the list - in patch, z-slab, y, x
-    // order - into 8 contiguous chunks of equal cost and interleave them, so that
-    // every XCD works on one compact region and a tile's halo is its neighbours'
-    // interior in the same L2.  Within a chunk, longer tiles go first (LPT) so the
-    // workgroups finish together; equal-cost tiles keep their spatial order.
-    // The plain form uses the per-patch ranges of the unsorted list, kept as a
-    // second copy at the end of the same buffer.
+    // deals workgroups round-robin over the 8 XCDs) and walks groups b, b+G, ... of
+    // W consecutive positions (W tiles per workgroup; G, the grid, is a multiple of
+    // 8).  Split the list - in patch, z-slab, y, x order - into 8 contiguous chunks
+    // of equal cost and interleave them group by group, so that every XCD works on
+    // one compact region and a tile's halo is its neighbours' interior in the same
+    // L2.  Within a chunk, longer tiles go first (LPT) so the workgroups finish
+    // together; equal-cost tiles keep their spatial order.  The plain form uses the
+    // per-patch ranges of the unsorted list, kept as a second copy at the end of
+    // the same buffer.
     const int NX = 8;
     auto cost = [](const Tile& a) { return (int64_t)(a.z1 - a.z0) + 2; };
     int64_t total = 0;
@@ -215,11 +235,12 @@ amr_status get_tiles(amr_table* t, int level, int shape, int zslab, TileSet** ou
       std::stable_sort(c.begin(), c.end(), [&](const Tile& a, const Tile& b) { return cost(a) > cost(b); });
       longest = std::max(longest, c.size());
     }
+    const size_t W = (size_t)shape_tiles_per_wg(shape);
     std::vector<Tile> sorted;
     sorted.reserve(list.size());
-    for (size_t m = 0; m < longest; ++m)
+    for (size_t m = 0; m < longest; m += W)
       for (int c = 0; c < NX; ++c)
-        if (m < chunk[c].size()) sorted.push_back(chunk[c][m]);
+        for (size_t q = m; q < std::min(m + W, chunk[c].size()); ++q) sorted.push_back(chunk[c][q]);
     std::vector<Tile> both = sorted;
     both.insert(both.end(), list.begin(), list.end());
     if (hipMalloc(&ts.d, sizeof(Tile) * both.size()) != hipSuccess) return AMR_ENOMEM;
@@ -287,16 +308,17 @@ amr_status enqueue_stage(amr_table* t, TileSet* ts, int stage, const double* V, 
   a.smax = (stage == 2 && fuse) ? t->fused_d : nullptr;
   a.reg = rec ? t->reg : nullptr;
   a.c = consts_of(t);
+  const int W = shape_tiles_per_wg(t->shape);
   if (t->ph.exec == AMR_EXEC_BATCHED) {
     a.tiles = ts->d;
     a.ntiles = ts->n;
-    HIPCHECK(launch_stage(mixed, t->shape, stage, occupancy_grid(t, stage, ts->n), s, a));
+    HIPCHECK(launch_stage(mixed, t->shape, stage, occupancy_grid(t, stage, (ts->n + W - 1) / W), s, a));
   } else {
     for (size_t p = 0; p < t->pdev.size(); ++p) {
       if (ts->count[p] == 0) continue;
       a.tiles = ts->d + ts->n + ts->first[p];
       a.ntiles = ts->count[p];
-      HIPCHECK(launch_stage(mixed, t->shape, stage, ts->count[p], s, a));
+      HIPCHECK(launch_stage(mixed, t->shape, stage, (ts->count[p] + W - 1) / W, s, a));
     }
   }
   return AMR_OK;
@@ -965,7 +987,7 @@ amr_status amr_patch_table_create(const amr_patch_desc* patches, int32_t npatch,
   if (launch_fill_u64(stream, t->fused_d, MAX_LEVELS + 1, 0ull) != hipSuccess) return fail(AMR_EHIP);
   if (hipStreamSynchronize(stream) != hipSuccess) return fail(AMR_EHIP);
   if (hipStreamCreateWithFlags(&t->cap_stream, hipStreamNonBlocking) != hipSuccess) return fail(AMR_EHIP);
-  t->shape = phys->ndim == 1 ? 0 : 1;
+  t->shape = default_shape(t);
   t->zslab = default_zslab(t);
   *out = t;
   return AMR_OK;

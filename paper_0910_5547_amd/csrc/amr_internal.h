@@ -49,6 +49,13 @@ __device__ __forceinline__ void block_max_to(unsigned long long* dst, double v) 
   }
 }
 
+// Wavefront max of a non-negative double merged into *dst (no workgroup barrier).
+__device__ __forceinline__ void wave_max_to(unsigned long long* dst, double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0 && v > 0) atomicMax(dst, (unsigned long long)__double_as_longlong(v));
+}
+
 hipError_t launch_stage(int mixed, int shape, int stage, int grid, hipStream_t s, const StageArgs& a);
 const void* stage_kernel_ptr(int mixed, int shape, int stage);
 hipError_t launch_cfl(int grid, hipStream_t s, const CflArgs& a);
@@ -70,9 +77,13 @@ hipError_t launch_restrict(hipStream_t s, const RestrictOp* ops, const Work& w, 
                            int ndim);
 hipError_t launch_scale_dt(hipStream_t s, const double* dt0, double* dtl, int nlev);
 
-// Compiled tile shapes (TX x TY lanes = 256); shape 0 is the 1D shape.
+// Compiled tile shapes; shape 0 is the 1D shape.  TX x TY = 256 lanes: one tile
+// per workgroup; 8 x 8 (shape 4, small patches): one tile per wavefront, four per
+// workgroup.  Every shape has at most one halo cell and one edge face per lane.
 constexpr int NSHAPES = 5;
-constexpr int SHAPE_TX[NSHAPES] = {256, 32, 64, 16, 128};
-constexpr int SHAPE_TY[NSHAPES] = {1, 8, 4, 16, 2};
+constexpr int SHAPE_TX[NSHAPES] = {256, 32, 64, 16, 8};
+constexpr int SHAPE_TY[NSHAPES] = {1, 8, 4, 16, 8};
+constexpr int SHAPE_SMALL = 4;
+constexpr int shape_tiles_per_wg(int shape) { return NT / (SHAPE_TX[shape] * SHAPE_TY[shape]); }
 
 }  // namespace amr

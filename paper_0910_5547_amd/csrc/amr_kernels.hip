@@ -37,38 +37,54 @@ namespace amr {
 // instantiations (<= 168 VGPRs), two for FP64 (LDS-bound at two per CU anyway).
 // REC: record fine-face fluxes into the refluxing registers (patches of levels > 0).
 // TH1: the limiter parameter is 1 (the two-argument minmod, see plm_slope_t).
+// A tile of TX x TY = 256 columns is the whole workgroup's; a tile of 64 columns
+// (small patches) is one wavefront's, each of the four wavefronts walking its own
+// tiles and synchronising only with itself.
 template <typename RT, int TX, int TY, int STAGE, bool REC, bool TH1>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Fast<RT>::value ? 3 : 2)))
 void stage_kernel(StageArgs a) {
-  static_assert(TX * TY == NT, "one lane per column of the tile");
+  constexpr int TL = TX * TY;  // lanes (columns) per tile
+  static_assert(TL == NT || TL == 64, "a tile is the workgroup or one wavefront");
+  constexpr int WPB = NT / TL;  // tiles in flight per workgroup
   constexpr bool FAST = Fast<RT>::value;
   constexpr bool HASY = TY > 1;          // 1D tiles carry no y rows
   constexpr int PR = HASY ? TY + 4 : 1;  // LDS rows of the primitive plane
   constexpr int RO = HASY ? 2 : 0;       // row offset of tile row 0
   constexpr int YR = HASY ? TY + 1 : 1;  // y-face rows
-  constexpr int HMAX = HASY ? (4 * (TX + TY) + NT - 1) / NT : 1;  // halo cells per lane
+  constexpr int HMAX = HASY ? (4 * (TX + TY) + TL - 1) / TL : 1;  // halo cells per lane
   // face slots: x faces first, slot row*(nxT+1) + f, then y faces, slot nfx + f*nxT + col
   constexpr int NSLOT = TY * (TX + 1) + (HASY ? YR * TX : 0);
-  __shared__ RT sP[1][NVAR][PR][TX + 4];        // primitives of the plane (+ face halo)
-  __shared__ RT sFL[NVAR][NSLOT], sFR[NVAR][NSLOT];  // left/right face states; sFL then holds the flux
+  __shared__ RT sP[WPB][NVAR][PR][TX + 4];        // primitives of the plane (+ face halo)
+  __shared__ RT sFL[WPB][NVAR][NSLOT], sFR[WPB][NVAR][NSLOT];  // face states; sFL then holds the flux
   // conserved state of this lane's cell in planes k and k+1 (3D), for the update:
   // lane-private, kept in LDS rather than registers or a second read (FP32
-  // instantiations; the FP64 ones re-read the cell, their LDS budget being spent)
-  constexpr bool RING = FAST;
+  // instantiations with workgroup tiles; the others re-read the cell, their LDS
+  // budget being spent)
+  constexpr bool RING = FAST && WPB == 1;
   __shared__ double sV[RING ? 2 : 1][NVAR][RING ? NT : 1];
 
   const Consts C = a.c;
   const FaceConsts<RT> K{(RT)C.gamma, (RT)C.gm1, (RT)C.gg1};
   const RT theta = (RT)C.theta;
   const int kind = C.flux;
-  const int tid = threadIdx.x;
+  const int sub = WPB == 1 ? 0 : (int)threadIdx.x / TL;  // this lane's tile slot in the workgroup
+  const int tid = WPB == 1 ? (int)threadIdx.x : (int)threadIdx.x % TL;  // lane in the tile
   const int cx = tid % TX, cy = tid / TX;
+  auto tile_sync = [] {
+    if constexpr (WPB == 1) {
+      __syncthreads();
+    } else {  // one wavefront: its LDS operations complete in order
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  };
   const double dt = *a.dt;
   int bad = 0;
   double smax = 0.0;
-  constexpr int buf = 0;
+  const int buf = sub;
 
-  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+  for (int t = blockIdx.x * WPB + sub; t < a.ntiles; t += gridDim.x * WPB) {
     const Tile T = a.tiles[t];
     const PatchDev P = a.patches[T.patch];
     const int nxT = min(TX, P.n[0] - T.x0);
@@ -114,13 +130,13 @@ void stage_kernel(StageArgs a) {
       bad |= cons2prim<RT>(u, C, qz);
       if constexpr (RING) {
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) sV[T.z0 & 1][v][tid] = u[v];
+        for (int v = 0; v < NVAR; ++v) sV[T.z0 & 1][v][threadIdx.x] = u[v];
       }
       load_col(T.z0 + 1, u);
       bad |= cons2prim<RT>(u, C, qz1);
       if constexpr (RING) {
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) sV[(T.z0 + 1) & 1][v][tid] = u[v];
+        for (int v = 0; v < NVAR; ++v) sV[(T.z0 + 1) & 1][v][threadIdx.x] = u[v];
       }
       RT qL[NVAR], qR[NVAR];
 #pragma unroll
@@ -134,21 +150,12 @@ void stage_kernel(StageArgs a) {
     }
     // fine-face flux registers (Berger-Colella refluxing): faces on this patch's
     // boundary whose flux the coarse level must later see, dt/2 per stage
+    // (recorded in the update below, from the fluxes it reads anyway)
     const double hdt = 0.5 * dt;
     const bool rec = REC && P.level > 0;
-    const bool rec_xy = rec && ((T.x0 == 0 && P.reg[0] >= 0) || (T.x0 + nxT == P.n[0] && P.reg[1] >= 0) ||
-                                (hasy && T.y0 == 0 && P.reg[2] >= 0) ||
-                                (hasy && T.y0 + nyT == P.n[1] && P.reg[3] >= 0));
-    if (REC && hasz && act && rec && T.z0 == 0 && P.reg[4] >= 0) {
-#pragma unroll
-      for (int v = 0; v < NVAR; ++v) {
-        double* r = a.reg + P.reg[4] + ((int64_t)v * P.n[1] + j) * P.n[0] + i;
-        *r = *r + hdt * (double)Fzm[v];
-      }
-    }
 
     // Face halo of every plane: x halo = cols -2,-1,nxT,nxT+1 of every row, y halo =
-    // rows -2,-1,nyT,nyT+1 of every column.  Lane tid owns halo cells tid + s*NT; their
+    // rows -2,-1,nyT,nyT+1 of every column.  Lane tid owns halo cells tid + s*TL; their
     // conserved states are loaded one plane ahead so the loads' latency overlaps a
     // whole plane of work.
     const int nhx = 4 * nyT, nhy = hasy ? 4 * nxT : 0;
@@ -162,7 +169,7 @@ void stage_kernel(StageArgs a) {
     };
 #pragma unroll
     for (int s = 0; s < HMAX; ++s) {
-      const int h = tid + s * NT;
+      const int h = tid + s * TL;
       if (h < nhx) {
         hrow[s] = h >> 2;
         const int w = h & 3;
@@ -180,10 +187,46 @@ void stage_kernel(StageArgs a) {
       hbase[s] = P.off + (int64_t)P.g[2] * pstride + (int64_t)(jj + P.g[1]) * P.s[0] + (ii + P.g[0]);
       if (h < nhx + nhy) load_halo(s, T.z0, Hn[s]);
     }
-    // lane -> (row, column) of the flattened slope and face index spaces: exact
-    // float reciprocals (indices < 2^10, divisors <= 2^9) instead of integer division
-    const float r_x1 = 1.0f / (float)(nxT + 1), r_x2 = 1.0f / (float)(nxT + 2), r_x0 = 1.0f / (float)nxT;
-    auto idiv = [](int w, float r) { return (int)(((float)w + 0.5f) * r); };
+    // Per-lane work of the slope and face passes, fixed for the tile:
+    //  * the lane's own cell (active lanes): its x and y slopes, giving the right
+    //    state of its low faces and the left state of its high faces, then the flux
+    //    of its low x and low y faces;
+    //  * one halo cell beside the tile (lanes < nhs): its slope across that side,
+    //    giving the left state of the tile's first face or the right state of its
+    //    last one;
+    //  * one face on the tile's high x or high y edge (lanes < nfe).
+    // Face slots: x faces row * (nxT + 1) + f, then y faces nfx + f * nxT + col.
+    const int nfx = (nxT + 1) * nyT;
+    const int pc_own = (cy + RO) * (TX + 4) + cx + 2;
+    const int xs_own = cy * (nxT + 1) + cx, ys_own = nfx + cy * nxT + cx;
+    const int nhs = 2 * nyT + (HASY ? 2 * nxT : 0);
+    int pc_h = 0, st_h = 1, slot_h = 0;
+    bool left_h = false;
+    if (tid < nhs) {
+      if (tid < 2 * nyT) {  // columns -1 and nxT
+        const int row = tid >> 1, hi = tid & 1;
+        pc_h = (row + RO) * (TX + 4) + (hi ? nxT : -1) + 2;
+        slot_h = row * (nxT + 1) + (hi ? nxT : 0);
+        left_h = !hi;
+      } else {  // rows -1 and nyT
+        const int q = tid - 2 * nyT, col = q >> 1, hi = q & 1;
+        pc_h = ((hi ? nyT : -1) + RO) * (TX + 4) + col + 2;
+        st_h = TX + 4;
+        slot_h = nfx + (hi ? nyT : 0) * nxT + col;
+        left_h = !hi;
+      }
+    }
+    const int nfe = nyT + (HASY ? nxT : 0);
+    int slot_e = 0;
+    bool ydir_e = false;
+    if (tid < nfe) {
+      if (tid < nyT) {
+        slot_e = tid * (nxT + 1) + nxT;
+      } else {
+        slot_e = nfx + nyT * nxT + (tid - nyT);
+        ydir_e = true;
+      }
+    }
 
     for (int k = T.z0; k < T.z1; ++k) {
       // this step's HBM read first: plane k+2 of the column in 3D (consumed by the z
@@ -194,7 +237,7 @@ void stage_kernel(StageArgs a) {
       // halo of plane k (prefetched) into LDS, then prefetch the halo of plane k+1
 #pragma unroll
       for (int s = 0; s < HMAX; ++s) {
-        if (tid + s * NT < nhx + nhy) {
+        if (tid + s * TL < nhx + nhy) {
           RT q[NVAR];
           if (hflip[s] == 1) Hn[s][1] = -Hn[s][1];
           if (hflip[s] == 2) Hn[s][2] = -Hn[s][2];
@@ -222,7 +265,7 @@ void stage_kernel(StageArgs a) {
           bad |= cons2prim<RT>(Vn2, C, qc);
           if constexpr (RING) {
 #pragma unroll
-            for (int v = 0; v < NVAR; ++v) sV[k & 1][v][tid] = Vn2[v];
+            for (int v = 0; v < NVAR; ++v) sV[k & 1][v][threadIdx.x] = Vn2[v];
           }
         }
         if (act) {
@@ -230,98 +273,92 @@ void stage_kernel(StageArgs a) {
           for (int v = 0; v < NVAR; ++v) sP[buf][v][cy + RO][cx + 2] = qc[v];
         }
       }
-      __syncthreads();  // (A) plane primitives ready; previous plane's fluxes consumed
+      tile_sync();  // (A) plane primitives ready; previous plane's fluxes consumed
 
-      // (1) slopes, once per cell: x for cells -1..nxT of every row, y for rows -1..nyT of
-      // every column.  One code path for both: centre cell, neighbour stride, and the
-      // two face slots the cell's states go to (its low face's right state and its
-      // high face's left state).
-      const int nsx = (nxT + 2) * nyT, nsy = hasy ? nxT * (nyT + 2) : 0;
-      const int nfx = (nxT + 1) * nyT, nfy = hasy ? nxT * (nyT + 1) : 0;
-      for (int w = tid; w < nsx + nsy; w += NT) {
-        int pc, stride, slo, shi;  // LDS cell, stride to its neighbours, slots (-1: none)
-        if (w < nsx) {
-          const int row = idiv(w, r_x2), c = w - row * (nxT + 2) - 1;
-          pc = (row + RO) * (TX + 4) + c + 2;
-          stride = 1;
-          slo = c >= 0 ? row * (nxT + 1) + c : -1;
-          shi = c < nxT ? row * (nxT + 1) + c + 1 : -1;
-        } else {
-          const int w2 = w - nsx;
-          const int r = idiv(w2, r_x0) - 1, col = w2 - (r + 1) * nxT;
-          pc = (r + RO) * (TX + 4) + col + 2;
-          stride = TX + 4;
-          slo = r >= 0 ? nfx + r * nxT + col : -1;
-          shi = r < nyT ? nfx + (r + 1) * nxT + col : -1;
-        }
+      // (1) slopes, once per cell, as face states
+      if (act) {
 #pragma unroll
         for (int v = 0; v < NVAR; ++v) {
           const RT* pl = &sP[buf][v][0][0];
-          const RT qm = pl[pc - stride], q0 = pl[pc], qp = pl[pc + stride];
-          const RT sg = plm_slope_t<RT, TH1>(qm, q0, qp, theta);
-          if (slo >= 0) sFR[v][slo] = madd(RT(-0.5), sg, q0);  // right state of the cell's low face
-          if (shi >= 0) sFL[v][shi] = madd(RT(0.5), sg, q0);   // left state of its high face
+          const RT q0 = pl[pc_own];
+          const RT sx = plm_slope_t<RT, TH1>(pl[pc_own - 1], q0, pl[pc_own + 1], theta);
+          sFR[buf][v][xs_own] = madd(RT(-0.5), sx, q0);     // right state of its low x face
+          sFL[buf][v][xs_own + 1] = madd(RT(0.5), sx, q0);  // left state of its high x face
+          if constexpr (HASY) {
+            const RT sy = plm_slope_t<RT, TH1>(pl[pc_own - (TX + 4)], q0, pl[pc_own + (TX + 4)], theta);
+            sFR[buf][v][ys_own] = madd(RT(-0.5), sy, q0);
+            sFL[buf][v][ys_own + nxT] = madd(RT(0.5), sy, q0);
+          }
         }
       }
-      __syncthreads();  // (B) face states ready
+      if (tid < nhs) {
+        RT* dst = left_h ? &sFL[buf][0][slot_h] : &sFR[buf][0][slot_h];
+        const RT hs = left_h ? RT(0.5) : RT(-0.5);
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) {
+          const RT* pl = &sP[buf][v][0][0];
+          const RT q0 = pl[pc_h];
+          const RT sg = plm_slope_t<RT, TH1>(pl[pc_h - st_h], q0, pl[pc_h + st_h], theta);
+          dst[v * NSLOT] = madd(hs, sg, q0);
+        }
+      }
+      tile_sync();  // (B) face states ready
 
-      // the stage input (from the lane's LDS ring; FP64 instantiations re-read it) and
-      // (stage 2) U^n of this cell, for the update: read here so the face pass hides
-      // the latency
+      // the stage input of this cell (from the lane's LDS ring, else re-read) and, in
+      // stage 2, U^n: the global loads are issued before the face pass so that it
+      // hides their latency (wavefront tiles, short of VGPRs, issue them after it)
       double Vc[NVAR], U0c[NVAR];
       const int64_t ecell = col0 + (int64_t)k * pstride;
-      {
-        const int64_t e = ecell;
-        if constexpr (RING) {
-#pragma unroll
-          for (int v = 0; v < NVAR; ++v) Vc[v] = sV[k & 1][v][tid];
-        } else {
-#pragma unroll
-          for (int v = 0; v < NVAR; ++v) Vc[v] = a.V[e + v * P.S];
-        }
+      auto load_u0 = [&] {
         if (STAGE == 2) {
 #pragma unroll
-          for (int v = 0; v < NVAR; ++v) U0c[v] = a.U0[e + v * P.S];
+          for (int v = 0; v < NVAR; ++v) U0c[v] = a.U0[ecell + v * P.S];
         }
+      };
+      auto load_vc = [&] {
+        if constexpr (RING) {
+#pragma unroll
+          for (int v = 0; v < NVAR; ++v) Vc[v] = sV[k & 1][v][threadIdx.x];
+        } else {
+#pragma unroll
+          for (int v = 0; v < NVAR; ++v) Vc[v] = a.V[ecell + v * P.S];
+        }
+      };
+      if constexpr (WPB == 1) {
+        load_u0();
+        if constexpr (!RING) load_vc();
       }
 
       // (2) every x- and y-face flux of the block, once, written over its left state
-      for (int w = tid; w < nfx + nfy; w += NT) {
-        RT qL[NVAR], qR[NVAR], F[NVAR];
+      auto face_at = [&](int slot, RT qL[NVAR], RT qR[NVAR]) {
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) { qL[v] = sFL[v][w]; qR[v] = sFR[v][w]; }
-        riemann_flux_xy<RT>(qL, qR, w >= nfx, K, kind, F);
-#pragma unroll
-        for (int v = 0; v < NVAR; ++v) sFL[v][w] = F[v];
-        if (REC && rec_xy) {
-          int64_t base = -1, stride = 0;
-          // (constant indices into P: a runtime index would move P to scratch memory)
-          if (w < nfx) {
-            const int row = idiv(w, r_x1), f = w - row * (nxT + 1);
-            const int gi = T.x0 + f, gj = T.y0 + row;
-            const int64_t rg = gi == 0 ? P.reg[0] : (gi == P.n[0] ? P.reg[1] : -1);
-            if (rg >= 0) {
-              base = rg + (int64_t)k * P.n[1] + gj;
-              stride = (int64_t)P.n[2] * P.n[1];
-            }
-          } else {
-            const int w2 = w - nfx;
-            const int f = idiv(w2, r_x0), col = w2 - f * nxT;
-            const int gj = T.y0 + f, gi = T.x0 + col;
-            const int64_t rg = gj == 0 ? P.reg[2] : (gj == P.n[1] ? P.reg[3] : -1);
-            if (rg >= 0) {
-              base = rg + (int64_t)k * P.n[0] + gi;
-              stride = (int64_t)P.n[2] * P.n[0];
-            }
-          }
-          if (base >= 0) {
-#pragma unroll
-            for (int v = 0; v < NVAR; ++v) {
-              double* r = a.reg + base + v * stride;
-              *r = *r + hdt * (double)F[v];
-            }
-          }
+        for (int v = 0; v < NVAR; ++v) {
+          qL[v] = sFL[buf][v][slot];
+          qR[v] = sFR[buf][v][slot];
         }
+      };
+      if (act) {
+        RT qL[NVAR], qR[NVAR], F[NVAR];
+        face_at(xs_own, qL, qR);
+        riemann_flux<RT, 0>(qL, qR, K, kind, F);
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) sFL[buf][v][xs_own] = F[v];
+        if constexpr (HASY) {
+          face_at(ys_own, qL, qR);
+          // (the x-frame evaluation, as for every y face: riemann_flux<RT, 1> sums the
+          // kinetic energy in another order, and in the mixed path its FP32 rounding
+          // would differ from the coarse level's recomputed flux in refluxing)
+          riemann_flux_xy<RT>(qL, qR, true, K, kind, F);
+#pragma unroll
+          for (int v = 0; v < NVAR; ++v) sFL[buf][v][ys_own] = F[v];
+        }
+      }
+      if (tid < nfe) {
+        RT qL[NVAR], qR[NVAR], F[NVAR];
+        face_at(slot_e, qL, qR);
+        riemann_flux_xy<RT>(qL, qR, ydir_e, K, kind, F);
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) sFL[buf][v][slot_e] = F[v];
       }
       // z-face flux F_{k+1/2} of this column from the register queue
       RT Fzp[NVAR], qn2[NVAR], sg1[NVAR];
@@ -336,41 +373,61 @@ void stage_kernel(StageArgs a) {
           qR[v] = madd(RT(-0.5), sg1[v], qz1[v]);
         }
         riemann_flux<RT, 2>(qL, qR, K, kind, Fzp);
-        if (REC && act && rec && k == P.n[2] - 1 && P.reg[5] >= 0) {
-#pragma unroll
-          for (int v = 0; v < NVAR; ++v) {
-            double* r = a.reg + P.reg[5] + ((int64_t)v * P.n[1] + j) * P.n[0] + i;
-            *r = *r + hdt * (double)Fzp[v];
-          }
-        }
       }
-      __syncthreads();  // (C) fluxes ready
+      tile_sync();  // (C) fluxes ready
+      if constexpr (WPB > 1) {
+        load_u0();
+        load_vc();
+      } else if constexpr (RING) {
+        load_vc();
+      }
 
-      // (3) L(U) in the order x, y, z, then the TVD-RK2 stage combine
+      // (3) L(U) in the order x, y, z, then the TVD-RK2 stage combine; fluxes of
+      // this cell's faces on a coarse/fine boundary of the patch also go to the
+      // refluxing registers (+= dt/2 F, Berger-Colella)
       {
         double L[NVAR];
-        const int sx = cy * (nxT + 1) + cx, sy = nfx + cy * nxT + cx;
+        const int sx = xs_own, sy = ys_own;
+        // at most one x, one y and one z face of this cell lies on a recorded patch
+        // face (patches of a refined level are at least 2 cells wide); register
+        // elements [v][k][j] (x faces), [v][k][i] (y faces), [v][j][i] (z faces)
+        // (constant indices into P: a runtime index would move P to scratch memory)
+        int64_t rx = -1, ry = -1, rz = -1;
+        if (REC && rec && act) {
+          rx = i == 0 ? P.reg[0] : (i == P.n[0] - 1 ? P.reg[1] : -1);
+          if (hasy) ry = j == 0 ? P.reg[2] : (j == P.n[1] - 1 ? P.reg[3] : -1);
+          if (hasz) rz = k == 0 ? P.reg[4] : (k == P.n[2] - 1 ? P.reg[5] : -1);
+        }
+        auto record = [&](int64_t e, double F) {
+          double* r = a.reg + e;
+          *r = *r + hdt * F;
+        };
 #pragma unroll
         for (int v = 0; v < NVAR; ++v) {
-          const double d = (double)sFL[v][sx + 1] - (double)sFL[v][sx];
+          const double fl = (double)sFL[buf][v][sx], fh = (double)sFL[buf][v][sx + 1];
+          const double d = fh - fl;
           if constexpr (FAST) L[v] = -d * P.rdx[0];
           else L[v] = 0.0 - d / P.dx[0];
+          if (REC && rx >= 0) record(rx + ((int64_t)v * P.n[2] + k) * P.n[1] + j, i == 0 ? fl : fh);
         }
         if (hasy) {
 #pragma unroll
           for (int v = 0; v < NVAR; ++v) {
-            const double d = (double)sFL[v][sy + nxT] - (double)sFL[v][sy];
+            const double fl = (double)sFL[buf][v][sy], fh = (double)sFL[buf][v][sy + nxT];
+            const double d = fh - fl;
             if constexpr (FAST) L[v] = fma(-d, P.rdx[1], L[v]);
             else L[v] = L[v] - d / P.dx[1];
+            if (REC && ry >= 0) record(ry + ((int64_t)v * P.n[2] + k) * P.n[0] + i, j == 0 ? fl : fh);
           }
         }
         if (hasz) {
 #pragma unroll
           for (int v = 0; v < NVAR; ++v) {
+            if (REC && rz >= 0) record(rz + ((int64_t)v * P.n[1] + j) * P.n[0] + i, (double)(k == 0 ? Fzm[v] : Fzp[v]));
             const double d = (double)Fzp[v] - (double)Fzm[v];
             if constexpr (FAST) L[v] = fma(-d, P.rdx[2], L[v]);
             else L[v] = L[v] - d / P.dx[2];
-            if constexpr (RING) sV[k & 1][v][tid] = Vn2[v];  // plane k+2 takes plane k's slot
+            if constexpr (RING) sV[k & 1][v][threadIdx.x] = Vn2[v];  // plane k+2 takes plane k's slot
             qz[v] = qz1[v];
             qz1[v] = qn2[v];
             sgz[v] = sg1[v];
@@ -395,7 +452,8 @@ void stage_kernel(StageArgs a) {
       }
     }
     if (STAGE == 2 && a.smax != nullptr) {  // fused next-dt reduction, per level
-      block_max_to(a.smax + P.level, smax);
+      if constexpr (WPB == 1) block_max_to(a.smax + P.level, smax);
+      else wave_max_to(a.smax + P.level, smax);
       smax = 0.0;
     }
   }
@@ -506,7 +564,7 @@ static hipError_t launch_stage_rt(int shape, int stage, dim3 grid, hipStream_t s
     case 1: return launch_stage_s<RT, 32, 8>(stage, grid, s, a);
     case 2: return launch_stage_s<RT, 64, 4>(stage, grid, s, a);
     case 3: return launch_stage_s<RT, 16, 16>(stage, grid, s, a);
-    case 4: return launch_stage_s<RT, 128, 2>(stage, grid, s, a);
+    case 4: return launch_stage_s<RT, 8, 8>(stage, grid, s, a);
     default: return hipErrorInvalidValue;
   }
 }
@@ -527,7 +585,7 @@ const void* stage_kernel_ptr(int mixed, int shape, int stage) {
       case 1: return AMR_KP(float, 32, 8);
       case 2: return AMR_KP(float, 64, 4);
       case 3: return AMR_KP(float, 16, 16);
-      case 4: return AMR_KP(float, 128, 2);
+      case 4: return AMR_KP(float, 8, 8);
     }
   } else {
     switch (shape) {
@@ -535,7 +593,7 @@ const void* stage_kernel_ptr(int mixed, int shape, int stage) {
       case 1: return AMR_KP(double, 32, 8);
       case 2: return AMR_KP(double, 64, 4);
       case 3: return AMR_KP(double, 16, 16);
-      case 4: return AMR_KP(double, 128, 2);
+      case 4: return AMR_KP(double, 8, 8);
     }
   }
 #undef AMR_KP

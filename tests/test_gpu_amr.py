@@ -35,10 +35,12 @@ def env():
     return torch, A, O
 
 
-def run_pair(env, case, steps, prec=0, exe=1):
+def run_pair(env, case, steps, prec=0, exe=1, shape=None):
     torch, A, O = env
     ps, U, per, dom = CASES[case]()
     T = A.Table(ps, precision=prec, exec_form=exe, periodic=per, domain=dom)
+    if shape is not None:
+        A.amr_table_set_tiling(T.h, shape, 0)
     Ud = T.upload(U)
     o = O.AmrOracle(ps, periodic=per, domain=dom)
     Uo = U.copy()
@@ -55,14 +57,17 @@ def run_pair(env, case, steps, prec=0, exe=1):
     return ps, U, Ug, Uo
 
 
-@pytest.mark.parametrize("exe", [1, 0])
+@pytest.mark.parametrize("exe,shape", [(1, None), (0, None), (1, 1), (1, 4)])
 @pytest.mark.parametrize("case", list(CASES))
-def test_hierarchy_fp64_matches_oracle(env, case, exe):
-    log(f"case amr {case} fp64 exec={exe}")
-    ps, U0, Ug, Uo = run_pair(env, case, 3, prec=0, exe=exe)
+def test_hierarchy_fp64_matches_oracle(env, case, exe, shape):
+    """shape None: the library's default tiling; 1 and 4: workgroup and wavefront tiles."""
+    if shape is not None and case.endswith("1d"):
+        pytest.skip("1D tables have the one 1D tiling")
+    log(f"case amr {case} fp64 exec={exe} shape={shape}")
+    ps, U0, Ug, Uo = run_pair(env, case, 3, prec=0, exe=exe, shape=shape)
     g, r = active_all(ps, Ug), active_all(ps, Uo)
     e = rel_err(g, r)
-    log(f"{case} exec={exe}: rel err {['%.1e' % x for x in e]} bitwise={np.array_equal(g, r)}")
+    log(f"{case} exec={exe} shape={shape}: rel err {['%.1e' % x for x in e]} bitwise={np.array_equal(g, r)}")
     assert max(e) <= 1e-12, e
     t0 = W.composite_totals(ps, U0)
     sc = W.composite_totals(ps, np.abs(U0))
@@ -70,10 +75,13 @@ def test_hierarchy_fp64_matches_oracle(env, case, exe):
     assert np.all(np.abs(t1 - t0) <= 1e-12 * sc), (t1 - t0) / sc
 
 
+@pytest.mark.parametrize("shape", [None, 1, 4])
 @pytest.mark.parametrize("case", list(CASES))
-def test_hierarchy_mixed(env, case):
-    log(f"case amr {case} mixed")
-    ps, U0, Ug, Uo = run_pair(env, case, 3, prec=1)
+def test_hierarchy_mixed(env, case, shape):
+    if shape is not None and case.endswith("1d"):
+        pytest.skip("1D tables have the one 1D tiling")
+    log(f"case amr {case} mixed shape={shape}")
+    ps, U0, Ug, Uo = run_pair(env, case, 3, prec=1, shape=shape)
     g, r = active_all(ps, Ug), active_all(ps, Uo)
     l1 = l1_rel(g, r)
     log(f"{case} mixed: L1(rho) {l1:.2e}")
