@@ -70,7 +70,7 @@ struct amr_table {
   // fused dt bookkeeping
   const double* fused_U = nullptr;
   int fused_level = -2;
-  int occ[2][NSHAPES][2] = {};  // resident stage workgroups per CU
+  int occ[2][NSHAPES][2][2] = {};  // resident stage workgroups per CU: [mixed][shape][stage][recording]
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // AMR_STEP_TIMED: before/between/after the stages
   bool timed_valid = false;
   // ---- hierarchy (levels > 0 present): coarse/fine coupling plans, see build_hierarchy
@@ -119,7 +119,7 @@ bool shape_valid(int ndim, int shape) {
   return ndim == 1 ? shape == 0 : shape != 0;
 }
 
-int occupancy_grid(amr_table* t, int stage, int ntiles);
+int occupancy_grid(amr_table* t, int stage, int ntiles, bool rec);
 
 // z-slab length that balances the persistent launch: per-tile time is taken as
 // proportional to its planes + 4 (the z prologue reads 4 planes); with T_xy column
@@ -137,7 +137,8 @@ int auto_zslab(amr_table* t, int level, int shape) {
   }
   const int keep = t->shape;
   t->shape = shape;
-  const int64_t G = (int64_t)occupancy_grid(t, 2, 1 << 30) * shape_tiles_per_wg(shape);  // tiles in flight
+  const bool rec = level > 0 && t->reg != nullptr;
+  const int64_t G = (int64_t)occupancy_grid(t, 2, 1 << 30, rec) * shape_tiles_per_wg(shape);  // tiles in flight
   t->shape = keep;
   if (txy >= 4 * G) return nz;
   int64_t best = -1;
@@ -265,13 +266,14 @@ Consts consts_of(const amr_table* t) {
 }
 
 // Resident workgroups per CU of the stage kernel in use (queried once per
-// (precision, shape, stage), outside any graph capture).
-int occupancy_grid(amr_table* t, int stage, int ntiles) {
+// (precision, shape, stage, recording), outside any graph capture); the grid of a
+// persistent launch, no larger than what is resident at once.
+int occupancy_grid(amr_table* t, int stage, int ntiles, bool rec) {
   if (ntiles < 1) ntiles = 1;
   const int mixed = t->ph.precision == AMR_PREC_MIXED;
-  int& per_cu = t->occ[mixed][t->shape][stage - 1];
+  int& per_cu = t->occ[mixed][t->shape][stage - 1][rec ? 1 : 0];
   if (per_cu <= 0) {
-    const void* k = stage_kernel_ptr(mixed, t->shape, stage);
+    const void* k = stage_kernel_ptr(mixed, t->shape, stage, rec);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, NT, 0) != hipSuccess || per_cu < 1) per_cu = 1;
   }
   const int g = std::max(1, std::min(ntiles, per_cu * t->ncu));
@@ -312,7 +314,7 @@ amr_status enqueue_stage(amr_table* t, TileSet* ts, int stage, const double* V, 
   if (t->ph.exec == AMR_EXEC_BATCHED) {
     a.tiles = ts->d;
     a.ntiles = ts->n;
-    HIPCHECK(launch_stage(mixed, t->shape, stage, occupancy_grid(t, stage, (ts->n + W - 1) / W), s, a));
+    HIPCHECK(launch_stage(mixed, t->shape, stage, occupancy_grid(t, stage, (ts->n + W - 1) / W, rec), s, a));
   } else {
     for (size_t p = 0; p < t->pdev.size(); ++p) {
       if (ts->count[p] == 0) continue;
@@ -1041,8 +1043,10 @@ amr_status amr_hydro_rk2_step(amr_table* t, double* U, const double* dt_dev, int
       TileSet* ts = nullptr;
       amr_status st = get_tiles(t, level, t->shape, t->zslab, &ts);
       if (st != AMR_OK) return st;
-      occupancy_grid(t, 1, ts->n);
-      occupancy_grid(t, 2, ts->n);
+      for (bool r : {false, true}) {
+        occupancy_grid(t, 1, ts->n, r);
+        occupancy_grid(t, 2, ts->n, r);
+      }
       HIPCHECK(hipStreamBeginCapture(t->cap_stream, hipStreamCaptureModeThreadLocal));
       st = enqueue_step(t, U, dt_dev, level, flags, t->cap_stream, nullptr, substep);
       hipGraph_t graph = nullptr;
@@ -1140,8 +1144,10 @@ amr_status amr_hydro_advance(amr_table* t, double* U, const double* dt0_dev, uin
     TileSet* ts = nullptr;
     amr_status st = get_tiles(t, l, t->shape, t->zslab, &ts);
     if (st != AMR_OK) return st;
-    occupancy_grid(t, 1, ts->n);
-    occupancy_grid(t, 2, ts->n);
+    for (bool r : {false, true}) {
+      occupancy_grid(t, 1, ts->n, r);
+      occupancy_grid(t, 2, ts->n, r);
+    }
   }
   if (t->ph.exec == AMR_EXEC_BATCHED) {
     GraphCache& g = t->gadv;

@@ -57,7 +57,7 @@ __device__ __forceinline__ void wave_max_to(unsigned long long* dst, double v) {
 }
 
 hipError_t launch_stage(int mixed, int shape, int stage, int grid, hipStream_t s, const StageArgs& a);
-const void* stage_kernel_ptr(int mixed, int shape, int stage);
+const void* stage_kernel_ptr(int mixed, int shape, int stage, bool rec);
 hipError_t launch_cfl(int grid, hipStream_t s, const CflArgs& a);
 hipError_t launch_cfl_finalize(hipStream_t s, const unsigned long long* smax, int lmin, int lmax, int root,
                                double cfl, double* dt);

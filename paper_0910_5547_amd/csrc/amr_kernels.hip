@@ -41,7 +41,7 @@ namespace amr {
 // (small patches) is one wavefront's, each of the four wavefronts walking its own
 // tiles and synchronising only with itself.
 template <typename RT, int TX, int TY, int STAGE, bool REC, bool TH1>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Fast<RT>::value ? 3 : 2)))
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Fast<RT>::value && !REC ? 3 : 2)))
 void stage_kernel(StageArgs a) {
   constexpr int TL = TX * TY;  // lanes (columns) per tile
   static_assert(TL == NT || TL == 64, "a tile is the workgroup or one wavefront");
@@ -574,11 +574,14 @@ hipError_t launch_stage(int mixed, int shape, int stage, int grid, hipStream_t s
   return launch_stage_rt<double>(shape, stage, dim3(grid), s, a);
 }
 
-// The non-recording, theta = 1 instantiation (the others share its resource class).
-const void* stage_kernel_ptr(int mixed, int shape, int stage) {
-#define AMR_KP(RT, TX, TY)                                                                          \
-  (stage == 1 ? reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, 1, false, true>)            \
-              : reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, 2, false, true>))
+// The theta = 1 instantiation with or without register recording (the theta
+// instantiations share a resource class; the recording ones have their own).
+const void* stage_kernel_ptr(int mixed, int shape, int stage, bool rec) {
+#define AMR_KP(RT, TX, TY)                                                                               \
+  (stage == 1 ? (rec ? reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, 1, true, true>)           \
+                     : reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, 1, false, true>))         \
+              : (rec ? reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, 2, true, true>)           \
+                     : reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, 2, false, true>)))
   if (mixed) {
     switch (shape) {
       case 0: return AMR_KP(float, 256, 1);
