@@ -174,7 +174,7 @@ def time_form(A, torch, ps, U, precision, exec_form, steps, warmup, kw, tune=Tru
         A.amr_table_set_tiling(T.h, shape, 0)
     Ud = T.upload(U)
     T.cfl_dt(Ud, 0.8)
-    if tune:
+    if tune and shape is None:
         ms = A.amr_autotune(T.h, Ud, T.dt, -1, 3)
         log(f"  autotune: best {A.amr_table_get_tiling(T.h)} at {ms:.3f} ms/step")
     fuse = A.AMR_STEP_FUSE_DT
@@ -253,8 +253,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="box256")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--tune", action="store_true",
-                    help="run the library's autotuner per form first (default: the library's default tiling)")
+    ap.add_argument("--no-tune", dest="tune", action="store_false",
+                    help="skip the library's autotuner (tile shape and z-slab) and keep its default tiling")
     ap.add_argument("--forms", default="plain_fp64,batched_fp64,batched_mixed")
     ap.add_argument("--shape", type=int, default=None,
                     help="tile shape id (default: the library's choice for the workload; --tune overrides)")

@@ -138,7 +138,11 @@ int auto_zslab(amr_table* t, int level, int shape) {
   const int keep = t->shape;
   t->shape = shape;
   const bool rec = level > 0 && t->reg != nullptr;
-  const int64_t G = (int64_t)occupancy_grid(t, 2, 1 << 30, rec) * shape_tiles_per_wg(shape);  // tiles in flight
+  // tiles in flight, counted at no more than two workgroups per CU: beyond that the
+  // co-resident tiles' halo rows (the neighbours' interiors) no longer stay in the
+  // XCD's L2 between the two reads (on the 256^3 box two slabs of 128 planes beat
+  // three of 86 although three fill every resident slot)
+  const int64_t G = (int64_t)std::min(occupancy_grid(t, 2, 1 << 30, rec), 2 * t->ncu) * shape_tiles_per_wg(shape);
   t->shape = keep;
   if (txy >= 4 * G) return nz;
   int64_t best = -1;
@@ -274,7 +278,8 @@ int occupancy_grid(amr_table* t, int stage, int ntiles, bool rec) {
   int& per_cu = t->occ[mixed][t->shape][stage - 1][rec ? 1 : 0];
   if (per_cu <= 0) {
     const void* k = stage_kernel_ptr(mixed, t->shape, stage, rec);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, NT, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, SHAPE_NT[t->shape], 0) != hipSuccess || per_cu < 1)
+      per_cu = 1;
   }
   const int g = std::max(1, std::min(ntiles, per_cu * t->ncu));
   return g >= 8 ? g / 8 * 8 : g;  // a multiple of the XCD count (tile list interleave)

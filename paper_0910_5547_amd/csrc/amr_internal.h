@@ -35,7 +35,7 @@ struct CflArgs {
 // Block-wide max of a non-negative double merged into *dst with a 64-bit
 // atomicMax on its bit pattern.  Must be called by every lane of the block.
 __device__ __forceinline__ void block_max_to(unsigned long long* dst, double v) {
-  __shared__ double red[NT / 64];
+  __shared__ double red[16];  // one per wavefront, up to 1024 threads
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -77,13 +77,16 @@ hipError_t launch_restrict(hipStream_t s, const RestrictOp* ops, const Work& w, 
                            int ndim);
 hipError_t launch_scale_dt(hipStream_t s, const double* dt0, double* dtl, int nlev);
 
-// Compiled tile shapes; shape 0 is the 1D shape.  TX x TY = 256 lanes: one tile
-// per workgroup; 8 x 8 (shape 4, small patches): one tile per wavefront, four per
-// workgroup.  Every shape has at most one halo cell and one edge face per lane.
-constexpr int NSHAPES = 5;
-constexpr int SHAPE_TX[NSHAPES] = {256, 32, 64, 16, 8};
-constexpr int SHAPE_TY[NSHAPES] = {1, 8, 4, 16, 8};
+// Compiled tile shapes; shape 0 is the 1D shape.  TX x TY = workgroup size: one
+// tile per workgroup (256 threads; 512 for 32 x 16, shape 5, which halves the
+// y-halo share of a tile); 8 x 8 (shape 4, small patches): one tile per
+// wavefront, four per workgroup.  Every shape has at most one halo cell and one
+// edge face per lane.
+constexpr int NSHAPES = 6;
+constexpr int SHAPE_TX[NSHAPES] = {256, 32, 64, 16, 8, 32};
+constexpr int SHAPE_TY[NSHAPES] = {1, 8, 4, 16, 8, 16};
+constexpr int SHAPE_NT[NSHAPES] = {256, 256, 256, 256, 256, 512};
 constexpr int SHAPE_SMALL = 4;
-constexpr int shape_tiles_per_wg(int shape) { return NT / (SHAPE_TX[shape] * SHAPE_TY[shape]); }
+constexpr int shape_tiles_per_wg(int shape) { return SHAPE_NT[shape] / (SHAPE_TX[shape] * SHAPE_TY[shape]); }
 
 }  // namespace amr

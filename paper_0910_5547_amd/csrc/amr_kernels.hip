@@ -40,12 +40,14 @@ namespace amr {
 // A tile of TX x TY = 256 columns is the whole workgroup's; a tile of 64 columns
 // (small patches) is one wavefront's, each of the four wavefronts walking its own
 // tiles and synchronising only with itself.
-template <typename RT, int TX, int TY, int STAGE, bool REC, bool TH1>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Fast<RT>::value && !REC ? 3 : 2)))
+// NTH: threads per workgroup (256, or 512 for the 32 x 16 tile, whose LDS allows one
+// workgroup per CU).
+template <typename RT, int TX, int TY, int NTH, int STAGE, bool REC, bool TH1>
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(Fast<RT>::value && !REC && NTH == 256 ? 3 : 2)))
 void stage_kernel(StageArgs a) {
   constexpr int TL = TX * TY;  // lanes (columns) per tile
-  static_assert(TL == NT || TL == 64, "a tile is the workgroup or one wavefront");
-  constexpr int WPB = NT / TL;  // tiles in flight per workgroup
+  static_assert(TL == NTH || TL == 64, "a tile is the workgroup or one wavefront");
+  constexpr int WPB = NTH / TL;  // tiles in flight per workgroup
   constexpr bool FAST = Fast<RT>::value;
   constexpr bool HASY = TY > 1;          // 1D tiles carry no y rows
   constexpr int PR = HASY ? TY + 4 : 1;  // LDS rows of the primitive plane
@@ -61,7 +63,7 @@ void stage_kernel(StageArgs a) {
   // instantiations with workgroup tiles; the others re-read the cell, their LDS
   // budget being spent)
   constexpr bool RING = FAST && WPB == 1;
-  __shared__ double sV[RING ? 2 : 1][NVAR][RING ? NT : 1];
+  __shared__ double sV[RING ? 2 : 1][NVAR][RING ? NTH : 1];
 
   const Consts C = a.c;
   const FaceConsts<RT> K{(RT)C.gamma, (RT)C.gm1, (RT)C.gg1};
@@ -539,22 +541,22 @@ __global__ void fill_i32(int* p, int n, int v) {
 }
 
 // ------------------------------------------------------------------ launchers
-template <typename RT, int TX, int TY, int STAGE>
+template <typename RT, int TX, int TY, int NTH, int STAGE>
 static hipError_t launch_stage_t(dim3 grid, hipStream_t s, const StageArgs& a) {
   const bool th1 = a.c.theta == 1.0;
   if (a.reg) {
-    if (th1) hipLaunchKernelGGL((stage_kernel<RT, TX, TY, STAGE, true, true>), grid, dim3(NT), 0, s, a);
-    else hipLaunchKernelGGL((stage_kernel<RT, TX, TY, STAGE, true, false>), grid, dim3(NT), 0, s, a);
+    if (th1) hipLaunchKernelGGL((stage_kernel<RT, TX, TY, NTH, STAGE, true, true>), grid, dim3(NTH), 0, s, a);
+    else hipLaunchKernelGGL((stage_kernel<RT, TX, TY, NTH, STAGE, true, false>), grid, dim3(NTH), 0, s, a);
   } else {
-    if (th1) hipLaunchKernelGGL((stage_kernel<RT, TX, TY, STAGE, false, true>), grid, dim3(NT), 0, s, a);
-    else hipLaunchKernelGGL((stage_kernel<RT, TX, TY, STAGE, false, false>), grid, dim3(NT), 0, s, a);
+    if (th1) hipLaunchKernelGGL((stage_kernel<RT, TX, TY, NTH, STAGE, false, true>), grid, dim3(NTH), 0, s, a);
+    else hipLaunchKernelGGL((stage_kernel<RT, TX, TY, NTH, STAGE, false, false>), grid, dim3(NTH), 0, s, a);
   }
   return hipGetLastError();
 }
 
-template <typename RT, int TX, int TY>
+template <typename RT, int TX, int TY, int NTH = NT>
 static hipError_t launch_stage_s(int stage, dim3 grid, hipStream_t s, const StageArgs& a) {
-  return stage == 1 ? launch_stage_t<RT, TX, TY, 1>(grid, s, a) : launch_stage_t<RT, TX, TY, 2>(grid, s, a);
+  return stage == 1 ? launch_stage_t<RT, TX, TY, NTH, 1>(grid, s, a) : launch_stage_t<RT, TX, TY, NTH, 2>(grid, s, a);
 }
 
 template <typename RT>
@@ -565,6 +567,7 @@ static hipError_t launch_stage_rt(int shape, int stage, dim3 grid, hipStream_t s
     case 2: return launch_stage_s<RT, 64, 4>(stage, grid, s, a);
     case 3: return launch_stage_s<RT, 16, 16>(stage, grid, s, a);
     case 4: return launch_stage_s<RT, 8, 8>(stage, grid, s, a);
+    case 5: return launch_stage_s<RT, 32, 16, 512>(stage, grid, s, a);
     default: return hipErrorInvalidValue;
   }
 }
@@ -577,26 +580,28 @@ hipError_t launch_stage(int mixed, int shape, int stage, int grid, hipStream_t s
 // The theta = 1 instantiation with or without register recording (the theta
 // instantiations share a resource class; the recording ones have their own).
 const void* stage_kernel_ptr(int mixed, int shape, int stage, bool rec) {
-#define AMR_KP(RT, TX, TY)                                                                               \
-  (stage == 1 ? (rec ? reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, 1, true, true>)           \
-                     : reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, 1, false, true>))         \
-              : (rec ? reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, 2, true, true>)           \
-                     : reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, 2, false, true>)))
+#define AMR_KP(RT, TX, TY, NTH)                                                                               \
+  (stage == 1 ? (rec ? reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, NTH, 1, true, true>)           \
+                     : reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, NTH, 1, false, true>))         \
+              : (rec ? reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, NTH, 2, true, true>)           \
+                     : reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, NTH, 2, false, true>)))
   if (mixed) {
     switch (shape) {
-      case 0: return AMR_KP(float, 256, 1);
-      case 1: return AMR_KP(float, 32, 8);
-      case 2: return AMR_KP(float, 64, 4);
-      case 3: return AMR_KP(float, 16, 16);
-      case 4: return AMR_KP(float, 8, 8);
+      case 0: return AMR_KP(float, 256, 1, 256);
+      case 1: return AMR_KP(float, 32, 8, 256);
+      case 2: return AMR_KP(float, 64, 4, 256);
+      case 3: return AMR_KP(float, 16, 16, 256);
+      case 4: return AMR_KP(float, 8, 8, 256);
+      case 5: return AMR_KP(float, 32, 16, 512);
     }
   } else {
     switch (shape) {
-      case 0: return AMR_KP(double, 256, 1);
-      case 1: return AMR_KP(double, 32, 8);
-      case 2: return AMR_KP(double, 64, 4);
-      case 3: return AMR_KP(double, 16, 16);
-      case 4: return AMR_KP(double, 8, 8);
+      case 0: return AMR_KP(double, 256, 1, 256);
+      case 1: return AMR_KP(double, 32, 8, 256);
+      case 2: return AMR_KP(double, 64, 4, 256);
+      case 3: return AMR_KP(double, 16, 16, 256);
+      case 4: return AMR_KP(double, 8, 8, 256);
+      case 5: return AMR_KP(double, 32, 16, 512);
     }
   }
 #undef AMR_KP

@@ -57,10 +57,10 @@ def run_pair(env, case, steps, prec=0, exe=1, shape=None):
     return ps, U, Ug, Uo
 
 
-@pytest.mark.parametrize("exe,shape", [(1, None), (0, None), (1, 1), (1, 4)])
+@pytest.mark.parametrize("exe,shape", [(1, None), (0, None), (1, 1), (1, 4), (1, 5)])
 @pytest.mark.parametrize("case", list(CASES))
 def test_hierarchy_fp64_matches_oracle(env, case, exe, shape):
-    """shape None: the library's default tiling; 1 and 4: workgroup and wavefront tiles."""
+    """shape None: the library's default tiling; 1, 4 and 5: 32x8 workgroup, 8x8 wavefront and 32x16 512-thread tiles."""
     if shape is not None and case.endswith("1d"):
         pytest.skip("1D tables have the one 1D tiling")
     log(f"case amr {case} fp64 exec={exe} shape={shape}")
@@ -75,7 +75,7 @@ def test_hierarchy_fp64_matches_oracle(env, case, exe, shape):
     assert np.all(np.abs(t1 - t0) <= 1e-12 * sc), (t1 - t0) / sc
 
 
-@pytest.mark.parametrize("shape", [None, 1, 4])
+@pytest.mark.parametrize("shape", [None, 1, 4, 5])
 @pytest.mark.parametrize("case", list(CASES))
 def test_hierarchy_mixed(env, case, shape):
     if shape is not None and case.endswith("1d"):
