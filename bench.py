@@ -52,17 +52,26 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def traffic_for(workload, form, cells):
-    """Measured HBM bytes per stage launch (average of the two stages), or None."""
+def traffic_for(workload, form, cells, tile):
+    """Measured HBM bytes per stage launch (average of the two stages), or None when no
+    measurement was taken on these kernel sources, this workload and this tile shape."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
     e = t.get("entries", {}).get(f"{workload}/{form}")
-    if not e or e.get("kernel_source_sha") != kernel_source_sha() or e.get("cells") != cells:
+    if (not e or e.get("kernel_source_sha") != kernel_source_sha() or e.get("cells") != cells
+            or e.get("tile") != tile):
         return None
     return e["hbm_bytes_per_launch"]
+
+
+def stage_tile(kernel_name):
+    """'TXxTY' from a stage kernel's template arguments (type, TX, TY, ...)."""
+    import re
+    m = re.search(r"stage_kernel<\w+, (\d+), (\d+),", kernel_name)
+    return f"{m.group(1)}x{m.group(2)}" if m else None
 
 
 def summarize_pmc(fetch_csv, write_csv, workload, form, cells):
@@ -93,7 +102,9 @@ def summarize_pmc(fetch_csv, write_csv, workload, form, cells):
         w = statistics.median(write.get(k, [0.0])) * 1024.0 * sw
         out[k] = {"fetch_bytes": f, "write_bytes": w}
     per_launch = sum(v["fetch_bytes"] + v["write_bytes"] for v in out.values()) / max(1, len(out))
+    tiles = {stage_tile(k) for k in out}
     entry = {"kernel_source_sha": kernel_source_sha(), "cells": cells, "hbm_bytes_per_launch": per_launch,
+             "tile": tiles.pop() if len(tiles) == 1 else None,
              "algorithmic_bytes_per_launch": BYTES_PER_CELL_STEP * cells / 2, "copy_scale_fetch": sf,
              "copy_scale_write": sw, "kernels": out}
     try:
@@ -158,12 +169,13 @@ def time_hierarchy(A, torch, ps, U, precision, exec_form, steps, warmup, kw, sha
     wall = time.perf_counter() - t0
     status = T.status()
     tiling = A.amr_table_get_tiling(T.h)
+    tile = "%dx%d" % A.amr_table_tiling_shape(T.h, tiling[0])
     T.close()
     if status != A.AMR_OK:
         raise SystemExit(f"unphysical state during the benchmark: {A.amr_status_string(status)}")
     ms = 1e3 * wall / steps
     return {"ms_per_step": ms, "event_ms_per_step": e0.elapsed_time(e1) / steps, "stage_ms": [ms / 2, ms / 2],
-            "tiling": list(tiling)}
+            "tiling": list(tiling), "tile": tile}
 
 
 def time_form(A, torch, ps, U, precision, exec_form, steps, warmup, kw, tune=True, shape=None):
@@ -203,11 +215,12 @@ def time_form(A, torch, ps, U, precision, exec_form, steps, warmup, kw, tune=Tru
         st[1] += b
     status = T.status()
     tiling = A.amr_table_get_tiling(T.h)
+    tile = "%dx%d" % A.amr_table_tiling_shape(T.h, tiling[0])
     T.close()
     if status != A.AMR_OK:
         raise SystemExit(f"unphysical state during the benchmark: {A.amr_status_string(status)}")
     return {"ms_per_step": 1e3 * wall / steps, "event_ms_per_step": ev_ms / steps,
-            "stage_ms": [st[0] / steps, st[1] / steps], "tiling": list(tiling)}
+            "stage_ms": [st[0] / steps, st[1] / steps], "tiling": list(tiling), "tile": tile}
 
 
 def cpu_baseline(ps_full, U_full, kw, budget_s=12.0):
@@ -342,10 +355,11 @@ def main():
                       "steps": v["steps"],
                       "stage_ms": v["stage_ms"], "tiling": v["tiling"]} for k, v in res.items()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_for(args.workload, main_form, cells),
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_for(args.workload, main_form, cells, m["tile"]),
                      "kernel": (f"whole root step of all levels ({main_form}): stage, ghost, register, refluxing "
                                 f"and restriction kernels, {BYTES_PER_CELL_STEP} B per cell-update" if hierarchy else
-                                f"stage_kernel ({main_form}), 2 launches/step, {BYTES_STAGE[0]}+{BYTES_STAGE[1]} "
+                                f"stage_kernel ({main_form}, {m['tile']} tiles), 2 launches/step, "
+                                f"{BYTES_STAGE[0]}+{BYTES_STAGE[1]} "
                                 f"B/cell, avg {sum(stage_ms) / 2:.4f} ms/launch")},
     }
     if not args.no_cpu:

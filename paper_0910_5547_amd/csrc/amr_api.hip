@@ -161,10 +161,11 @@ int auto_zslab(amr_table* t, int level, int shape) {
 
 int default_zslab(const amr_table* t) { return t->ph.ndim == 3 ? 0 : 1; }  // 0 = auto_zslab
 
-// Default tile shape: 32 x 8 workgroup tiles, unless small patches would leave
-// more than half of their lanes idle; then 8 x 8 wavefront tiles, which fill every
-// lane of patches whose x-y extents are multiples of 8 (their larger halo share
-// makes them slower where the workgroup tiles are at least half full).
+// Default tile shape: 32 x 16 tiles (512 threads) where they are nearly full (the
+// smallest halo share per cell), else 32 x 8, unless small patches would leave more
+// than half of those lanes idle; then 8 x 8 wavefront tiles, which fill every lane
+// of patches whose x-y extents are multiples of 8 (their larger halo share makes
+// them slower where the workgroup tiles are at least half full).
 int default_shape(const amr_table* t) {
   if (t->ph.ndim == 1) return 0;
   auto lane_use = [&](int shape) {
@@ -176,6 +177,7 @@ int default_shape(const amr_table* t) {
     }
     return cols / lanes;
   };
+  if (t->ph.ndim == 3 && lane_use(5) >= 0.9) return 5;
   const double u1 = lane_use(1), us = lane_use(SHAPE_SMALL);
   return (u1 < 0.5 && us > u1) ? SHAPE_SMALL : 1;
 }

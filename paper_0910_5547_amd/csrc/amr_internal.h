@@ -78,14 +78,14 @@ hipError_t launch_restrict(hipStream_t s, const RestrictOp* ops, const Work& w, 
 hipError_t launch_scale_dt(hipStream_t s, const double* dt0, double* dtl, int nlev);
 
 // Compiled tile shapes; shape 0 is the 1D shape.  TX x TY = workgroup size: one
-// tile per workgroup (256 threads; 512 for 32 x 16, shape 5, which halves the
-// y-halo share of a tile); 8 x 8 (shape 4, small patches): one tile per
-// wavefront, four per workgroup.  Every shape has at most one halo cell and one
-// edge face per lane.
-constexpr int NSHAPES = 6;
-constexpr int SHAPE_TX[NSHAPES] = {256, 32, 64, 16, 8, 32};
-constexpr int SHAPE_TY[NSHAPES] = {1, 8, 4, 16, 8, 16};
-constexpr int SHAPE_NT[NSHAPES] = {256, 256, 256, 256, 256, 512};
+// tile per workgroup (256 threads; 512 for 32 x 16, shape 5, and 384 for 32 x 12,
+// shape 6, which cut the y-halo share of a tile); 8 x 8 (shape 4, small patches):
+// one tile per wavefront, four per workgroup.  Every shape has at most one halo
+// cell and one edge face per lane.
+constexpr int NSHAPES = 7;
+constexpr int SHAPE_TX[NSHAPES] = {256, 32, 64, 16, 8, 32, 32};
+constexpr int SHAPE_TY[NSHAPES] = {1, 8, 4, 16, 8, 16, 12};
+constexpr int SHAPE_NT[NSHAPES] = {256, 256, 256, 256, 256, 512, 384};
 constexpr int SHAPE_SMALL = 4;
 constexpr int shape_tiles_per_wg(int shape) { return SHAPE_NT[shape] / (SHAPE_TX[shape] * SHAPE_TY[shape]); }
 

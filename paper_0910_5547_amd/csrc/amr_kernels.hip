@@ -40,10 +40,10 @@ namespace amr {
 // A tile of TX x TY = 256 columns is the whole workgroup's; a tile of 64 columns
 // (small patches) is one wavefront's, each of the four wavefronts walking its own
 // tiles and synchronising only with itself.
-// NTH: threads per workgroup (256, or 512 for the 32 x 16 tile, whose LDS allows one
-// workgroup per CU).
+// NTH: threads per workgroup (256; 512 for the 32 x 16 tile, whose LDS allows one
+// workgroup per CU; 384 for 32 x 12, two per CU).
 template <typename RT, int TX, int TY, int NTH, int STAGE, bool REC, bool TH1>
-__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(Fast<RT>::value && !REC && NTH == 256 ? 3 : 2)))
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(Fast<RT>::value && !REC && NTH != 512 ? 3 : 2)))
 void stage_kernel(StageArgs a) {
   constexpr int TL = TX * TY;  // lanes (columns) per tile
   static_assert(TL == NTH || TL == 64, "a tile is the workgroup or one wavefront");
@@ -568,6 +568,7 @@ static hipError_t launch_stage_rt(int shape, int stage, dim3 grid, hipStream_t s
     case 3: return launch_stage_s<RT, 16, 16>(stage, grid, s, a);
     case 4: return launch_stage_s<RT, 8, 8>(stage, grid, s, a);
     case 5: return launch_stage_s<RT, 32, 16, 512>(stage, grid, s, a);
+    case 6: return launch_stage_s<RT, 32, 12, 384>(stage, grid, s, a);
     default: return hipErrorInvalidValue;
   }
 }
@@ -593,6 +594,7 @@ const void* stage_kernel_ptr(int mixed, int shape, int stage, bool rec) {
       case 3: return AMR_KP(float, 16, 16, 256);
       case 4: return AMR_KP(float, 8, 8, 256);
       case 5: return AMR_KP(float, 32, 16, 512);
+      case 6: return AMR_KP(float, 32, 12, 384);
     }
   } else {
     switch (shape) {
@@ -602,6 +604,7 @@ const void* stage_kernel_ptr(int mixed, int shape, int stage, bool rec) {
       case 3: return AMR_KP(double, 16, 16, 256);
       case 4: return AMR_KP(double, 8, 8, 256);
       case 5: return AMR_KP(double, 32, 16, 512);
+      case 6: return AMR_KP(double, 32, 12, 384);
     }
   }
 #undef AMR_KP

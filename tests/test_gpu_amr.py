@@ -57,10 +57,10 @@ def run_pair(env, case, steps, prec=0, exe=1, shape=None):
     return ps, U, Ug, Uo
 
 
-@pytest.mark.parametrize("exe,shape", [(1, None), (0, None), (1, 1), (1, 4), (1, 5)])
+@pytest.mark.parametrize("exe,shape", [(1, None), (0, None), (1, 1), (1, 4), (1, 5), (1, 6)])
 @pytest.mark.parametrize("case", list(CASES))
 def test_hierarchy_fp64_matches_oracle(env, case, exe, shape):
-    """shape None: the library's default tiling; 1, 4 and 5: 32x8 workgroup, 8x8 wavefront and 32x16 512-thread tiles."""
+    """shape None: the library's default tiling; 1, 4, 5, 6: 32x8 workgroup, 8x8 wavefront, 32x16 (512 threads) and 32x12 (384) tiles."""
     if shape is not None and case.endswith("1d"):
         pytest.skip("1D tables have the one 1D tiling")
     log(f"case amr {case} fp64 exec={exe} shape={shape}")
