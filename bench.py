@@ -94,13 +94,20 @@ def summarize_pmc(fetch_csv, write_csv, workload, form, cells):
     big_w = max(copy_w)
     sf = COPY_BYTES / (big_f * 1024.0)
     sw = COPY_BYTES / (big_w * 1024.0)
+    # the timed run's kernels: the tile shape with the most dispatches (the autotuner
+    # tries every shape a few times first)
+    counts = {}
+    for k, vs in fetch.items():
+        if "stage_kernel" in k:
+            counts[stage_tile(k)] = counts.get(stage_tile(k), 0) + len(vs)
+    main_tile = max(counts, key=counts.get)
     out = {}
     for k in fetch:
-        if "stage_kernel" not in k:
+        if "stage_kernel" not in k or stage_tile(k) != main_tile:
             continue
         f = statistics.median(fetch[k]) * 1024.0 * sf
         w = statistics.median(write.get(k, [0.0])) * 1024.0 * sw
-        out[k] = {"fetch_bytes": f, "write_bytes": w}
+        out[k] = {"fetch_bytes": f, "write_bytes": w, "dispatches": len(fetch[k])}
     per_launch = sum(v["fetch_bytes"] + v["write_bytes"] for v in out.values()) / max(1, len(out))
     tiles = {stage_tile(k) for k in out}
     entry = {"kernel_source_sha": kernel_source_sha(), "cells": cells, "hbm_bytes_per_launch": per_launch,
