@@ -33,14 +33,14 @@ def env():
 
 
 def run_pair(env, ps, U, steps, prec=0, exe=1, flux=0, cfl=0.8, periodic=0, domain=(0, 0, 0), tiling=None,
-             check_dt=True):
+             check_dt=True, theta=None):
     """Advance U on the GPU and with the oracle with identical dt (the GPU's); return both."""
     torch, A, O = env
-    T = A.Table(ps, precision=prec, exec_form=exe, flux=flux, periodic=periodic, domain=domain)
+    T = A.Table(ps, precision=prec, exec_form=exe, flux=flux, theta=theta, periodic=periodic, domain=domain)
     if tiling is not None:
         A.amr_table_set_tiling(T.h, *tiling)
     Ud = T.upload(U)
-    o = O.Oracle(ps, flux=flux, periodic=periodic, domain=domain)
+    o = O.Oracle(ps, flux=flux, theta=theta, periodic=periodic, domain=domain)
     Uo = U.copy()
     for s in range(steps):
         dt = T.cfl_dt(Ud, cfl)
@@ -130,6 +130,19 @@ def test_two_dimensional(env):
     U = W.random_state(ps, 8, shocks=1.0)
     Ug, Uo = run_pair(env, ps, U, 5)
     compare(ps, Ug, Uo, bitwise=True, what="2d")
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.5, 2.0])
+def test_limiter_theta(env, theta):
+    """theta != 1: the three-argument minmod path of the stage kernel (theta = 1 compiles to
+    the two-argument form), bitwise against the oracle in FP64 and to 1e-5 in mixed."""
+    log(f"case theta {theta}")
+    ps, U = W.uneven_patches(npatch=8, seed=36)
+    Ug, Uo = run_pair(env, ps, U, 3, theta=theta)
+    compare(ps, Ug, Uo, bitwise=True, what=f"theta {theta}")
+    Ug, Uo = run_pair(env, ps, U, 3, prec=1, theta=theta, check_dt=False)
+    g, r = active_all(ps, Ug), active_all(ps, Uo)
+    assert l1_rel(g, r) <= 1e-5
 
 
 def test_hll2_flux(env):
