@@ -17,11 +17,14 @@
  *    one-speed form: F = (F_L + F_R - lambda0 (U_R - U_L))/2 with conserved
  *    U_R - U_L); the two-speed HLL of Harten, Lax & van Leer is a flag.
  *  - c_s = sqrt(gamma p / rho) at each face state; in a y or z sweep the normal
- *    velocity of that sweep replaces v_x in lambda^+-.
+ *    velocity of that sweep replaces v_x in lambda^+-.  For MHD (nvar 8, psi held
+ *    at 0) the fast magnetosonic speed along the sweep replaces c_s, B joins the
+ *    reconstructed primitives, and reflect also negates the normal field.
  *  - Ghost layers are refilled before each RK stage; "outflow" is a zero-gradient
  *    copy of the edge cell's conserved variables; reflect mirrors and negates the
  *    normal momentum.
- *  - CFL rule (absent from the paper): dt = C / max_cells sum_d (|v_d|+c_s)/dx_d.
+ *  - CFL rule (absent from the paper): dt = C / max_cells sum_d (|v_d|+c_d)/dx_d,
+ *    c_d the signal speed above.
  */
 #include "oracle.h"
 #include <math.h>
@@ -65,15 +68,24 @@ double or_minmod3(double a, double b, double c) {
   return 0.25 * (sa + sb) * fabs(sa + sc) * m;
 }
 
-int or_prim(const or_phys* ph, const double U[5], double q[6]) {
-  /* Sec. 4: U = (rho, rho v, rho E), E = v^2/2 + e, ideal gas p = (gamma-1) rho e. */
+int or_prim(const or_phys* ph, const double* U, double* q) {
+  /* Sec. 4: U = (rho, rho v, rho E), E = v^2/2 + e, ideal gas p = (gamma-1) rho e.
+   * MHD section: the energy variable is rho E + B^2/2 and B follows; the reconstructed
+   * primitives are the hydro set plus B. */
+  const int nv = ph->nvar;
   int bad = 0;
-  for (int k = 0; k < 5; ++k)
+  for (int k = 0; k < nv; ++k)
     if (!isfinite(U[k])) bad = 1;
   double rho = U[0];
   double vx = U[1] / rho, vy = U[2] / rho, vz = U[3] / rho;
   double kin = 0.5 * ((U[1] * U[1] + U[2] * U[2]) + U[3] * U[3]) / rho; /* rho v^2 / 2 */
-  double e = (U[4] - kin) / rho;
+  double e;
+  if (nv == 8) {
+    double mag = 0.5 * ((U[5] * U[5] + U[6] * U[6]) + U[7] * U[7]); /* B^2 / 2 */
+    e = ((U[4] - kin) - mag) / rho;
+  } else {
+    e = (U[4] - kin) / rho;
+  }
   if (!(rho > 0) && !(ph->rho_floor > 0)) bad = 1;
   if (!(e > 0) && !(ph->e_floor > 0)) bad = 1;
   if (ph->rho_floor > 0 && rho < ph->rho_floor) rho = ph->rho_floor;
@@ -83,40 +95,88 @@ int or_prim(const or_phys* ph, const double U[5], double q[6]) {
   q[2] = vx;
   q[3] = vy;
   q[4] = vz;
-  q[5] = (ph->gamma - 1.0) * rho * e;
+  if (nv == 8) {
+    q[5] = U[5];
+    q[6] = U[6];
+    q[7] = U[7];
+  }
+  q[nv] = (ph->gamma - 1.0) * rho * e;
   return bad;
 }
 
-/* Conserved state, pressure and sound speed of one primitive face state q = (rho,e,vx,vy,vz). */
-static void face_state(const or_phys* ph, const double q[5], double U[5], double* p, double* c) {
+/* Signal speed along d of a primitive state: the sound speed sqrt(gamma p / rho) for
+ * hydro; for MHD the fast magnetosonic speed
+ *   c_f^2 = (a^2 + b^2 + sqrt((a^2 + b^2)^2 - 4 a^2 b_d^2)) / 2,
+ * a^2 = gamma p / rho, b^2 = |B|^2 / rho, b_d^2 = B_d^2 / rho.  The radicand is evaluated
+ * as (a^2 - b^2)^2 + 4 a^2 b_t^2 with b_t^2 = b^2 - b_d^2 formed from the two transverse
+ * components: the same quantity, a sum of non-negative terms, with no cancellation where
+ * a = b_d. */
+double or_signal_speed(const or_phys* ph, int d, const double* q) {
+  double p = (ph->gamma - 1.0) * q[0] * q[1];
+  double a2 = ph->gamma * p / q[0];
+  if (ph->nvar != 8) return sqrt(a2);
+  double b2 = ((q[5] * q[5] + q[6] * q[6]) + q[7] * q[7]) / q[0];
+  int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  double bt2 = (q[5 + t1] * q[5 + t1] + q[5 + t2] * q[5 + t2]) / q[0];
+  double dab = a2 - b2;
+  double r = dab * dab + 4.0 * a2 * bt2;
+  return sqrt(0.5 * ((a2 + b2) + sqrt(r)));
+}
+
+/* Conserved state, pressure and signal speed along d of one primitive face state. */
+static void face_state(const or_phys* ph, int d, const double* q, double* U, double* p, double* c) {
   double rho = q[0], e = q[1], vx = q[2], vy = q[3], vz = q[4];
   *p = (ph->gamma - 1.0) * rho * e;
-  *c = sqrt(ph->gamma * (*p) / rho);
+  *c = or_signal_speed(ph, d, q);
   U[0] = rho;
   U[1] = rho * vx;
   U[2] = rho * vy;
   U[3] = rho * vz;
   U[4] = rho * (e + 0.5 * ((vx * vx + vy * vy) + vz * vz));
+  if (ph->nvar == 8) {
+    U[4] = U[4] + 0.5 * ((q[5] * q[5] + q[6] * q[6]) + q[7] * q[7]); /* + B^2/2 */
+    U[5] = q[5];
+    U[6] = q[6];
+    U[7] = q[7];
+  }
 }
 
-void or_phys_flux(const or_phys* ph, int d, const double q[5], double F[5]) {
+void or_phys_flux(const or_phys* ph, int d, const double* q, double* F) {
   /* Sec. 4 flux vectors: F^d = (rho v_d, rho v_d v + p e_d, rho (v^2/2 + h) v_d),
-   * with rho (v^2/2 + h) = rho E + p since h = e + p/rho. */
-  double U[5], p, c;
-  face_state(ph, q, U, &p, &c);
+   * with rho (v^2/2 + h) = rho E_h + p, E_h = v^2/2 + e, since h = e + p/rho.
+   * MHD fluxes (psi = 0): momentum rho v_d v_j + (p + B^2/2) delta_jd - B_j B_d;
+   * energy rho (v^2/2 + h) v_d + B^2 v_d - B_d (B . v); induction v_d B_j - v_j B_d
+   * for j != d (the x flux as printed; the printed y and z induction entries are
+   * permuted, and the axis-permutation invariance of the system fixes them) and
+   * psi = 0 for j = d. */
+  double U[OR_NVMAX], p, c;
+  face_state(ph, d, q, U, &p, &c);
   double vd = q[2 + d];
+  double rEh = q[0] * (q[1] + 0.5 * ((q[2] * q[2] + q[3] * q[3]) + q[4] * q[4]));
   F[0] = U[1 + d];
-  for (int j = 0; j < 3; ++j) F[1 + j] = U[1 + d] * q[2 + j] + (j == d ? p : 0.0);
-  F[4] = (U[4] + p) * vd;
+  if (ph->nvar != 8) {
+    for (int j = 0; j < 3; ++j) F[1 + j] = U[1 + d] * q[2 + j] + (j == d ? p : 0.0);
+    F[4] = (rEh + p) * vd;
+    return;
+  }
+  double B2 = (q[5] * q[5] + q[6] * q[6]) + q[7] * q[7];
+  double Bd = q[5 + d];
+  double Bv = (q[5] * q[2] + q[6] * q[3]) + q[7] * q[4];
+  for (int j = 0; j < 3; ++j)
+    F[1 + j] = (U[1 + d] * q[2 + j] + (j == d ? p + 0.5 * B2 : 0.0)) - q[5 + j] * Bd;
+  F[4] = ((rEh + p) * vd + B2 * vd) - Bd * Bv;
+  for (int j = 0; j < 3; ++j) F[5 + j] = j == d ? 0.0 : vd * q[5 + j] - q[2 + j] * Bd;
 }
 
-void or_face_flux(const or_phys* ph, int d, const double qL[5], const double qR[5], double F[5]) {
-  /* Sec. 4 Riemann flux.  lambda^+- = v_d +- c_s for each face state,
-   * a+ = max(0, lambda+_L, lambda+_R), a- = max(0, -lambda-_L, -lambda-_R),
-   * lambda0 = max(a+, a-);  F = 0.5 (F_L + F_R - lambda0 (U_R - U_L)). */
-  double UL[5], UR[5], FL[5], FR[5], pL, pR, cL, cR;
-  face_state(ph, qL, UL, &pL, &cL);
-  face_state(ph, qR, UR, &pR, &cR);
+void or_face_flux(const or_phys* ph, int d, const double* qL, const double* qR, double* F) {
+  /* Sec. 4 Riemann flux.  lambda^+- = v_d +- c for each face state (c the sound speed,
+   * or for MHD the fast magnetosonic speed along d), a+ = max(0, lambda+_L, lambda+_R),
+   * a- = max(0, -lambda-_L, -lambda-_R), lambda0 = max(a+, a-);
+   * F = 0.5 (F_L + F_R - lambda0 (U_R - U_L)). */
+  const int nv = ph->nvar;
+  double UL[OR_NVMAX], UR[OR_NVMAX], FL[OR_NVMAX], FR[OR_NVMAX], pL, pR, cL, cR;
+  face_state(ph, d, qL, UL, &pL, &cL);
+  face_state(ph, d, qR, UR, &pR, &cR);
   or_phys_flux(ph, d, qL, FL);
   or_phys_flux(ph, d, qR, FR);
   double vL = qL[2 + d], vR = qR[2 + d];
@@ -124,11 +184,11 @@ void or_face_flux(const or_phys* ph, int d, const double qL[5], const double qR[
   double am = fmax(0.0, fmax(-(vL - cL), -(vR - cR)));
   if (ph->flux == OR_FLUX_HLL2) {
     /* Two-speed HLL (Harten, Lax & van Leer 1983) with S_R = a+, S_L = -a-. */
-    for (int k = 0; k < 5; ++k)
+    for (int k = 0; k < nv; ++k)
       F[k] = ((ap * FL[k] + am * FR[k]) - (ap * am) * (UR[k] - UL[k])) / (ap + am);
   } else {
     double lam = fmax(ap, am);
-    for (int k = 0; k < 5; ++k) F[k] = 0.5 * ((FL[k] + FR[k]) - lam * (UR[k] - UL[k]));
+    for (int k = 0; k < nv; ++k) F[k] = 0.5 * ((FL[k] + FR[k]) - lam * (UR[k] - UL[k]));
   }
 }
 
@@ -158,7 +218,7 @@ static double minmod2(double a, double b) {
  * of a coarse cell).  The 2^d children of C average to u(C).  Returns 0 if no coarse
  * patch holds C. */
 static int prolong_cell(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph, const double* Cold,
-                        const double* Cnew, double alpha, int level, const int L[3], double out[5]) {
+                        const double* Cnew, double alpha, int level, const int L[3], double* out) {
   int Cc[3] = {0, 0, 0};
   for (int e = 0; e < ph->ndim; ++e) Cc[e] = L[e] >> 1; /* L >= 0 after the periodic wrap */
   for (int q = 0; q < np; ++q) {
@@ -171,7 +231,7 @@ static int prolong_cell(int32_t np, const int32_t* meta, const int64_t* off, con
     geom Q = get_geom(mq, off[q], ph->ndim);
     int c0[3] = {0, 0, 0};
     for (int e = 0; e < ph->ndim; ++e) c0[e] = Cc[e] - mq[1 + e];
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < ph->nvar; ++k) {
       double u0 = coarse_at(Cold, Cnew, alpha, at(&Q, k, c0));
       double v = u0;
       for (int e = 0; e < ph->ndim; ++e) {
@@ -224,7 +284,7 @@ static void fill_external(int32_t np, const int32_t* meta, const int64_t* off, c
           break;
         }
         if (!found && m[0] > 0 && Cold && Cnew) {
-          double u[5];
+          double u[OR_NVMAX];
           if (prolong_cell(np, meta, off, ph, Cold, Cnew, alpha, m[0], L, u))
             for (int k = 0; k < ph->nvar; ++k) V[at(G, k, cg)] = u[k];
         }
@@ -271,7 +331,7 @@ int or_fill_ghosts_amr(int32_t np, const int32_t* meta, const int64_t* off, cons
               cs[d] = si; cs[a] = ia; cs[b] = ib;
               for (int k = 0; k < ph->nvar; ++k) {
                 double v = V[at(&G, k, cs)];
-                if (k == 1 + d) v = sgn * v;
+                if (k == 1 + d || (ph->nvar == 8 && k == 5 + d)) v = sgn * v; /* normal v and B */
                 V[at(&G, k, cg)] = v;
               }
             }
@@ -290,7 +350,7 @@ int or_patch_L(const int32_t* m, int64_t off, const or_phys* ph, const double* V
 int64_t or_face_record_size(const int32_t* m, const or_phys* ph) {
   int64_t tot = 0;
   for (int d = 0; d < ph->ndim; ++d) {
-    int64_t c = 5 * (int64_t)(m[4 + d] + 1);
+    int64_t c = (int64_t)ph->nvar * (m[4 + d] + 1);
     for (int e = 0; e < 3; ++e)
       if (e != d) c *= m[4 + e];
     tot += c;
@@ -300,15 +360,16 @@ int64_t or_face_record_size(const int32_t* m, const or_phys* ph) {
 
 int or_patch_L_rec(const int32_t* m, int64_t off, const or_phys* ph, const double* V, double* L, double* Frec) {
   geom G = get_geom(m, off, ph->ndim);
+  const int nv = ph->nvar;
   int bad = 0;
   int64_t nact = (int64_t)G.n[0] * G.n[1] * G.n[2];
-  for (int64_t i = 0; i < 5 * nact; ++i) L[i] = 0.0;
+  for (int64_t i = 0; i < nv * nact; ++i) L[i] = 0.0;
   int maxn = G.n[0] > G.n[1] ? G.n[0] : G.n[1];
   if (G.n[2] > maxn) maxn = G.n[2];
   /* line buffers, indexed by position along the line + 2 (cells -2 .. n+1) */
-  double(*q)[5] = malloc(sizeof(double[5]) * (size_t)(maxn + 4));
-  double(*sig)[5] = malloc(sizeof(double[5]) * (size_t)(maxn + 4));
-  double(*F)[5] = malloc(sizeof(double[5]) * (size_t)(maxn + 1));
+  double(*q)[OR_NVMAX] = malloc(sizeof(double[OR_NVMAX]) * (size_t)(maxn + 4));
+  double(*sig)[OR_NVMAX] = malloc(sizeof(double[OR_NVMAX]) * (size_t)(maxn + 4));
+  double(*F)[OR_NVMAX] = malloc(sizeof(double[OR_NVMAX]) * (size_t)(maxn + 1));
   for (int d = 0; d < ph->ndim; ++d) {
     /* Sec. 4 MOL equation: the d-flux needs only cells along d; level l has dx0/2^l. */
     double dxd = ldexp(ph->dx0[d], -G.level);
@@ -319,21 +380,21 @@ int or_patch_L_rec(const int32_t* m, int64_t off, const or_phys* ph, const doubl
         for (int i = -2; i <= n + 1; ++i) {
           int c[3];
           c[d] = i; c[a] = ia; c[b] = ib;
-          double Uc[5], w[6];
-          for (int k = 0; k < 5; ++k) Uc[k] = V[at(&G, k, c)];
+          double Uc[OR_NVMAX], w[OR_NVMAX + 1];
+          for (int k = 0; k < nv; ++k) Uc[k] = V[at(&G, k, c)];
           bad |= or_prim(ph, Uc, w);
-          for (int k = 0; k < 5; ++k) q[i + 2][k] = w[k];
+          for (int k = 0; k < nv; ++k) q[i + 2][k] = w[k];
         }
         /* O3: limited slope of cells -1 .. n (Sec. 4 PLM with theta-minmod) */
         for (int i = -1; i <= n; ++i)
-          for (int k = 0; k < 5; ++k) {
+          for (int k = 0; k < nv; ++k) {
             double qm = q[i + 1][k], q0 = q[i + 2][k], qp = q[i + 3][k];
             sig[i + 2][k] = or_minmod3(ph->theta * (q0 - qm), ph->theta * (qp - q0), (qp - qm) / 2.0);
           }
         /* O4-O5: flux at face f (between cells f-1 and f), f = 0 .. n */
         for (int f = 0; f <= n; ++f) {
-          double qL[5], qR[5];
-          for (int k = 0; k < 5; ++k) {
+          double qL[OR_NVMAX], qR[OR_NVMAX];
+          for (int k = 0; k < nv; ++k) {
             qL[k] = q[f + 1][k] + 0.5 * sig[f + 1][k]; /* u_{f-1/2,l} = u_{f-1} + sigma_{f-1}/2 */
             qR[k] = q[f + 2][k] - 0.5 * sig[f + 2][k]; /* u_{f-1/2,r} = u_f - sigma_f/2 */
           }
@@ -342,12 +403,12 @@ int or_patch_L_rec(const int32_t* m, int64_t off, const or_phys* ph, const doubl
         if (Frec) { /* every face flux of the line: [v][ib][ia][f] within this dimension's block */
           int64_t base = 0;
           for (int e = 0; e < d; ++e) {
-            int64_t c = 5 * (int64_t)(G.n[e] + 1);
+            int64_t c = (int64_t)nv * (G.n[e] + 1);
             for (int e2 = 0; e2 < 3; ++e2)
               if (e2 != e) c *= G.n[e2];
             base += c;
           }
-          for (int k = 0; k < 5; ++k)
+          for (int k = 0; k < nv; ++k)
             for (int f = 0; f <= n; ++f)
               Frec[base + (((int64_t)k * G.n[b] + ib) * G.n[a] + ia) * (n + 1) + f] = F[f][k];
         }
@@ -356,7 +417,7 @@ int or_patch_L_rec(const int32_t* m, int64_t off, const or_phys* ph, const doubl
           int c[3];
           c[d] = i; c[a] = ia; c[b] = ib;
           int64_t cell = ((int64_t)c[2] * G.n[1] + c[1]) * G.n[0] + c[0];
-          for (int k = 0; k < 5; ++k) L[k * nact + cell] = L[k * nact + cell] - (F[i + 1][k] - F[i][k]) / dxd;
+          for (int k = 0; k < nv; ++k) L[k * nact + cell] = L[k * nact + cell] - (F[i + 1][k] - F[i][k]) / dxd;
         }
       }
   }
@@ -381,14 +442,14 @@ int or_stage_rec(int32_t np, const int32_t* meta, const int64_t* off, const or_p
     if (!is_level(m, level)) continue;
     geom G = get_geom(m, off[p], ph->ndim);
     int64_t nact = (int64_t)G.n[0] * G.n[1] * G.n[2];
-    double* L = malloc(sizeof(double) * 5 * (size_t)nact);
+    double* L = malloc(sizeof(double) * ph->nvar * (size_t)nact);
     bad |= or_patch_L_rec(m, off[p], ph, V, L, (Frec && rec_off && rec_off[p] >= 0) ? Frec + rec_off[p] : NULL);
     for (int k3 = 0; k3 < G.n[2]; ++k3)
       for (int j = 0; j < G.n[1]; ++j)
         for (int i = 0; i < G.n[0]; ++i) {
           int c[3] = {i, j, k3};
           int64_t cell = ((int64_t)k3 * G.n[1] + j) * G.n[0] + i;
-          for (int k = 0; k < 5; ++k) {
+          for (int k = 0; k < ph->nvar; ++k) {
             int64_t e = at(&G, k, c);
             double u1 = V[e] + dt * L[k * nact + cell]; /* Sec. 4 TVD-RK2: U + dt L(U) */
             out[e] = stage == 1 ? u1 : 0.5 * U0[e] + 0.5 * u1;
@@ -423,12 +484,12 @@ double or_max_speed(int32_t np, const int32_t* meta, const int64_t* off, const o
       for (int j = 0; j < G.n[1]; ++j)
         for (int i = 0; i < G.n[0]; ++i) {
           int c[3] = {i, j, k3};
-          double Uc[5], w[6];
-          for (int k = 0; k < 5; ++k) Uc[k] = U[at(&G, k, c)];
+          double Uc[OR_NVMAX], w[OR_NVMAX + 1];
+          for (int k = 0; k < ph->nvar; ++k) Uc[k] = U[at(&G, k, c)];
           bad |= or_prim(ph, Uc, w);
-          double cs = sqrt(ph->gamma * w[5] / w[0]);
           double s = 0.0;
-          for (int d = 0; d < ph->ndim; ++d) s = s + (fabs(w[2 + d]) + cs) / ldexp(ph->dx0[d], -G.level);
+          for (int d = 0; d < ph->ndim; ++d)
+            s = s + (fabs(w[2 + d]) + or_signal_speed(ph, d, w)) / ldexp(ph->dx0[d], -G.level);
           if (s > smax) smax = s;
         }
   }

@@ -12,8 +12,10 @@
  * in each active dimension d < ndim (g[d] = 0, n[d] = 1 in absent dimensions);
  * s[d] = n[d] + 2 g[d].  Variable k of cell (i,j,k) (storage indices, x fastest)
  * lives at  U[off + k*S + (kz*s[1] + jy)*s[0] + ix]  with S = s[0]*s[1]*s[2].
- * Variables are the conserved U = (rho, rho vx, rho vy, rho vz, rho E) of the
- * paper's Sec. 4, with rho E the total energy density.
+ * Variables (nvar = 5) are the conserved U = (rho, rho vx, rho vy, rho vz, rho E)
+ * of the paper's Sec. 4, with rho E the total energy density; for ideal MHD
+ * (nvar = 8) they are (rho, rho v, rho E + B^2/2, Bx, By, Bz), the paper's MHD
+ * variables with the divergence-cleaning field psi held at zero.
  *
  * Patch metadata is an int32 array of OR_META entries per patch:
  *   [0] level, [1..3] lo (lower active index in level space), [4..6] n,
@@ -24,6 +26,7 @@
 #include <stdint.h>
 
 #define OR_META 16
+#define OR_NVMAX 8 /* hydro: 5 variables; ideal MHD (Sec. 5 of the MHD extension): 8 */
 enum { OR_BC_OUTFLOW = 0, OR_BC_PERIODIC = 1, OR_BC_REFLECT = 2, OR_BC_EXTERNAL = 3 };
 enum { OR_FLUX_PAPER = 0, OR_FLUX_HLL2 = 1 };
 
@@ -42,12 +45,16 @@ extern "C" {
 
 /* Three-argument minmod of Sec. 4 (0.25(sgn a+sgn b)|sgn a+sgn c| min|.|). */
 double or_minmod3(double a, double b, double c);
-/* Conserved -> (rho, e, vx, vy, vz, p) for one cell; returns 1 if unphysical. */
-int or_prim(const or_phys* ph, const double U[5], double q[6]);
-/* Face flux in direction d from primitive face states qL, qR = (rho,e,vx,vy,vz). */
-void or_face_flux(const or_phys* ph, int d, const double qL[5], const double qR[5], double F[5]);
-/* Physical flux F^d(U(q)) of Sec. 4 for one primitive state. */
-void or_phys_flux(const or_phys* ph, int d, const double q[5], double F[5]);
+/* Conserved -> primitives for one cell; returns 1 if unphysical.
+ * nvar 5: q = (rho, e, vx, vy, vz), q[5] = p.  nvar 8: q = (rho, e, vx, vy, vz, Bx, By, Bz),
+ * q[8] = p.  (nvar + 1 entries are written.) */
+int or_prim(const or_phys* ph, const double* U, double* q);
+/* Face flux in direction d (nvar entries) from primitive face states qL, qR (nvar entries). */
+void or_face_flux(const or_phys* ph, int d, const double* qL, const double* qR, double* F);
+/* Physical flux F^d(U(q)) for one primitive state (Sec. 4; MHD section for nvar 8). */
+void or_phys_flux(const or_phys* ph, int d, const double* q, double* F);
+/* Signal speed along d: sound speed (nvar 5) or fast magnetosonic speed (nvar 8). */
+double or_signal_speed(const or_phys* ph, int d, const double* q);
 
 /* O1: fill the face ghosts (all ng layers, over the active range of the other
  * dimensions) of every patch on `level` (-1 = all) from the boundary condition
@@ -61,7 +68,7 @@ int or_fill_ghosts(int32_t np, const int32_t* meta, const int64_t* off, const or
  * time fraction alpha between Cold and Cnew (arenas with the coarse ghosts filled). */
 int or_fill_ghosts_amr(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph, double* V,
                        int32_t level, const double* Cold, const double* Cnew, double alpha);
-/* Size of the face-flux record of one patch: for each active dimension d, 5 x
+/* Size of the face-flux record of one patch: for each active dimension d, nvar x
  * (n_d + 1) x prod(other n), laid out [v][b][a][face] with (a, b) the other two
  * dimensions in cyclic order after d. */
 int64_t or_face_record_size(const int32_t* meta, const or_phys* ph);
@@ -71,7 +78,7 @@ int or_patch_L_rec(const int32_t* meta, int64_t off, const or_phys* ph, const do
 int or_stage_rec(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph, const double* V,
                  const double* U0, double* out, double dt, int32_t stage, int32_t level, const int64_t* rec_off,
                  double* Frec);
-/* L(V) of the MOL equation for one patch, written to L (5 x active cells, x fastest).
+/* L(V) of the MOL equation for one patch, written to L (nvar x active cells, x fastest).
  * V must have its ghosts filled.  Returns 1 if an unphysical state was met. */
 int or_patch_L(const int32_t* meta, int64_t off, const or_phys* ph, const double* V, double* L);
 /* One RK2 stage over the patches of `level`: stage 1 out = V + dt L(V);
@@ -81,7 +88,8 @@ int or_stage(int32_t np, const int32_t* meta, const int64_t* off, const or_phys*
 /* One full TVD-RK2 step of `level` on U (in place), W = scratch arena of the same size. */
 int or_rk2_step(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph,
                 double* U, double* W, double dt, int32_t level);
-/* Largest signal speed sum_d (|v_d| + c_s)/dx_d over active cells of `level`. */
+/* Largest signal speed sum_d (|v_d| + c_d)/dx_d over active cells of `level`, c_d the
+ * sound speed (hydro) or the fast magnetosonic speed along d (MHD). */
 double or_max_speed(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph,
                     const double* U, int32_t level, int* flag);
 /* dt = cfl / max speed (one level or a single-level table). */

@@ -47,6 +47,8 @@ def lib():
         L.or_face_flux.restype = None
         L.or_phys_flux.argtypes = [pp, C.c_int, dp, dp]
         L.or_phys_flux.restype = None
+        L.or_signal_speed.argtypes = [pp, C.c_int, dp]
+        L.or_signal_speed.restype = C.c_double
         L.or_fill_ghosts.argtypes = [C.c_int32, ip, lp, pp, dp, C.c_int32]
         L.or_fill_ghosts_amr.argtypes = [C.c_int32, ip, lp, pp, dp, C.c_int32, dp, dp, C.c_double]
         L.or_face_record_size.restype = C.c_int64
@@ -69,9 +71,11 @@ def _dp(a):
 
 
 def phys(gamma=1.4, theta=1.0, ndim=3, dx0=(1.0, 1.0, 1.0), flux=FLUX_PAPER, rho_floor=0.0, e_floor=0.0,
-         periodic=0, domain=(0, 0, 0)):
+         periodic=0, domain=(0, 0, 0), nvar=5):
+    """nvar 5: hydro (Sec. 4).  nvar 8: ideal MHD with the cleaning field held at zero."""
+    assert nvar in (5, 8)
     ph = Phys()
-    ph.nvar, ph.ndim, ph.gamma, ph.theta = 5, ndim, gamma, theta
+    ph.nvar, ph.ndim, ph.gamma, ph.theta = nvar, ndim, gamma, theta
     ph.periodic = periodic
     for d in range(3):
         ph.dx0[d] = dx0[d]
@@ -84,26 +88,37 @@ def minmod3(a, b, c):
     return lib().or_minmod3(a, b, c)
 
 
-def prim(ph, U5):
-    U5 = np.ascontiguousarray(U5, np.float64)
-    q = np.zeros(6)
-    bad = lib().or_prim(C.byref(ph), _dp(U5), _dp(q))
+def prim(ph, U):
+    """Primitives (rho, e, v[, B]) followed by p: nvar + 1 entries."""
+    U = np.ascontiguousarray(U, np.float64)
+    assert U.shape == (ph.nvar,)
+    q = np.zeros(ph.nvar + 1)
+    bad = lib().or_prim(C.byref(ph), _dp(U), _dp(q))
     return q, bad
 
 
 def face_flux(ph, d, qL, qR):
     qL = np.ascontiguousarray(qL, np.float64)
     qR = np.ascontiguousarray(qR, np.float64)
-    F = np.zeros(5)
+    assert qL.shape[0] >= ph.nvar and qR.shape[0] >= ph.nvar
+    F = np.zeros(ph.nvar)
     lib().or_face_flux(C.byref(ph), d, _dp(qL), _dp(qR), _dp(F))
     return F
 
 
 def phys_flux(ph, d, q):
     q = np.ascontiguousarray(q, np.float64)
-    F = np.zeros(5)
+    assert q.shape[0] >= ph.nvar
+    F = np.zeros(ph.nvar)
     lib().or_phys_flux(C.byref(ph), d, _dp(q), _dp(F))
     return F
+
+
+def signal_speed(ph, d, q):
+    """Sound speed (hydro) or fast magnetosonic speed along d (MHD) of primitive state q."""
+    q = np.ascontiguousarray(q, np.float64)
+    assert q.shape[0] >= ph.nvar
+    return lib().or_signal_speed(C.byref(ph), d, _dp(q))
 
 
 class Oracle:
@@ -112,7 +127,7 @@ class Oracle:
     def __init__(self, ps, flux=FLUX_PAPER, rho_floor=0.0, e_floor=0.0, theta=None, periodic=0, domain=(0, 0, 0)):
         self.ps = ps
         self.ph = phys(ps.gamma, ps.theta if theta is None else theta, ps.ndim, ps.dx0, flux, rho_floor, e_floor,
-                       periodic, domain)
+                       periodic, domain, ps.nvar)
         self.meta = np.ascontiguousarray(ps.meta(), np.int32)
         self.off = np.ascontiguousarray(ps.offset, np.int64)
         self._W = None
@@ -205,18 +220,19 @@ class AmrOracle:
             raise FloatingPointError(f"oracle met an unphysical state on level {level}")
 
     def _face_block(self, rec, p, d):
-        """(5, n_b, n_a, n_d + 1) view of patch p's recorded d-face fluxes."""
+        """(nvar, n_b, n_a, n_d + 1) view of patch p's recorded d-face fluxes."""
         n = [int(x) for x in self.ps.n[p]]
+        nv = self.ps.nvar
         base = int(self.rec_off[p])
         for e in range(d):
-            c = 5 * (n[e] + 1)
+            c = nv * (n[e] + 1)
             for e2 in range(3):
                 if e2 != e:
                     c *= n[e2]
             base += c
         a, b = (d + 1) % 3, (d + 2) % 3
-        size = 5 * n[b] * n[a] * (n[d] + 1)
-        return rec[base:base + size].reshape(5, n[b], n[a], n[d] + 1)
+        size = nv * n[b] * n[a] * (n[d] + 1)
+        return rec[base:base + size].reshape(nv, n[b], n[a], n[d] + 1)
 
     def _patch_at(self, level, C3):
         """The patch of `level` whose active box holds cell C3, or -1."""
@@ -251,7 +267,7 @@ class AmrOracle:
                 for side in (0, 1):
                     if ps.bc[p, 2 * d + side] != 3:
                         continue
-                    R = self.reg[(p, d, side)]  # (5, n_b, n_a)
+                    R = self.reg[(p, d, side)]  # (nvar, n_b, n_a)
                     Ff = int(ps.lo[p, d]) + (0 if side == 0 else int(ps.n[p, d]))
                     cf = Ff // 2
                     Cd = self._wrap(l, d, cf - 1 if side == 0 else cf)
@@ -270,7 +286,7 @@ class AmrOracle:
                             # fine average over the 2^(ndim-1) fine faces under this coarse face
                             ia = [2 * ja, 2 * ja + 1] if a < ps.ndim else [0]
                             ib = [2 * jb, 2 * jb + 1] if b < ps.ndim else [0]
-                            Rf = np.zeros(5)
+                            Rf = np.zeros(ps.nvar)
                             for y in ib:
                                 for x in ia:
                                     Rf = Rf + R[:, y, x]
@@ -302,7 +318,7 @@ class AmrOracle:
                     for ix in range(cn[0]):
                         C3 = [(int(lo[0]) >> 1) + ix, (int(lo[1]) >> 1) + jy, (int(lo[2]) >> 1) + kz]
                         q = self._patch_at(l, C3)
-                        acc = np.zeros(5)
+                        acc = np.zeros(ps.nvar)
                         for dz in (range(2) if nd > 2 else [0]):
                             for dy in (range(2) if nd > 1 else [0]):
                                 for dx in range(2):
@@ -334,7 +350,7 @@ class AmrOracle:
             if ps.level[p] == l:
                 s, _ = ps.stored_shape(p)
                 o = int(ps.offset[p])
-                out.append((o, o + 5 * s[0] * s[1] * s[2]))
+                out.append((o, o + ps.nvar * s[0] * s[1] * s[2]))
         return out
 
     def _advance(self, U, l, s):

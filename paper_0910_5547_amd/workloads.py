@@ -19,6 +19,13 @@ text; no dataset is involved):
   synthetic stand-in for the many grids of an AMR hierarchy (Sec. 3, Sec. 6.3).
 * :func:`advected_wave` - a smooth density wave advected at v = 1 (exact
   solution known), for convergence tests.
+* :func:`brio_wu` - the 1D MHD shock tube of the paper's MHD section
+  (Brio & Wu 1988), Gamma = 2, N = 200.
+* :func:`alfven_wave` - a circularly polarised Alfven wave, an exact nonlinear
+  travelling solution of ideal MHD, for convergence tests of the MHD fluxes.
+* :func:`mhd_vortex_box` - a 3D periodic MHD box (Orszag-Tang-like vortex
+  velocity, divergence-free random field B = curl A), split into patches with
+  EXTERNAL faces: the synthetic stand-in for the paper's 3D MHD runs.
 
 Initial states are set from (rho, v, p) with the ideal-gas relation of Sec. 4,
 rho E = p/(gamma-1) + rho |v|^2 / 2 - the definition of the conserved energy,
@@ -32,7 +39,8 @@ import math
 import numpy as np
 
 BC_OUTFLOW, BC_PERIODIC, BC_REFLECT, BC_EXTERNAL = 0, 1, 2, 3
-NVAR = 5
+NVAR = 5       # hydro: (rho, rho v, rho E)
+NVAR_MHD = 8   # ideal MHD: (rho, rho v, rho E + B^2/2, B), the divergence-cleaning field held at 0
 
 
 @dataclasses.dataclass
@@ -55,6 +63,7 @@ class PatchSet:
     gamma: float = 1.4
     theta: float = 1.0
     dx0: tuple = (1.0, 1.0, 1.0)
+    nvar: int = NVAR
 
     @property
     def npatch(self) -> int:
@@ -79,14 +88,14 @@ class PatchSet:
         return m
 
     def view(self, U: np.ndarray, p: int) -> np.ndarray:
-        """(5, sz, sy, sx) view of patch p (storage incl. ghosts) in arena U."""
+        """(nvar, sz, sy, sx) view of patch p (storage incl. ghosts) in arena U."""
         s, _ = self.stored_shape(p)
         S = s[0] * s[1] * s[2]
         o = int(self.offset[p])
-        return U[o:o + NVAR * S].reshape(NVAR, s[2], s[1], s[0])
+        return U[o:o + self.nvar * S].reshape(self.nvar, s[2], s[1], s[0])
 
     def active(self, U: np.ndarray, p: int) -> np.ndarray:
-        """(5, nz, ny, nx) view of the active cells of patch p."""
+        """(nvar, nz, ny, nx) view of the active cells of patch p."""
         v = self.view(U, p)
         _, g = self.stored_shape(p)
         n = self.n[p]
@@ -94,7 +103,7 @@ class PatchSet:
 
 
 def make_patchset(ndim, n, ng, bc, level=None, lo=None, gamma=1.4, theta=1.0, dx0=(1.0, 1.0, 1.0),
-                  align=64) -> PatchSet:
+                  align=64, nvar=NVAR) -> PatchSet:
     """Lay out patches back to back in one arena, each start aligned to ``align`` elements."""
     n = np.asarray(n, np.int32).reshape(-1, 3)
     npch = n.shape[0]
@@ -108,9 +117,9 @@ def make_patchset(ndim, n, ng, bc, level=None, lo=None, gamma=1.4, theta=1.0, dx
         s = [int(n[p, d]) + (2 * int(ng[p]) if d < ndim else 0) for d in range(3)]
         cur = (cur + align - 1) // align * align
         off[p] = cur
-        cur += NVAR * s[0] * s[1] * s[2]
+        cur += nvar * s[0] * s[1] * s[2]
     return PatchSet(ndim, level, lo, n, ng, bc, off, cur, float(gamma), float(theta),
-                    tuple(float(x) for x in dx0))
+                    tuple(float(x) for x in dx0), int(nvar))
 
 
 def conserved(rho, vx, vy, vz, p, gamma):
@@ -118,6 +127,14 @@ def conserved(rho, vx, vy, vz, p, gamma):
     rho = np.asarray(rho, np.float64)
     E = p / (gamma - 1.0) + 0.5 * rho * (vx * vx + vy * vy + vz * vz)
     return np.stack(np.broadcast_arrays(rho, rho * vx, rho * vy, rho * vz, E))
+
+
+def conserved_mhd(rho, vx, vy, vz, p, Bx, By, Bz, gamma):
+    """Conserved ideal-MHD variables (rho, rho v, rho E + B^2/2, B) from primitives; the energy
+    variable is the definition p/(gamma-1) + rho |v|^2/2 + |B|^2/2 of the paper's MHD section."""
+    rho = np.asarray(rho, np.float64)
+    E = p / (gamma - 1.0) + 0.5 * rho * (vx * vx + vy * vy + vz * vz) + 0.5 * (Bx * Bx + By * By + Bz * Bz)
+    return np.stack(np.broadcast_arrays(rho, rho * vx, rho * vy, rho * vz, E, Bx, By, Bz)).astype(np.float64)
 
 
 def new_arena(ps: PatchSet, fill=np.nan) -> np.ndarray:
@@ -156,6 +173,105 @@ def advected_wave(N, ng=2, gamma=1.4, theta=1.0, amp=0.2, ndim=1, axis=0):
     v[axis] = np.ones(shape)
     U = new_arena(ps)
     ps.active(U, 0)[...] = conserved(rho, v[0], v[1], v[2], np.ones(shape), gamma)
+    return ps, U
+
+
+# ---------------------------------------------------------------- MHD set-ups
+def brio_wu(N=200, ng=2, gamma=2.0, theta=1.0, x0=0.5):
+    """Brio-Wu MHD shock tube on [0,1], outflow ends, Gamma = 2 (the paper's MHD section).
+
+    Left: rho = 1, p = 1, v = 0, B = (0.75, 1, 0).  Right: rho = 0.125, p = 0.1, v = 0,
+    B = (0.75, -1, 0) (the paper's right-state subscripts are misprinted as left ones).
+    """
+    ps = make_patchset(1, [[N, 1, 1]], ng, [BC_OUTFLOW] * 6, gamma=gamma, theta=theta,
+                       dx0=(1.0 / N, 1.0, 1.0), nvar=NVAR_MHD)
+    x = (np.arange(N) + 0.5) / N
+    left = x < x0
+    rho = np.where(left, 1.0, 0.125)
+    p = np.where(left, 1.0, 0.1)
+    By = np.where(left, 1.0, -1.0)
+    z = np.zeros(N)
+    U = new_arena(ps)
+    ps.active(U, 0)[...] = conserved_mhd(rho, z, z, z, p, 0.75 + z, By, z, gamma).reshape(NVAR_MHD, 1, 1, N)
+    return ps, U
+
+
+def alfven_wave(N, ng=2, gamma=5.0 / 3.0, theta=1.0, amp=0.1, p=0.1, ndim=1, axis=0):
+    """Circularly polarised Alfven wave travelling along ``axis`` of the periodic unit box.
+
+    rho = 1, v_par = 0, B_par = 1 (Alfven speed 1), B_perp = amp (sin phi, cos phi),
+    v_perp = -B_perp, phi = 2 pi x_axis.  |B_perp| is constant, so the total pressure
+    is uniform and the profile translates at speed 1 without change of shape.
+    """
+    n = [N if d < ndim else 1 for d in range(3)]
+    dx0 = tuple(1.0 / N if d < ndim else 1.0 for d in range(3))
+    ps = make_patchset(ndim, [n], ng, [BC_PERIODIC] * 6, gamma=gamma, theta=theta, dx0=dx0, nvar=NVAR_MHD)
+    shape = (n[2], n[1], n[0])
+    xc = (np.arange(N) + 0.5) / N
+    sh = [1, 1, 1]
+    sh[2 - axis] = N
+    phi = np.broadcast_to(2 * np.pi * xc.reshape(sh), shape)
+    b1, b2 = (axis + 1) % 3, (axis + 2) % 3
+    B = [np.zeros(shape) for _ in range(3)]
+    v = [np.zeros(shape) for _ in range(3)]
+    B[axis] = np.ones(shape)
+    B[b1], B[b2] = amp * np.sin(phi), amp * np.cos(phi)
+    v[b1], v[b2] = -B[b1], -B[b2]
+    U = new_arena(ps)
+    ps.active(U, 0)[...] = conserved_mhd(np.ones(shape), v[0], v[1], v[2], p, B[0], B[1], B[2], gamma)
+    return ps, U
+
+
+def curl_spectral(A):
+    """B = curl A of a periodic vector field A[3] (arrays indexed z, y, x) on the unit box,
+    differentiated in Fourier space: the result is divergence-free to round-off in the same
+    spectral sense."""
+    shape = A[0].shape
+    ks = [2 * np.pi * np.fft.fftfreq(s, 1.0 / s) for s in shape]   # z, y, x
+    KZ, KY, KX = np.meshgrid(ks[0], ks[1], ks[2], indexing="ij")
+    Ax, Ay, Az = (np.fft.fftn(a) for a in A)
+    Bx = 1j * (KY * Az - KZ * Ay)
+    By = 1j * (KZ * Ax - KX * Az)
+    Bz = 1j * (KX * Ay - KY * Ax)
+    return [np.real(np.fft.ifftn(b)) for b in (Bx, By, Bz)]
+
+
+def mhd_vortex_box(N=192, patch=32, seed=50, gamma=5.0 / 3.0, theta=1.0, beta=1.7, ng=3):
+    """3D periodic MHD box of N^3 cells on the unit cube, as (N/patch)^3 patches with EXTERNAL faces.
+
+    rho = 25/(36 pi), p = 5/(12 pi) (sound speed 1 at gamma 5/3), v = (-sin 2 pi y, sin 2 pi x, 0);
+    B = curl A with A_i = grf(seed + i, 1 <= |k| <= 4, k^-2), scaled so that the mean plasma beta
+    2 p / <|B|^2> equals ``beta``.  Run it with the root domain periodic in all three dimensions
+    (domain N^3) so EXTERNAL ghosts wrap.  ``patch=None`` gives one periodic N^3 patch.
+    """
+    shape = (N, N, N)
+    x = (np.arange(N) + 0.5) / N
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    rho0, p0 = 25.0 / (36.0 * np.pi), 5.0 / (12.0 * np.pi)
+    vx, vy = -np.sin(2 * np.pi * Y), np.sin(2 * np.pi * X)
+    del Z, Y, X
+    A = [grf(shape, seed + i, 1.0, 4.0, 2.0) for i in range(3)]
+    B = curl_spectral(A)
+    del A
+    scale = math.sqrt(2.0 * p0 / beta / float(np.mean(B[0] ** 2 + B[1] ** 2 + B[2] ** 2)))
+    B = [scale * b for b in B]
+    Uf = conserved_mhd(rho0, vx, vy, 0.0, p0, B[0], B[1], B[2], gamma)
+    del B, vx, vy
+    if patch is None:
+        ps = make_patchset(3, [[N, N, N]], ng, [BC_PERIODIC] * 6, gamma=gamma, theta=theta,
+                           dx0=(1.0 / N,) * 3, nvar=NVAR_MHD)
+        U = new_arena(ps)
+        ps.active(U, 0)[...] = Uf
+        return ps, U
+    m = N // patch
+    assert m * patch == N
+    los = np.array([[i * patch, j * patch, k * patch] for k in range(m) for j in range(m) for i in range(m)],
+                   np.int32)
+    ps = make_patchset(3, [[patch] * 3] * len(los), ng, [BC_EXTERNAL] * 6, lo=los, gamma=gamma, theta=theta,
+                       dx0=(1.0 / N,) * 3, nvar=NVAR_MHD)
+    U = new_arena(ps)
+    for p, lo in enumerate(los):
+        ps.active(U, p)[...] = Uf[:, lo[2]:lo[2] + patch, lo[1]:lo[1] + patch, lo[0]:lo[0] + patch]
     return ps, U
 
 
@@ -219,8 +335,12 @@ def periodic_turbulent_box(N=256, seed=20, gamma=5.0 / 3.0, theta=1.0, mach=0.5,
     return ps, U
 
 
-def random_state(ps: PatchSet, seed, U=None, amp=0.3, vamp=0.5, shocks=0.0):
-    """Smooth random state on every patch of ``ps`` (see :func:`uneven_patches`)."""
+def random_state(ps: PatchSet, seed, U=None, amp=0.3, vamp=0.5, shocks=0.0, bamp=0.5):
+    """Smooth random state on every patch of ``ps`` (see :func:`uneven_patches`).
+
+    For an MHD patch set each field component is ``bamp`` S (drawn after the hydro fields, so
+    the hydro fields match those of a hydro set with the same seed).  This B is not
+    divergence-free; it exercises every term of the MHD flux."""
     rng = np.random.default_rng(seed)
     g = ps.gamma
     U = new_arena(ps) if U is None else U
@@ -261,7 +381,11 @@ def random_state(ps: PatchSet, seed, U=None, amp=0.3, vamp=0.5, shocks=0.0):
                 vel[d] = np.where(down, vel[d] + du * nv[d], vel[d])
             rho = np.where(down, rho * ratio, rho)
             pr = np.where(down, p2, pr)
-        ps.active(U, p)[...] = conserved(rho, vel[0], vel[1], vel[2], pr, g)
+        if ps.nvar == NVAR_MHD:
+            B = [bamp * S() for _ in range(3)]
+            ps.active(U, p)[...] = conserved_mhd(rho, vel[0], vel[1], vel[2], pr, B[0], B[1], B[2], g)
+        else:
+            ps.active(U, p)[...] = conserved(rho, vel[0], vel[1], vel[2], pr, g)
     return U
 
 
