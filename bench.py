@@ -11,6 +11,10 @@ Workloads (seeded, synthetic; see paper_0910_5547_amd.workloads):
                Mach 0.5 GRF velocities, p = 1 (the default, one patch)
   patches4000  4000 independent patches, sizes 8..32 per dimension, 3 ghost
                layers, smooth states with random planar shocks in 20%
+  sedov        deep-AMR octant Sedov hierarchy (7 levels, subcycled root steps)
+  mhd192       ideal MHD (8 variables), 192^3 periodic box as 216 patches of 32^3
+               with EXTERNAL faces: Orszag-Tang-like vortex velocity, B = curl of
+               a seeded GRF vector potential (divergence-free), plasma beta 1.7
 
 Three forms are timed on identical inputs: plain FP64 (one launch per patch
 per stage), batched FP64 (persistent launch per stage, graph-replayed step) and
@@ -28,8 +32,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0           # MI355X HBM3E
-BYTES_PER_CELL_STEP = 200        # 5 passes x 5 variables x 8 B (stage 1: read U, write U1; stage 2: read U1, U, write)
-BYTES_STAGE = (80, 120)          # per active cell, stage 1 and stage 2
+# algorithmic HBM bytes per cell-update: 5 passes x nvar variables x 8 B (stage 1: read U,
+# write U1; stage 2: read U1 and U, write U^{n+1}); 200 B for hydro, 320 B for MHD
+def bytes_per_cell(nvar):
+    return 5 * nvar * 8
+
+
+def bytes_stage(nvar):  # per active cell, stage 1 and stage 2
+    return (2 * nvar * 8, 3 * nvar * 8)
 METRIC = "cell-updates/s per RK2 step (batched FP32/FP64 vs plain FP64); % HBM peak"
 
 
@@ -74,7 +84,7 @@ def stage_tile(kernel_name):
     return f"{m.group(1)}x{m.group(2)}" if m else None
 
 
-def summarize_pmc(fetch_csv, write_csv, workload, form, cells):
+def summarize_pmc(fetch_csv, write_csv, workload, form, cells, nvar=5):
     """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) into HBM
     bytes per stage launch, each counter scaled by what it reads for the 1 GiB copy."""
     import csv
@@ -112,7 +122,7 @@ def summarize_pmc(fetch_csv, write_csv, workload, form, cells):
     tiles = {stage_tile(k) for k in out}
     entry = {"kernel_source_sha": kernel_source_sha(), "cells": cells, "hbm_bytes_per_launch": per_launch,
              "tile": tiles.pop() if len(tiles) == 1 else None,
-             "algorithmic_bytes_per_launch": BYTES_PER_CELL_STEP * cells / 2, "copy_scale_fetch": sf,
+             "algorithmic_bytes_per_launch": bytes_per_cell(nvar) * cells / 2, "copy_scale_fetch": sf,
              "copy_scale_write": sw, "kernels": out}
     try:
         with open(TRAFFIC_FILE) as fh:
@@ -143,6 +153,12 @@ def make_workload(name):
                 "of factor-2 refinement on the analytic profile, density-gradient flags (eps 0.3), "
                 f"{ps.npatch} patches of 8..32 cells per dimension, subcycled with refluxing, "
                 f"floors rho {kw['rho_floor']:g} e {kw['e_floor']:g}")
+    elif name == "mhd192":
+        ps, U = W.mhd_vortex_box(N=192, patch=32, seed=50)
+        kw = dict(periodic=7, domain=(192, 192, 192))
+        desc = ("ideal MHD (8 variables), 192^3 periodic as 216 patches of 32^3 (EXTERNAL faces, ng=3), "
+                "gamma=5/3, rho=25/(36 pi), p=5/(12 pi), v=(-sin 2 pi y, sin 2 pi x, 0), B=curl A with "
+                "A=GRF(k^-2, 1<=|k|<=4, seeds 50-52), beta=1.7")
     elif name.startswith("box"):
         N = int(name[3:])
         ps, U = W.periodic_turbulent_box(N=N, seed=20, kmax=min(16.0, N / 4))
@@ -236,22 +252,25 @@ def cpu_baseline(ps_full, U_full, kw, budget_s=12.0):
 
     from oracle import oracle as O
     from paper_0910_5547_amd import workloads as W
+    nv = ps_full.nvar
+    kw = {k: v for k, v in kw.items() if k not in ("periodic", "domain")}
     if ps_full.npatch == 1:
         B = 64
         a = ps_full.active(U_full, 0)[:, :B, :B, :B]
-        ps = W.make_patchset(3, [[B, B, B]], 2, [W.BC_PERIODIC] * 6, gamma=ps_full.gamma, dx0=ps_full.dx0)
+        ps = W.make_patchset(3, [[B, B, B]], 2, [W.BC_PERIODIC] * 6, gamma=ps_full.gamma, dx0=ps_full.dx0, nvar=nv)
         U = W.new_arena(ps)
         ps.active(U, 0)[...] = a
         what = f"{B}^3 periodic sub-box of the workload's field"
     else:
-        k = 64
+        k = 64 if nv == W.NVAR else 8
         sel = list(range(k))
         n = ps_full.n[sel]
-        ps = W.make_patchset(3, n, ps_full.ng[sel], [W.BC_OUTFLOW] * 6, gamma=ps_full.gamma, dx0=ps_full.dx0)
+        ps = W.make_patchset(3, n, ps_full.ng[sel], [W.BC_OUTFLOW] * 6, gamma=ps_full.gamma, dx0=ps_full.dx0,
+                             nvar=nv)
         U = W.new_arena(ps)
         for i, p in enumerate(sel):
             ps.active(U, i)[...] = ps_full.active(U_full, p)
-        what = f"first {k} of the workload's patches"
+        what = f"first {k} of the workload's patches (outflow faces)"
     o = O.Oracle(ps, **kw)
     cells = ps.active_cells()
     steps, t = 0, 0.0
@@ -285,11 +304,11 @@ def main():
     args = ap.parse_args()
     if args.summarize_pmc:
         from paper_0910_5547_amd import workloads as W
-        cells = {"box256": 256 ** 3}.get(args.workload)
+        cells, nvar = {"box256": (256 ** 3, 5), "mhd192": (192 ** 3, 8)}.get(args.workload, (None, 5))
         if cells is None:
             cells = make_workload(args.workload)[0].active_cells()
         form = args.forms.split(",")[-1]
-        e = summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, form, cells)
+        e = summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, form, cells, nvar)
         print(json.dumps(e, indent=1))
         return
     if args.gpus != 1:
@@ -314,6 +333,7 @@ def main():
     t0 = time.time()
     ps, U, desc, kw = make_workload(args.workload)
     hierarchy = int(ps.level.max()) > 0
+    bpc = bytes_per_cell(ps.nvar)
     # cell-updates per step: sum over levels of 2^l N_l (level l takes 2^l steps per root step)
     cells = int(sum((1 << int(ps.level[p])) * int(ps.n[p].prod()) for p in range(ps.npatch)))
     log(f"workload {args.workload}: {cells} cells, {ps.npatch} patches, arena {ps.arena * 8 / 1e9:.2f} GB "
@@ -331,9 +351,9 @@ def main():
         r = time_form(A, torch, ps, U, prec, exe, steps, warmup, kw, tune=args.tune, shape=args.shape)
         r["steps"] = steps
         r["value"] = cells / (r["ms_per_step"] * 1e-3)
-        r["hbm_frac_step"] = BYTES_PER_CELL_STEP * cells / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBPS
+        r["hbm_frac_step"] = bpc * cells / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBPS
         kern_ms = sum(r["stage_ms"])
-        r["stage_kernel_GBps"] = BYTES_PER_CELL_STEP * cells / (kern_ms * 1e-3) / 1e9
+        r["stage_kernel_GBps"] = bpc * cells / (kern_ms * 1e-3) / 1e9
         log(f"  {name}: {r['ms_per_step']:.3f} ms/step, {r['value'] / 1e9:.2f} G cell-updates/s, "
             f"stages {r['stage_ms'][0]:.3f}+{r['stage_ms'][1]:.3f} ms, {r['stage_kernel_GBps']:.0f} GB/s")
         res[name] = r
@@ -341,7 +361,7 @@ def main():
     main_form = "batched_mixed" if "batched_mixed" in res else list(res)[-1]
     m = res[main_form]
     stage_ms = m["stage_ms"]
-    achieved = BYTES_PER_CELL_STEP * cells / (sum(stage_ms) * 1e-3) / 1e9
+    achieved = bpc * cells / (sum(stage_ms) * 1e-3) / 1e9
     out = {
         "metric": METRIC,
         "value": m["value"],
@@ -355,7 +375,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if main_form == "batched_mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "cells": cells, "patches": ps.npatch, "form": main_form,
+        "config": {"workload": desc, "nvar": ps.nvar, "cells": cells, "patches": ps.npatch, "form": main_form,
                    "tiling": m["tiling"], "cfl": 0.8, "theta": ps.theta, "flux": "paper (Sec. 4)"},
         "hbm_frac": m["hbm_frac_step"],
         "forms": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"], "hbm_frac": v["hbm_frac_step"],
@@ -364,9 +384,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_for(args.workload, main_form, cells, m["tile"]),
                      "kernel": (f"whole root step of all levels ({main_form}): stage, ghost, register, refluxing "
-                                f"and restriction kernels, {BYTES_PER_CELL_STEP} B per cell-update" if hierarchy else
+                                f"and restriction kernels, {bpc} B per cell-update" if hierarchy else
                                 f"stage_kernel ({main_form}, {m['tile']} tiles), 2 launches/step, "
-                                f"{BYTES_STAGE[0]}+{BYTES_STAGE[1]} "
+                                f"{bytes_stage(ps.nvar)[0]}+{bytes_stage(ps.nvar)[1]} "
                                 f"B/cell, avg {sum(stage_ms) / 2:.4f} ms/launch")},
     }
     if not args.no_cpu:

@@ -11,6 +11,16 @@
  * each grid patch of a block-structured AMR hierarchy (Sec. 3), one patch being
  * the unit of GPU work (Sec. 5.2, Sec. 8).
  *
+ * With nvar = 8 the same update advances ideal MHD (the paper's MHD section,
+ * its divergence-cleaning field psi held at zero, so c_h plays no part):
+ * U = (rho, rho vx, rho vy, rho vz, rho E + B^2/2, Bx, By, Bz), B joins the
+ * reconstructed primitives, the physical flux is the paper's MHD flux with the
+ * induction entries v_d B_j - v_j B_d (its x flux; the printed y and z induction
+ * entries have their components permuted), the signal speed in the Riemann
+ * flux and in the CFL rule is the fast magnetosonic speed along the face
+ * normal, and REFLECT also negates the normal field.  MHD tables are single
+ * level (every patch at level 0).
+ *
  * Conventions shared by every entry point
  *   - Every function returns an amr_status: AMR_OK (0) or a negative code.
  *   - Device pointers (U, dt_dev) are caller-owned device memory (hipMalloc or
@@ -33,7 +43,7 @@
  *   One contiguous array of doubles holds every patch.  Patch p with n[d]
  *   active cells and ng ghost layers per side in each active dimension d < ndim
  *   (no ghosts, n[d] = 1 in absent dimensions) stores s[d] = n[d] + 2 g[d]
- *   cells per dimension, x fastest; variable k (0..4 in the order of U above)
+ *   cells per dimension, x fastest; variable k (0..nvar-1 in the order of U above)
  *   of storage cell (ix, iy, iz) is at element
  *       offset + k * S + (iz * s[1] + iy) * s[0] + ix,   S = s[0] s[1] s[2].
  *   Active cells are ix in [g, g + n[0]) and likewise in y and z.  Patches
@@ -64,7 +74,8 @@ typedef int32_t amr_status;
 /* Boundary condition of one patch face (Sec. 3 ghost zones; on-the-fly maps):
  *   OUTFLOW  ghost = copy of the nearest active cell (zero gradient),
  *   PERIODIC ghost = active cell one patch-length away (wrap within the patch),
- *   REFLECT  ghost = mirror image across the face, normal momentum negated,
+ *   REFLECT  ghost = mirror image across the face, normal momentum (and, for MHD,
+ *            normal field) negated,
  *   EXTERNAL ghost = filled by the library from the same-level patch that
  *            covers it (sibling copy); ghost storage is read by the stencil. */
 enum { AMR_BC_OUTFLOW = 0, AMR_BC_PERIODIC = 1, AMR_BC_REFLECT = 2, AMR_BC_EXTERNAL = 3 };
@@ -105,7 +116,7 @@ typedef struct {
 } amr_patch_desc;
 
 typedef struct {
-  int32_t nvar;      /* number of conserved variables; must be 5 (Sec. 4)                */
+  int32_t nvar;      /* conserved variables: 5 (hydro, Sec. 4) or 8 (ideal MHD, psi = 0)  */
   int32_t ndim;      /* 1, 2 or 3 active dimensions                                      */
   double gamma;      /* adiabatic index of p = (gamma-1) rho e, > 1                      */
   double theta;      /* PLM limiter parameter, 0 <= theta <= 2 (Sec. 4)                  */
@@ -126,7 +137,8 @@ typedef struct amr_table amr_table; /* opaque, library-owned */
 /* Create a table for `npatch` patches (Sec. 3 hierarchy as a flat list).
  * Copies the descriptors, validates them (AMR_EINVAL on: npatch < 1, n < 1,
  * ng out of range in an active dimension, n > 1 in an absent dimension,
- * overlapping storage, unknown bc/flux/precision/exec, nvar != 5,
+ * overlapping storage, unknown bc/flux/precision/exec, nvar not 5 or 8, a patch
+ * of level > 0 with nvar 8,
  * gamma <= 1, theta outside [0,2], dx0 <= 0, a PERIODIC face whose opposite
  * face is not PERIODIC), allocates the device-side copy, the stage scratch
  * arena U^(1) (same size as the U arena) and the reduction/flag words, builds
@@ -203,7 +215,10 @@ amr_status amr_table_status(amr_table* table, hipStream_t stream);
  * amr_table_num_tilings: number of compiled tile shapes.
  * amr_table_set_tiling: select shape `id` (0 <= id < num) and z-slab length
  *   zslab (>= 1; 0 = automatic: the slab length that fills whole rounds of the
- *   persistent launch); invalidates a captured graph.
+ *   persistent launch); invalidates a captured graph.  AMR_EINVAL for a shape
+ *   the table cannot run: shape 0 is the 1D shape and the only one for ndim 1;
+ *   MHD tables (nvar 8) have shapes 0, 1 and 4, and 5 and 6 in mixed precision
+ *   (in FP64 the larger tiles' LDS does not hold eight variables).
  * amr_table_get_tiling: current id and (resolved) zslab.
  * amr_table_tiling_shape: the (TX, TY) cells per tile of shape `id`. */
 int32_t amr_table_num_tilings(const amr_table* table);

@@ -134,7 +134,7 @@ def descriptors(ps):
 def physics(ps, precision=AMR_PREC_FP64, exec_form=AMR_EXEC_BATCHED, flux=AMR_FLUX_PAPER, theta=None,
             periodic=0, domain=(0, 0, 0), rho_floor=0.0, e_floor=0.0):
     ph = amr_physics()
-    ph.nvar, ph.ndim = 5, ps.ndim
+    ph.nvar, ph.ndim = int(getattr(ps, "nvar", 5)), ps.ndim
     ph.gamma = ps.gamma
     ph.theta = ps.theta if theta is None else theta
     for d in range(3):

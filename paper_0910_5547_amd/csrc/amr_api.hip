@@ -70,7 +70,7 @@ struct amr_table {
   // fused dt bookkeeping
   const double* fused_U = nullptr;
   int fused_level = -2;
-  int occ[2][NSHAPES][2][2] = {};  // resident stage workgroups per CU: [mixed][shape][stage][recording]
+  int occ[2][2][NSHAPES][2][2] = {};  // resident stage workgroups per CU: [mhd][mixed][shape][stage][recording]
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // AMR_STEP_TIMED: before/between/after the stages
   bool timed_valid = false;
   // ---- hierarchy (levels > 0 present): coarse/fine coupling plans, see build_hierarchy
@@ -112,11 +112,16 @@ struct amr_table {
 
 namespace {
 
-int ndim_of(const amr_table* t) { return t->ph.ndim; }
-
 bool shape_valid(int ndim, int shape) {
   if (shape < 0 || shape >= NSHAPES) return false;
   return ndim == 1 ? shape == 0 : shape != 0;
+}
+
+// A shape this table can run: right for its dimensionality and compiled for its
+// variable count and precision.
+bool shape_ok(const amr_table* t, int shape) {
+  if (!shape_valid(t->ph.ndim, shape)) return false;
+  return t->ph.nvar != NVAR_MHD || mhd_shape_ok(t->ph.precision == AMR_PREC_MIXED, shape);
 }
 
 int occupancy_grid(amr_table* t, int stage, int ntiles, bool rec);
@@ -177,8 +182,9 @@ int default_shape(const amr_table* t) {
     }
     return cols / lanes;
   };
-  if (t->ph.ndim == 3 && lane_use(5) >= 0.9) return 5;
   const double u1 = lane_use(1), us = lane_use(SHAPE_SMALL);
+  const bool big_ok = t->ph.nvar != NVAR_MHD || t->ph.precision == AMR_PREC_MIXED;  // shape 5 compiled
+  if (t->ph.ndim == 3 && big_ok && lane_use(5) >= 0.9) return 5;
   return (u1 < 0.5 && us > u1) ? SHAPE_SMALL : 1;
 }
 
@@ -277,11 +283,16 @@ Consts consts_of(const amr_table* t) {
 int occupancy_grid(amr_table* t, int stage, int ntiles, bool rec) {
   if (ntiles < 1) ntiles = 1;
   const int mixed = t->ph.precision == AMR_PREC_MIXED;
-  int& per_cu = t->occ[mixed][t->shape][stage - 1][rec ? 1 : 0];
+  const int mhd = t->ph.nvar == NVAR_MHD;
+  int& per_cu = t->occ[mhd][mixed][t->shape][stage - 1][rec ? 1 : 0];
   if (per_cu <= 0) {
-    const void* k = stage_kernel_ptr(mixed, t->shape, stage, rec);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, SHAPE_NT[t->shape], 0) != hipSuccess || per_cu < 1)
+    const void* k = stage_kernel_ptr(t->ph.nvar, mixed, t->shape, stage, rec);
+    if (!k) {  // not compiled (MHD recording kernels): never launched, nothing to size
       per_cu = 1;
+    } else if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, SHAPE_NT[t->shape], 0) != hipSuccess ||
+               per_cu < 1) {
+      per_cu = 1;
+    }
   }
   const int g = std::max(1, std::min(ntiles, per_cu * t->ncu));
   return g >= 8 ? g / 8 * 8 : g;  // a multiple of the XCD count (tile list interleave)
@@ -296,7 +307,8 @@ amr_status enqueue_ghosts(amr_table* t, double* A, const double* U, int level, d
   const int l0 = level < 0 ? 0 : level, l1 = level < 0 ? t->max_level : level;
   for (int l = l0; l <= l1; ++l)
     if (t->w_copy[l].nblk > 0)
-      HIPCHECK(launch_copy_ghosts(s, t->ops_d + t->ops_level_first[l], work_of(t, t->w_copy[l]), t->pdev_d, A));
+      HIPCHECK(launch_copy_ghosts(s, t->ops_d + t->ops_level_first[l], work_of(t, t->w_copy[l]), t->pdev_d, A,
+                                  t->ph.nvar));
   if (level > 0 && t->w_prol[level].nblk > 0)
     HIPCHECK(launch_prolong(s, t->prol_d + t->prol_first[level], work_of(t, t->w_prol[level]), t->pdev_d, A, t->snap,
                             U, alpha, t->ph.ndim));
@@ -321,13 +333,14 @@ amr_status enqueue_stage(amr_table* t, TileSet* ts, int stage, const double* V, 
   if (t->ph.exec == AMR_EXEC_BATCHED) {
     a.tiles = ts->d;
     a.ntiles = ts->n;
-    HIPCHECK(launch_stage(mixed, t->shape, stage, occupancy_grid(t, stage, (ts->n + W - 1) / W, rec), s, a));
+    HIPCHECK(launch_stage(t->ph.nvar, mixed, t->shape, stage, occupancy_grid(t, stage, (ts->n + W - 1) / W, rec), s,
+                          a));
   } else {
     for (size_t p = 0; p < t->pdev.size(); ++p) {
       if (ts->count[p] == 0) continue;
       a.tiles = ts->d + ts->n + ts->first[p];
       a.ntiles = ts->count[p];
-      HIPCHECK(launch_stage(mixed, t->shape, stage, (ts->count[p] + W - 1) / W, s, a));
+      HIPCHECK(launch_stage(t->ph.nvar, mixed, t->shape, stage, (ts->count[p] + W - 1) / W, s, a));
     }
   }
   return AMR_OK;
@@ -423,7 +436,7 @@ void drop_graph(amr_table* t) {
 
 amr_status validate(const amr_patch_desc* P, int32_t np, const amr_physics* ph) {
   if (!P || !ph || np < 1) return AMR_EINVAL;
-  if (ph->nvar != 5 || ph->ndim < 1 || ph->ndim > 3) return AMR_EINVAL;
+  if ((ph->nvar != NVAR && ph->nvar != NVAR_MHD) || ph->ndim < 1 || ph->ndim > 3) return AMR_EINVAL;
   if (!(ph->gamma > 1.0) || !(ph->theta >= 0.0 && ph->theta <= 2.0)) return AMR_EINVAL;
   for (int d = 0; d < 3; ++d)
     if (!(ph->dx0[d] > 0)) return AMR_EINVAL;
@@ -438,6 +451,7 @@ amr_status validate(const amr_patch_desc* P, int32_t np, const amr_physics* ph) 
   for (int p = 0; p < np; ++p) {
     const amr_patch_desc& D = P[p];
     if (D.level < 0 || D.level >= MAX_LEVELS || D.offset < 0 || D.reserved[0] || D.reserved[1]) return AMR_EINVAL;
+    if (ph->nvar == NVAR_MHD && D.level != 0) return AMR_EINVAL;  // MHD: single-level tables
     if (D.ng < 2 || D.ng > 8) return AMR_EINVAL;
     int64_t S = 1;
     for (int d = 0; d < 3; ++d) {
@@ -453,7 +467,7 @@ amr_status validate(const amr_patch_desc* P, int32_t np, const amr_physics* ph) 
       if (d < ph->ndim && ((D.bc[2 * d] == AMR_BC_PERIODIC) != (D.bc[2 * d + 1] == AMR_BC_PERIODIC)))
         return AMR_EINVAL;
     }
-    spans.emplace_back(D.offset, D.offset + 5 * S);
+    spans.emplace_back(D.offset, D.offset + ph->nvar * S);
   }
   std::sort(spans.begin(), spans.end());
   for (size_t i = 1; i < spans.size(); ++i)
@@ -694,7 +708,7 @@ amr_status build_hierarchy(amr_table* t, HierPlan& H) {
           for (int e = 0; e < 3; ++e)
             if (e != d) area *= D.n[e];
           t->pdev[p].reg[2 * d + side] = H.nreg;
-          H.nreg += 5 * area;
+          H.nreg += t->ph.nvar * area;
         }
     }
     t->reg_len[l] = H.nreg - t->reg_first[l];
@@ -714,8 +728,8 @@ amr_status build_hierarchy(amr_table* t, HierPlan& H) {
       if (D.level != l) continue;
       const PatchDev& P = t->pdev[p];
       H.snap.push_back(P.off);
-      H.snap.push_back(5 * P.S);
-      t->snap_maxlen[l] = std::max<int64_t>(t->snap_maxlen[l], 5 * P.S);
+      H.snap.push_back(t->ph.nvar * P.S);
+      t->snap_maxlen[l] = std::max<int64_t>(t->snap_maxlen[l], t->ph.nvar * P.S);
       for (int d = 0; d < nd; ++d)
         for (int side = 0; side < 2; ++side) {
           if (D.bc[2 * d + side] == AMR_BC_EXTERNAL) continue;
@@ -916,7 +930,7 @@ amr_status amr_patch_table_create(const amr_patch_desc* patches, int32_t npatch,
       P.reg[f] = -1;
     }
     t->pdev.push_back(P);
-    t->arena = std::max(t->arena, D.offset + 5 * S);
+    t->arena = std::max(t->arena, D.offset + phys->nvar * S);
     t->max_level = std::max(t->max_level, D.level);
   }
   std::vector<CopyOp> ops;
@@ -1113,6 +1127,7 @@ amr_status amr_cfl_dt(amr_table* t, const double* U, double cfl, int32_t level, 
       a.tx = SHAPE_TX[t->shape];
       a.ty = SHAPE_TY[t->shape];
       a.fast = t->ph.precision == AMR_PREC_MIXED;
+      a.nv = t->ph.nvar;
       a.flag = t->flag_d;
       a.smax = t->smax_d;
       a.c = consts_of(t);
@@ -1214,7 +1229,7 @@ amr_status amr_table_last_stage_ms(amr_table* t, float ms[2]) {
 int32_t amr_table_num_tilings(const amr_table* t) { return t ? NSHAPES : 0; }
 
 amr_status amr_table_set_tiling(amr_table* t, int32_t id, int32_t zslab) {
-  if (!t || !shape_valid(ndim_of(t), id) || zslab < 0) return AMR_EINVAL;
+  if (!t || !shape_ok(t, id) || zslab < 0) return AMR_EINVAL;
   t->shape = id;
   t->zslab = t->ph.ndim == 3 ? zslab : 1;  // 0 = balanced automatic choice
   drop_graph(t);
@@ -1260,7 +1275,7 @@ amr_status amr_autotune(amr_table* t, const double* U, const double* dt_dev, int
   int bshape = keep_shape, bz = keep_z;
   amr_status st = AMR_OK;
   for (int shape = 0; shape < NSHAPES && st == AMR_OK; ++shape) {
-    if (!shape_valid(t->ph.ndim, shape)) continue;
+    if (!shape_ok(t, shape)) continue;
     for (int z : zs) {
       t->shape = shape;
       t->zslab = z;

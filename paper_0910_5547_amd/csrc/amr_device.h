@@ -1,5 +1,8 @@
 // amr_device.h - device-side data structures and per-cell / per-face arithmetic
-// of the MOL hydro update (Wang, Abel & Kaehler, Sec. 4), for gfx950.
+// of the MOL hydro update (Wang, Abel & Kaehler, Sec. 4), for gfx950, and of its
+// ideal-MHD variant (the paper's MHD section with the cleaning field psi held at
+// zero): NV = 5 conserved variables (rho, rho v, rho E) or NV = 8
+// (rho, rho v, rho E + B^2/2, B).
 //
 // RT is the reconstruction type: double for the FP64 path, float for the mixed
 // path (FP32 reconstruction and face flux).  The conserved->primitive
@@ -20,7 +23,8 @@
 
 namespace amr {
 
-constexpr int NVAR = 5;
+constexpr int NVAR = 5;      // hydro
+constexpr int NVAR_MHD = 8;  // ideal MHD
 constexpr int NT = 256;  // threads per workgroup of the stage kernel (4 wave64s)
 constexpr int MAX_LEVELS = 32;
 
@@ -179,28 +183,38 @@ __device__ __forceinline__ int map_index(int i, int n, int bclo, int bchi, bool&
   return i;
 }
 
+// A reflecting face negates the normal momentum (and, for MHD, the normal field).
+template <int NV>
+__device__ __forceinline__ void reflect_flip(double* u, int d) {
+  u[1 + d] = -u[1 + d];
+  if constexpr (NV == NVAR_MHD) u[5 + d] = -u[5 + d];
+}
+
 // Conserved state of cell (i,j,k) (active-relative; at most one coordinate may be
 // outside the active range - the MOL stencil is a cross, Sec. 4).
+template <int NV = NVAR>
 __device__ __forceinline__ void load_cons(const double* __restrict__ A, const PatchDev& P, int i, int j, int k,
-                                          double u[NVAR]) {
+                                          double u[NV]) {
   bool fx = false, fy = false, fz = false;
   const int ii = map_index(i, P.n[0], P.bc[0], P.bc[1], fx);
   const int jj = map_index(j, P.n[1], P.bc[2], P.bc[3], fy);
   const int kk = map_index(k, P.n[2], P.bc[4], P.bc[5], fz);
   const int64_t e = cell_elem(P, ii, jj, kk);
 #pragma unroll
-  for (int v = 0; v < NVAR; ++v) u[v] = A[e + v * P.S];
-  if (fx) u[1] = -u[1];
-  if (fy) u[2] = -u[2];
-  if (fz) u[3] = -u[3];
+  for (int v = 0; v < NV; ++v) u[v] = A[e + v * P.S];
+  if (fx) reflect_flip<NV>(u, 0);
+  if (fy) reflect_flip<NV>(u, 1);
+  if (fz) reflect_flip<NV>(u, 2);
 }
 
 // ------------------------------------------------------------------ physics
-// Conserved -> primitive (rho, e, vx, vy, vz), in FP64 (Sec. 4: E = v^2/2 + e,
-// p = (gamma-1) rho e; the kinetic-energy subtraction cancels at high Mach, so it
-// is never done in FP32).  Returns true for an unphysical state.
-template <typename RT>
-__device__ __forceinline__ bool cons2prim(const double u[NVAR], const Consts& c, RT q[NVAR]) {
+// Conserved -> primitive (rho, e, vx, vy, vz[, Bx, By, Bz]), in FP64 (Sec. 4:
+// E = v^2/2 + e, p = (gamma-1) rho e; for MHD the energy variable also holds
+// B^2/2, subtracted as well; these subtractions cancel at high Mach or low beta,
+// so they are never done in FP32).  Returns true for an unphysical state.
+template <typename RT, int NV = NVAR>
+__device__ __forceinline__ bool cons2prim(const double u[NV], const Consts& c, RT q[NV]) {
+  constexpr bool MHD = NV == NVAR_MHD;
   const double rho = u[0];
   double vx, vy, vz, e;
   if constexpr (Fast<RT>::value) {
@@ -213,15 +227,27 @@ __device__ __forceinline__ bool cons2prim(const double u[NVAR], const Consts& c,
     vy = u[2] * ri;
     vz = u[3] * ri;
     const double kin = 0.5 * fma(u[1], vx, fma(u[2], vy, u[3] * vz));
-    e = (u[4] - kin) * ri;
+    if constexpr (MHD) {
+      const double mag = 0.5 * fma(u[5], u[5], fma(u[6], u[6], u[7] * u[7]));
+      e = ((u[4] - kin) - mag) * ri;
+    } else {
+      e = (u[4] - kin) * ri;
+    }
   } else {
     vx = u[1] / rho;
     vy = u[2] / rho;
     vz = u[3] / rho;
     const double kin = 0.5 * ((u[1] * u[1] + u[2] * u[2]) + u[3] * u[3]) / rho;
-    e = (u[4] - kin) / rho;
+    if constexpr (MHD) {
+      const double mag = 0.5 * ((u[5] * u[5] + u[6] * u[6]) + u[7] * u[7]);
+      e = ((u[4] - kin) - mag) / rho;
+    } else {
+      e = (u[4] - kin) / rho;
+    }
   }
-  bool bad = !(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]) && isfinite(u[3]) && isfinite(u[4]));
+  bool bad = false;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) bad |= !isfinite(u[v]);
   double r = rho;
   if (!(r > 0) && !(c.rho_floor > 0)) bad = true;
   if (!(e > 0) && !(c.e_floor > 0)) bad = true;
@@ -232,31 +258,78 @@ __device__ __forceinline__ bool cons2prim(const double u[NVAR], const Consts& c,
   q[2] = (RT)vx;
   q[3] = (RT)vy;
   q[4] = (RT)vz;
+  if constexpr (MHD) {
+    q[5] = (RT)u[5];
+    q[6] = (RT)u[6];
+    q[7] = (RT)u[7];
+  }
   return bad;
 }
 
-// Largest signal speed of one cell, sum_d (|v_d| + c_s)/dx_d (the CFL rule).
-// FAST selects the mixed path's evaluation (used for tables of that precision,
-// both by the CFL kernel and by the fused reduction in stage 2).
-template <bool FAST>
-__device__ __forceinline__ double cell_speed(const double u[NVAR], const Consts& c, const PatchDev& P, int& bad) {
+// Fast magnetosonic speed along D of a primitive MHD state, given a^2 = gamma p / rho:
+//   c_f^2 = (a^2 + b^2 + sqrt((a^2 - b^2)^2 + 4 a^2 b_t^2)) / 2,
+// b^2 = |B|^2 / rho, b_t^2 = (B_t1^2 + B_t2^2) / rho (t1, t2 = D+1, D+2 mod 3): the
+// larger root of the fast/slow dispersion relation, its radicand written as a sum of
+// non-negative terms (no cancellation where a = |B_D| / sqrt(rho)).
+template <typename RT, int D>
+__device__ __forceinline__ RT fast_speed(const RT* q, RT a2) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  if constexpr (Fast<RT>::value) {
+    const RT ri = __builtin_amdgcn_rcpf(q[0]);
+    const RT b2 = fmaf(q[5], q[5], fmaf(q[6], q[6], q[7] * q[7])) * ri;
+    const RT bt2 = fmaf(q[5 + T1], q[5 + T1], q[5 + T2] * q[5 + T2]) * ri;
+    const RT dab = a2 - b2;
+    const RT r = fmaf(dab, dab, 4.0f * a2 * bt2);
+    return __builtin_amdgcn_sqrtf(0.5f * ((a2 + b2) + __builtin_amdgcn_sqrtf(r)));
+  } else {
+    const RT b2 = ((q[5] * q[5] + q[6] * q[6]) + q[7] * q[7]) / q[0];
+    const RT bt2 = (q[5 + T1] * q[5 + T1] + q[5 + T2] * q[5 + T2]) / q[0];
+    const RT dab = a2 - b2;
+    const RT r = dab * dab + RT(4) * a2 * bt2;
+    return sqrt(RT(0.5) * ((a2 + b2) + sqrt(r)));
+  }
+}
+
+// Largest signal speed of one cell, sum_d (|v_d| + c_d)/dx_d (the CFL rule), c_d the
+// sound speed (hydro) or the fast magnetosonic speed along d (MHD).  FAST selects the
+// mixed path's evaluation (used for tables of that precision, both by the CFL kernel
+// and by the fused reduction in stage 2).
+template <bool FAST, int NV = NVAR>
+__device__ __forceinline__ double cell_speed(const double u[NV], const Consts& c, const PatchDev& P, int& bad) {
+  constexpr bool MHD = NV == NVAR_MHD;
   if constexpr (FAST) {
-    float q[NVAR];
-    bad |= cons2prim<float>(u, c, q) ? 1 : 0;
-    const double cs = (double)__builtin_amdgcn_sqrtf((float)c.gg1 * q[1]);
-    double s = (fabs((double)q[2]) + cs) * P.rdx[0];
-    if (c.ndim > 1) s = fma(fabs((double)q[3]) + cs, P.rdx[1], s);
-    if (c.ndim > 2) s = fma(fabs((double)q[4]) + cs, P.rdx[2], s);
+    float q[NV];
+    bad |= cons2prim<float, NV>(u, c, q) ? 1 : 0;
+    const float a2 = (float)c.gg1 * q[1];
+    double cx, cy, cz;
+    if constexpr (MHD) {
+      cx = (double)fast_speed<float, 0>(q, a2);
+      cy = c.ndim > 1 ? (double)fast_speed<float, 1>(q, a2) : 0.0;
+      cz = c.ndim > 2 ? (double)fast_speed<float, 2>(q, a2) : 0.0;
+    } else {
+      cx = cy = cz = (double)__builtin_amdgcn_sqrtf(a2);
+    }
+    double s = (fabs((double)q[2]) + cx) * P.rdx[0];
+    if (c.ndim > 1) s = fma(fabs((double)q[3]) + cy, P.rdx[1], s);
+    if (c.ndim > 2) s = fma(fabs((double)q[4]) + cz, P.rdx[2], s);
     return s;
   } else {
-    double q[NVAR];
-    bad |= cons2prim<double>(u, c, q) ? 1 : 0;
+    double q[NV];
+    bad |= cons2prim<double, NV>(u, c, q) ? 1 : 0;
     const double p = c.gm1 * q[0] * q[1];
-    const double cs = sqrt(c.gamma * p / q[0]);
+    const double a2 = c.gamma * p / q[0];
+    double cx, cy, cz;
+    if constexpr (MHD) {
+      cx = fast_speed<double, 0>(q, a2);
+      cy = c.ndim > 1 ? fast_speed<double, 1>(q, a2) : 0.0;
+      cz = c.ndim > 2 ? fast_speed<double, 2>(q, a2) : 0.0;
+    } else {
+      cx = cy = cz = sqrt(a2);
+    }
     double s = 0.0;
-    s = s + (fabs(q[2]) + cs) / P.dx[0];
-    if (c.ndim > 1) s = s + (fabs(q[3]) + cs) / P.dx[1];
-    if (c.ndim > 2) s = s + (fabs(q[4]) + cs) / P.dx[2];
+    s = s + (fabs(q[2]) + cx) / P.dx[0];
+    if (c.ndim > 1) s = s + (fabs(q[3]) + cy) / P.dx[1];
+    if (c.ndim > 2) s = s + (fabs(q[4]) + cz) / P.dx[2];
     return s;
   }
 }
@@ -342,27 +415,86 @@ __device__ __forceinline__ void face_state(const RT q[NVAR], const FaceConsts<RT
   }
 }
 
-// Riemann flux in direction D at a face with primitive states qL, qR (Sec. 4
-// flux equation): lambda^+- = v_D +- c_s on each side, a+ = max(0, l+_L, l+_R),
-// a- = max(0, -l-_L, -l-_R); the printed flux uses lambda0 = max(a+, a-).
-// Physical flux F^D(U) = (rho v_D, rho v_D v + p e_D, (rho E + p) v_D).
+// Physical flux F^D of one MHD face state (the paper's MHD flux vectors with psi = 0;
+// the induction entries as in its x flux, v_D B_j - v_j B_D, which the y and z flux
+// vectors equal up to the permutation of axes), its conserved state U and its fast
+// magnetosonic speed c along D.  The FP64 path evaluates each entry in the order
+//   momentum  (rho v_D v_j + [j = D] (p + B^2/2)) - B_j B_D
+//   energy    ((rho E_h + p) v_D + B^2 v_D) - B_D (B . v)
+// with rho E_h = rho (e + v^2/2) the gas part of the energy variable.
 template <typename RT, int D>
-__device__ __forceinline__ void riemann_flux(const RT qL[NVAR], const RT qR[NVAR], const FaceConsts<RT>& k, int kind,
-                                             RT F[NVAR]) {
-  RT UL[NVAR], UR[NVAR], pL, pR, cL, cR;
-  face_state<RT>(qL, k, UL, pL, cL);
-  face_state<RT>(qR, k, UR, pR, cR);
-  RT FL[NVAR], FR[NVAR];
-  FL[0] = UL[1 + D];
-  FR[0] = UR[1 + D];
+__device__ __forceinline__ void mhd_face(const RT q[NVAR_MHD], const FaceConsts<RT>& k, RT U[NVAR_MHD],
+                                         RT F[NVAR_MHD], RT& c) {
+  const RT rho = q[0], e = q[1], vx = q[2], vy = q[3], vz = q[4], Bx = q[5], By = q[6], Bz = q[7];
+  const RT p = k.gm1 * rho * e;
+  const RT vd = q[2 + D], Bd = q[5 + D];
+  U[0] = rho;
+  U[1] = rho * vx;
+  U[2] = rho * vy;
+  U[3] = rho * vz;
+  U[5] = Bx;
+  U[6] = By;
+  U[7] = Bz;
+  F[0] = U[1 + D];
+  F[5 + D] = RT(0);
+  if constexpr (Fast<RT>::value) {
+    const RT a2 = k.gg1 * e;  // gamma p / rho
+    c = fast_speed<RT, D>(q, a2);
+    const RT B2 = fmaf(Bx, Bx, fmaf(By, By, Bz * Bz));
+    const RT Bv = fmaf(Bx, vx, fmaf(By, vy, Bz * vz));
+    const RT rEh = rho * fmaf(0.5f, fmaf(vx, vx, fmaf(vy, vy, vz * vz)), e);
+    U[4] = fmaf(0.5f, B2, rEh);
 #pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    FL[1 + j] = (j == D) ? UL[1 + D] * qL[2 + j] + pL : UL[1 + D] * qL[2 + j];
-    FR[1 + j] = (j == D) ? UR[1 + D] * qR[2 + j] + pR : UR[1 + D] * qR[2 + j];
+    for (int j = 0; j < 3; ++j)
+      F[1 + j] = fmaf(-q[5 + j], Bd, fmaf(U[1 + D], q[2 + j], j == D ? fmaf(0.5f, B2, p) : 0.0f));
+    F[4] = fmaf(-Bd, Bv, ((rEh + p) + B2) * vd);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if (j != D) F[5 + j] = fmaf(vd, q[5 + j], -q[2 + j] * Bd);
+  } else {
+    const RT a2 = k.gamma * p / rho;
+    c = fast_speed<RT, D>(q, a2);
+    const RT B2 = (Bx * Bx + By * By) + Bz * Bz;
+    const RT Bv = (Bx * vx + By * vy) + Bz * vz;
+    const RT rEh = rho * (e + RT(0.5) * ((vx * vx + vy * vy) + vz * vz));
+    U[4] = rEh + RT(0.5) * B2;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      F[1 + j] = (U[1 + D] * q[2 + j] + (j == D ? p + RT(0.5) * B2 : RT(0))) - q[5 + j] * Bd;
+    F[4] = ((rEh + p) * vd + B2 * vd) - Bd * Bv;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if (j != D) F[5 + j] = vd * q[5 + j] - q[2 + j] * Bd;
+  }
+}
+
+// Riemann flux in direction D at a face with primitive states qL, qR (Sec. 4
+// flux equation): lambda^+- = v_D +- c on each side (c the sound speed, or the
+// fast magnetosonic speed along D for MHD), a+ = max(0, l+_L, l+_R),
+// a- = max(0, -l-_L, -l-_R); the printed flux uses lambda0 = max(a+, a-).
+// Hydro physical flux F^D(U) = (rho v_D, rho v_D v + p e_D, (rho E + p) v_D).
+template <typename RT, int D, int NV = NVAR>
+__device__ __forceinline__ void riemann_flux(const RT qL[NV], const RT qR[NV], const FaceConsts<RT>& k, int kind,
+                                             RT F[NV]) {
+  RT UL[NV], UR[NV], FL[NV], FR[NV], cL, cR;
+  if constexpr (NV == NVAR_MHD) {
+    mhd_face<RT, D>(qL, k, UL, FL, cL);
+    mhd_face<RT, D>(qR, k, UR, FR, cR);
+  } else {
+    RT pL, pR;
+    face_state<RT>(qL, k, UL, pL, cL);
+    face_state<RT>(qR, k, UR, pR, cR);
+    FL[0] = UL[1 + D];
+    FR[0] = UR[1 + D];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      FL[1 + j] = (j == D) ? UL[1 + D] * qL[2 + j] + pL : UL[1 + D] * qL[2 + j];
+      FR[1 + j] = (j == D) ? UR[1 + D] * qR[2 + j] + pR : UR[1 + D] * qR[2 + j];
+    }
+    FL[4] = (UL[4] + pL) * qL[2 + D];
+    FR[4] = (UR[4] + pR) * qR[2 + D];
   }
   const RT vL = qL[2 + D], vR = qR[2 + D];
-  FL[4] = (UL[4] + pL) * vL;
-  FR[4] = (UR[4] + pR) * vR;
   const RT ap = fmax(RT(0), fmax(vL + cL, vR + cR));
   const RT am = fmax(RT(0), fmax(-(vL - cL), -(vR - cR)));
   if (kind == FLUX_HLL2) {
@@ -370,38 +502,43 @@ __device__ __forceinline__ void riemann_flux(const RT qL[NVAR], const RT qR[NVAR
     if constexpr (Fast<RT>::value) {
       const RT rden = 1.0f / den;
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) F[v] = fmaf(-apm, UR[v] - UL[v], fmaf(ap, FL[v], am * FR[v])) * rden;
+      for (int v = 0; v < NV; ++v) F[v] = fmaf(-apm, UR[v] - UL[v], fmaf(ap, FL[v], am * FR[v])) * rden;
     } else {
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) F[v] = ((ap * FL[v] + am * FR[v]) - apm * (UR[v] - UL[v])) / den;
+      for (int v = 0; v < NV; ++v) F[v] = ((ap * FL[v] + am * FR[v]) - apm * (UR[v] - UL[v])) / den;
     }
   } else {
     const RT lam = fmax(ap, am);
 #pragma unroll
-    for (int v = 0; v < NVAR; ++v) F[v] = RT(0.5) * madd(-lam, UR[v] - UL[v], FL[v] + FR[v]);
+    for (int v = 0; v < NV; ++v) F[v] = RT(0.5) * madd(-lam, UR[v] - UL[v], FL[v] + FR[v]);
   }
 }
 
 // Riemann flux of a face whose normal is x (dir = 0) or y (dir = 1), the
 // direction being a per-lane value: y faces are evaluated in the x frame with
-// the x and y velocity components exchanged, then the two momentum fluxes are
-// exchanged back.  The arithmetic is that of riemann_flux<RT, dir>.
-template <typename RT>
-__device__ __forceinline__ void riemann_flux_xy(RT qL[NVAR], RT qR[NVAR], bool ydir, const FaceConsts<RT>& k,
-                                                int kind, RT F[NVAR]) {
+// the x and y velocity (and field) components exchanged, then the two momentum
+// (and induction) fluxes are exchanged back.  The arithmetic is that of
+// riemann_flux<RT, dir>: every sum it reorders has two commuted operands.
+template <typename RT, int NV = NVAR>
+__device__ __forceinline__ void riemann_flux_xy(RT qL[NV], RT qR[NV], bool ydir, const FaceConsts<RT>& k,
+                                                int kind, RT F[NV]) {
+  auto swap = [](RT& a, RT& b) {
+    const RT t = a;
+    a = b;
+    b = t;
+  };
   if (ydir) {
-    RT t = qL[2];
-    qL[2] = qL[3];
-    qL[3] = t;
-    t = qR[2];
-    qR[2] = qR[3];
-    qR[3] = t;
+    swap(qL[2], qL[3]);
+    swap(qR[2], qR[3]);
+    if constexpr (NV == NVAR_MHD) {
+      swap(qL[5], qL[6]);
+      swap(qR[5], qR[6]);
+    }
   }
-  riemann_flux<RT, 0>(qL, qR, k, kind, F);
+  riemann_flux<RT, 0, NV>(qL, qR, k, kind, F);
   if (ydir) {
-    const RT t = F[1];
-    F[1] = F[2];
-    F[2] = t;
+    swap(F[1], F[2]);
+    if constexpr (NV == NVAR_MHD) swap(F[5], F[6]);
   }
 }
 

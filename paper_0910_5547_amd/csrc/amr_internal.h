@@ -27,6 +27,7 @@ struct CflArgs {
   const PatchDev* patches;
   const Tile* tiles;
   int ntiles, tx, ty, fast;         // fast: the mixed path's evaluation of the CFL rule
+  int nv;                           // conserved variables (5 hydro, 8 MHD)
   int* flag;
   unsigned long long* smax;      // per-level maxima
   Consts c;
@@ -56,12 +57,12 @@ __device__ __forceinline__ void wave_max_to(unsigned long long* dst, double v) {
   if ((threadIdx.x & 63) == 0 && v > 0) atomicMax(dst, (unsigned long long)__double_as_longlong(v));
 }
 
-hipError_t launch_stage(int mixed, int shape, int stage, int grid, hipStream_t s, const StageArgs& a);
-const void* stage_kernel_ptr(int mixed, int shape, int stage, bool rec);
+hipError_t launch_stage(int nv, int mixed, int shape, int stage, int grid, hipStream_t s, const StageArgs& a);
+const void* stage_kernel_ptr(int nv, int mixed, int shape, int stage, bool rec);
 hipError_t launch_cfl(int grid, hipStream_t s, const CflArgs& a);
 hipError_t launch_cfl_finalize(hipStream_t s, const unsigned long long* smax, int lmin, int lmax, int root,
                                double cfl, double* dt);
-hipError_t launch_copy_ghosts(hipStream_t s, const CopyOp* ops, const Work& w, const PatchDev* p, double* A);
+hipError_t launch_copy_ghosts(hipStream_t s, const CopyOp* ops, const Work& w, const PatchDev* p, double* A, int nv);
 hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, int n, unsigned long long v);
 hipError_t launch_fill_i32(hipStream_t s, int* p, int n, int v);
 
@@ -88,5 +89,12 @@ constexpr int SHAPE_TY[NSHAPES] = {1, 8, 4, 16, 8, 16, 12};
 constexpr int SHAPE_NT[NSHAPES] = {256, 256, 256, 256, 256, 512, 384};
 constexpr int SHAPE_SMALL = 4;
 constexpr int shape_tiles_per_wg(int shape) { return SHAPE_NT[shape] / (SHAPE_TX[shape] * SHAPE_TY[shape]); }
+// Shapes compiled for MHD (8 variables): 1D, 32 x 8 and 8 x 8 in both precisions;
+// 32 x 16 and 32 x 12 in FP32 only (in FP64 the primitive plane and face states of
+// eight variables exceed the LDS of a workgroup, or leave one workgroup per CU
+// that spills registers).
+constexpr bool mhd_shape_ok(int mixed, int shape) {
+  return shape == 0 || shape == 1 || shape == 4 || ((shape == 5 || shape == 6) && mixed);
+}
 
 }  // namespace amr

@@ -42,8 +42,11 @@ namespace amr {
 // tiles and synchronising only with itself.
 // NTH: threads per workgroup (256; 512 for the 32 x 16 tile, whose LDS allows one
 // workgroup per CU; 384 for 32 x 12, two per CU).
-template <typename RT, int TX, int TY, int NTH, int STAGE, bool REC, bool TH1>
-__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(Fast<RT>::value && !REC && NTH != 512 ? 3 : 2)))
+// MHD (NV = 8): two waves per SIMD in FP32; one in FP64, whose eight-variable LDS
+// tiles leave one workgroup per CU, so the kernel may use the whole register file.
+template <typename RT, int NV, int TX, int TY, int NTH, int STAGE, bool REC, bool TH1>
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(
+    NV == NVAR_MHD ? (Fast<RT>::value ? 2 : 1) : (Fast<RT>::value && !REC && NTH != 512 ? 3 : 2))))
 void stage_kernel(StageArgs a) {
   constexpr int TL = TX * TY;  // lanes (columns) per tile
   static_assert(TL == NTH || TL == 64, "a tile is the workgroup or one wavefront");
@@ -56,14 +59,14 @@ void stage_kernel(StageArgs a) {
   constexpr int HMAX = HASY ? (4 * (TX + TY) + TL - 1) / TL : 1;  // halo cells per lane
   // face slots: x faces first, slot row*(nxT+1) + f, then y faces, slot nfx + f*nxT + col
   constexpr int NSLOT = TY * (TX + 1) + (HASY ? YR * TX : 0);
-  __shared__ RT sP[WPB][NVAR][PR][TX + 4];        // primitives of the plane (+ face halo)
-  __shared__ RT sFL[WPB][NVAR][NSLOT], sFR[WPB][NVAR][NSLOT];  // face states; sFL then holds the flux
+  __shared__ RT sP[WPB][NV][PR][TX + 4];        // primitives of the plane (+ face halo)
+  __shared__ RT sFL[WPB][NV][NSLOT], sFR[WPB][NV][NSLOT];  // face states; sFL then holds the flux
   // conserved state of this lane's cell in planes k and k+1 (3D), for the update:
   // lane-private, kept in LDS rather than registers or a second read (FP32
   // instantiations with workgroup tiles; the others re-read the cell, their LDS
   // budget being spent)
-  constexpr bool RING = FAST && WPB == 1;
-  __shared__ double sV[RING ? 2 : 1][NVAR][RING ? NTH : 1];
+  constexpr bool RING = FAST && WPB == 1 && NV == NVAR;
+  __shared__ double sV[RING ? 2 : 1][NV][RING ? NTH : 1];
 
   const Consts C = a.c;
   const FaceConsts<RT> K{(RT)C.gamma, (RT)C.gm1, (RT)C.gg1};
@@ -106,49 +109,49 @@ void stage_kernel(StageArgs a) {
     // The REFLECT sign flip of the normal momentum is applied where loaded values
     // are used, not at the load: a flip right after the load would make the load
     // wait for its data, and the prefetches below would stop hiding latency.
-    auto load_col_raw = [&](int kz, double u[NVAR]) -> bool {  // true: negate u[3]
+    auto load_col_raw = [&](int kz, double u[NV]) -> bool {  // true: reflect in z
       bool fz = false;
       const int kk = map_index(kz, P.n[2], P.bc[4], P.bc[5], fz);
       const int64_t e = col0 + (int64_t)kk * pstride;
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) u[v] = a.V[e + v * P.S];
+      for (int v = 0; v < NV; ++v) u[v] = a.V[e + v * P.S];
       return fz;
     };
-    auto load_col = [&](int kz, double u[NVAR]) {
-      if (load_col_raw(kz, u)) u[3] = -u[3];
+    auto load_col = [&](int kz, double u[NV]) {
+      if (load_col_raw(kz, u)) reflect_flip<NV>(u, 2);
     };
 
     // z-direction register queue (3D only): primitives of planes k and k+1, the
     // z-slope of plane k and the flux F_{k-1/2}
-    RT qz[NVAR], qz1[NVAR], sgz[NVAR], Fzm[NVAR];
+    RT qz[NV], qz1[NV], sgz[NV], Fzm[NV];
     if (hasz) {
-      double u[NVAR];
-      RT qa[NVAR], qb[NVAR];
+      double u[NV];
+      RT qa[NV], qb[NV];
       load_col(T.z0 - 2, u);
-      bad |= cons2prim<RT>(u, C, qa);
+      bad |= cons2prim<RT, NV>(u, C, qa);
       load_col(T.z0 - 1, u);
-      bad |= cons2prim<RT>(u, C, qb);
+      bad |= cons2prim<RT, NV>(u, C, qb);
       load_col(T.z0, u);
-      bad |= cons2prim<RT>(u, C, qz);
+      bad |= cons2prim<RT, NV>(u, C, qz);
       if constexpr (RING) {
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) sV[T.z0 & 1][v][threadIdx.x] = u[v];
+        for (int v = 0; v < NV; ++v) sV[T.z0 & 1][v][threadIdx.x] = u[v];
       }
       load_col(T.z0 + 1, u);
-      bad |= cons2prim<RT>(u, C, qz1);
+      bad |= cons2prim<RT, NV>(u, C, qz1);
       if constexpr (RING) {
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) sV[(T.z0 + 1) & 1][v][threadIdx.x] = u[v];
+        for (int v = 0; v < NV; ++v) sV[(T.z0 + 1) & 1][v][threadIdx.x] = u[v];
       }
-      RT qL[NVAR], qR[NVAR];
+      RT qL[NV], qR[NV];
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) {
+      for (int v = 0; v < NV; ++v) {
         const RT sa = plm_slope_t<RT, TH1>(qa[v], qb[v], qz[v], theta);
         sgz[v] = plm_slope_t<RT, TH1>(qb[v], qz[v], qz1[v], theta);
         qL[v] = madd(RT(0.5), sa, qb[v]);
         qR[v] = madd(RT(-0.5), sgz[v], qz[v]);
       }
-      riemann_flux<RT, 2>(qL, qR, K, kind, Fzm);
+      riemann_flux<RT, 2, NV>(qL, qR, K, kind, Fzm);
     }
     // fine-face flux registers (Berger-Colella refluxing): faces on this patch's
     // boundary whose flux the coarse level must later see, dt/2 per stage
@@ -163,11 +166,11 @@ void stage_kernel(StageArgs a) {
     const int nhx = 4 * nyT, nhy = hasy ? 4 * nxT : 0;
     int hrow[HMAX], hcol[HMAX], hflip[HMAX];
     int64_t hbase[HMAX];  // element of the halo cell's source in plane 0 (boundary maps applied)
-    double Hn[HMAX][NVAR];
-    auto load_halo = [&](int s, int kz, double u[NVAR]) {  // raw: hflip applied at use
+    double Hn[HMAX][NV];
+    auto load_halo = [&](int s, int kz, double u[NV]) {  // raw: hflip applied at use
       const int64_t e = hbase[s] + (int64_t)kz * pstride;
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) u[v] = a.V[e + v * P.S];
+      for (int v = 0; v < NV; ++v) u[v] = a.V[e + v * P.S];
     };
 #pragma unroll
     for (int s = 0; s < HMAX; ++s) {
@@ -234,18 +237,18 @@ void stage_kernel(StageArgs a) {
       // this step's HBM read first: plane k+2 of the column in 3D (consumed by the z
       // flux after the x-y work), plane k itself in 1D/2D.  Issued by every lane
       // without a branch, so that nothing between here and the use waits for it.
-      double Vn2[NVAR];
+      double Vn2[NV];
       const bool fz2 = load_col_raw(hasz ? k + 2 : k, Vn2);
       // halo of plane k (prefetched) into LDS, then prefetch the halo of plane k+1
 #pragma unroll
       for (int s = 0; s < HMAX; ++s) {
         if (tid + s * TL < nhx + nhy) {
-          RT q[NVAR];
-          if (hflip[s] == 1) Hn[s][1] = -Hn[s][1];
-          if (hflip[s] == 2) Hn[s][2] = -Hn[s][2];
-          bad |= cons2prim<RT>(Hn[s], C, q);
+          RT q[NV];
+          if (hflip[s] == 1) reflect_flip<NV>(Hn[s], 0);
+          if (hflip[s] == 2) reflect_flip<NV>(Hn[s], 1);
+          bad |= cons2prim<RT, NV>(Hn[s], C, q);
 #pragma unroll
-          for (int v = 0; v < NVAR; ++v) sP[buf][v][hrow[s] + RO][hcol[s] + 2] = q[v];
+          for (int v = 0; v < NV; ++v) sP[buf][v][hrow[s] + RO][hcol[s] + 2] = q[v];
           if (k + 1 < T.z1) load_halo(s, k + 1, Hn[s]);
         }
       }
@@ -254,25 +257,25 @@ void stage_kernel(StageArgs a) {
       // their uses would leave loads pending on one path, and the next iteration would
       // wait for all memory at its first prefetch)
       {
-        RT qc[NVAR];
+        RT qc[NV];
         if (hasz) {
 #pragma unroll
-          for (int v = 0; v < NVAR; ++v) qc[v] = qz[v];
+          for (int v = 0; v < NV; ++v) qc[v] = qz[v];
         } else {
           // (the empty asm keeps this use inside the 1D/2D branch: hoisted above it, the
           // conversion would make 3D wait here for its plane k+2 prefetch)
 #pragma unroll
-          for (int v = 0; v < NVAR; ++v) asm volatile("" : "+v"(Vn2[v]));
-          if (fz2) Vn2[3] = -Vn2[3];
-          bad |= cons2prim<RT>(Vn2, C, qc);
+          for (int v = 0; v < NV; ++v) asm volatile("" : "+v"(Vn2[v]));
+          if (fz2) reflect_flip<NV>(Vn2, 2);
+          bad |= cons2prim<RT, NV>(Vn2, C, qc);
           if constexpr (RING) {
 #pragma unroll
-            for (int v = 0; v < NVAR; ++v) sV[k & 1][v][threadIdx.x] = Vn2[v];
+            for (int v = 0; v < NV; ++v) sV[k & 1][v][threadIdx.x] = Vn2[v];
           }
         }
         if (act) {
 #pragma unroll
-          for (int v = 0; v < NVAR; ++v) sP[buf][v][cy + RO][cx + 2] = qc[v];
+          for (int v = 0; v < NV; ++v) sP[buf][v][cy + RO][cx + 2] = qc[v];
         }
       }
       tile_sync();  // (A) plane primitives ready; previous plane's fluxes consumed
@@ -280,7 +283,7 @@ void stage_kernel(StageArgs a) {
       // (1) slopes, once per cell, as face states
       if (act) {
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) {
+        for (int v = 0; v < NV; ++v) {
           const RT* pl = &sP[buf][v][0][0];
           const RT q0 = pl[pc_own];
           const RT sx = plm_slope_t<RT, TH1>(pl[pc_own - 1], q0, pl[pc_own + 1], theta);
@@ -297,7 +300,7 @@ void stage_kernel(StageArgs a) {
         RT* dst = left_h ? &sFL[buf][0][slot_h] : &sFR[buf][0][slot_h];
         const RT hs = left_h ? RT(0.5) : RT(-0.5);
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) {
+        for (int v = 0; v < NV; ++v) {
           const RT* pl = &sP[buf][v][0][0];
           const RT q0 = pl[pc_h];
           const RT sg = plm_slope_t<RT, TH1>(pl[pc_h - st_h], q0, pl[pc_h + st_h], theta);
@@ -309,21 +312,21 @@ void stage_kernel(StageArgs a) {
       // the stage input of this cell (from the lane's LDS ring, else re-read) and, in
       // stage 2, U^n: the global loads are issued before the face pass so that it
       // hides their latency (wavefront tiles, short of VGPRs, issue them after it)
-      double Vc[NVAR], U0c[NVAR];
+      double Vc[NV], U0c[NV];
       const int64_t ecell = col0 + (int64_t)k * pstride;
       auto load_u0 = [&] {
         if (STAGE == 2) {
 #pragma unroll
-          for (int v = 0; v < NVAR; ++v) U0c[v] = a.U0[ecell + v * P.S];
+          for (int v = 0; v < NV; ++v) U0c[v] = a.U0[ecell + v * P.S];
         }
       };
       auto load_vc = [&] {
         if constexpr (RING) {
 #pragma unroll
-          for (int v = 0; v < NVAR; ++v) Vc[v] = sV[k & 1][v][threadIdx.x];
+          for (int v = 0; v < NV; ++v) Vc[v] = sV[k & 1][v][threadIdx.x];
         } else {
 #pragma unroll
-          for (int v = 0; v < NVAR; ++v) Vc[v] = a.V[ecell + v * P.S];
+          for (int v = 0; v < NV; ++v) Vc[v] = a.V[ecell + v * P.S];
         }
       };
       if constexpr (WPB == 1) {
@@ -332,49 +335,49 @@ void stage_kernel(StageArgs a) {
       }
 
       // (2) every x- and y-face flux of the block, once, written over its left state
-      auto face_at = [&](int slot, RT qL[NVAR], RT qR[NVAR]) {
+      auto face_at = [&](int slot, RT qL[NV], RT qR[NV]) {
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) {
+        for (int v = 0; v < NV; ++v) {
           qL[v] = sFL[buf][v][slot];
           qR[v] = sFR[buf][v][slot];
         }
       };
       if (act) {
-        RT qL[NVAR], qR[NVAR], F[NVAR];
+        RT qL[NV], qR[NV], F[NV];
         face_at(xs_own, qL, qR);
-        riemann_flux<RT, 0>(qL, qR, K, kind, F);
+        riemann_flux<RT, 0, NV>(qL, qR, K, kind, F);
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) sFL[buf][v][xs_own] = F[v];
+        for (int v = 0; v < NV; ++v) sFL[buf][v][xs_own] = F[v];
         if constexpr (HASY) {
           face_at(ys_own, qL, qR);
           // (the x-frame evaluation, as for every y face: riemann_flux<RT, 1> sums the
           // kinetic energy in another order, and in the mixed path its FP32 rounding
           // would differ from the coarse level's recomputed flux in refluxing)
-          riemann_flux_xy<RT>(qL, qR, true, K, kind, F);
+          riemann_flux_xy<RT, NV>(qL, qR, true, K, kind, F);
 #pragma unroll
-          for (int v = 0; v < NVAR; ++v) sFL[buf][v][ys_own] = F[v];
+          for (int v = 0; v < NV; ++v) sFL[buf][v][ys_own] = F[v];
         }
       }
       if (tid < nfe) {
-        RT qL[NVAR], qR[NVAR], F[NVAR];
+        RT qL[NV], qR[NV], F[NV];
         face_at(slot_e, qL, qR);
-        riemann_flux_xy<RT>(qL, qR, ydir_e, K, kind, F);
+        riemann_flux_xy<RT, NV>(qL, qR, ydir_e, K, kind, F);
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) sFL[buf][v][slot_e] = F[v];
+        for (int v = 0; v < NV; ++v) sFL[buf][v][slot_e] = F[v];
       }
       // z-face flux F_{k+1/2} of this column from the register queue
-      RT Fzp[NVAR], qn2[NVAR], sg1[NVAR];
+      RT Fzp[NV], qn2[NV], sg1[NV];
       if (hasz) {
-        RT qL[NVAR], qR[NVAR];
-        if (fz2) Vn2[3] = -Vn2[3];
-        bad |= cons2prim<RT>(Vn2, C, qn2);
+        RT qL[NV], qR[NV];
+        if (fz2) reflect_flip<NV>(Vn2, 2);
+        bad |= cons2prim<RT, NV>(Vn2, C, qn2);
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) {
+        for (int v = 0; v < NV; ++v) {
           sg1[v] = plm_slope_t<RT, TH1>(qz[v], qz1[v], qn2[v], theta);
           qL[v] = madd(RT(0.5), sgz[v], qz[v]);
           qR[v] = madd(RT(-0.5), sg1[v], qz1[v]);
         }
-        riemann_flux<RT, 2>(qL, qR, K, kind, Fzp);
+        riemann_flux<RT, 2, NV>(qL, qR, K, kind, Fzp);
       }
       tile_sync();  // (C) fluxes ready
       if constexpr (WPB > 1) {
@@ -388,7 +391,7 @@ void stage_kernel(StageArgs a) {
       // this cell's faces on a coarse/fine boundary of the patch also go to the
       // refluxing registers (+= dt/2 F, Berger-Colella)
       {
-        double L[NVAR];
+        double L[NV];
         const int sx = xs_own, sy = ys_own;
         // at most one x, one y and one z face of this cell lies on a recorded patch
         // face (patches of a refined level are at least 2 cells wide); register
@@ -405,7 +408,7 @@ void stage_kernel(StageArgs a) {
           *r = *r + hdt * F;
         };
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) {
+        for (int v = 0; v < NV; ++v) {
           const double fl = (double)sFL[buf][v][sx], fh = (double)sFL[buf][v][sx + 1];
           const double d = fh - fl;
           if constexpr (FAST) L[v] = -d * P.rdx[0];
@@ -414,7 +417,7 @@ void stage_kernel(StageArgs a) {
         }
         if (hasy) {
 #pragma unroll
-          for (int v = 0; v < NVAR; ++v) {
+          for (int v = 0; v < NV; ++v) {
             const double fl = (double)sFL[buf][v][sy], fh = (double)sFL[buf][v][sy + nxT];
             const double d = fh - fl;
             if constexpr (FAST) L[v] = fma(-d, P.rdx[1], L[v]);
@@ -424,7 +427,7 @@ void stage_kernel(StageArgs a) {
         }
         if (hasz) {
 #pragma unroll
-          for (int v = 0; v < NVAR; ++v) {
+          for (int v = 0; v < NV; ++v) {
             if (REC && rz >= 0) record(rz + ((int64_t)v * P.n[1] + j) * P.n[0] + i, (double)(k == 0 ? Fzm[v] : Fzp[v]));
             const double d = (double)Fzp[v] - (double)Fzm[v];
             if constexpr (FAST) L[v] = fma(-d, P.rdx[2], L[v]);
@@ -438,9 +441,9 @@ void stage_kernel(StageArgs a) {
         }
         // TVD-RK2 (Sec. 4): stage 1 U1 = U + dt L(U); stage 2 U^{n+1} = U^n/2 + (U1 + dt L(U1))/2
         const int64_t e = ecell;
-        double un[NVAR];
+        double un[NV];
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) {
+        for (int v = 0; v < NV; ++v) {
           double u1;
           if constexpr (FAST) u1 = fma(dt, L[v], Vc[v]);
           else u1 = Vc[v] + dt * L[v];
@@ -448,8 +451,8 @@ void stage_kernel(StageArgs a) {
         }
         if (act) {
 #pragma unroll
-          for (int v = 0; v < NVAR; ++v) a.out[e + v * P.S] = un[v];
-          if (STAGE == 2 && a.smax != nullptr) smax = fmax(smax, cell_speed<FAST>(un, C, P, bad));
+          for (int v = 0; v < NV; ++v) a.out[e + v * P.S] = un[v];
+          if (STAGE == 2 && a.smax != nullptr) smax = fmax(smax, cell_speed<FAST, NV>(un, C, P, bad));
         }
       }
     }
@@ -466,7 +469,7 @@ void stage_kernel(StageArgs a) {
 // Max signal speed over the active cells of the tile list (one plane of a tile
 // per workgroup iteration); the block max is merged into smax[level] with a
 // 64-bit atomicMax on the bit pattern (non-negative doubles order as integers).
-template <bool FAST>
+template <bool FAST, int NV>
 __global__ __launch_bounds__(NT) void cfl_kernel(CflArgs a) {
   const Consts C = a.c;
   int bad = 0;
@@ -481,10 +484,10 @@ __global__ __launch_bounds__(NT) void cfl_kernel(CflArgs a) {
       const int kk = c / per_plane, r = c - kk * per_plane;
       const int jj = r / nxT, ii = r - jj * nxT;
       const int64_t e = cell_elem(P, T.x0 + ii, T.y0 + jj, T.z0 + kk);
-      double u[NVAR];
+      double u[NV];
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) u[v] = a.U[e + v * P.S];
-      smax = fmax(smax, cell_speed<FAST>(u, C, P, bad));
+      for (int v = 0; v < NV; ++v) u[v] = a.U[e + v * P.S];
+      smax = fmax(smax, cell_speed<FAST, NV>(u, C, P, bad));
     }
     block_max_to(a.smax + P.level, smax);
   }
@@ -506,9 +509,9 @@ __global__ void cfl_finalize(const unsigned long long* smax, int lmin, int lmax,
 }
 
 // ------------------------------------------------------------------ ghosts
-// Same-level EXTERNAL ghost fill, one ghost cell per lane.
+// Same-level EXTERNAL ghost fill, one ghost cell (all nv variables) per lane.
 __global__ __launch_bounds__(NT) void copy_ghosts(const CopyOp* __restrict__ ops, Work w,
-                                                  const PatchDev* __restrict__ patches, double* A) {
+                                                  const PatchDev* __restrict__ patches, double* A, int nv) {
   int c;
   const int o = work_item(w, c);
   if (o < 0) return;
@@ -520,8 +523,7 @@ __global__ __launch_bounds__(NT) void copy_ghosts(const CopyOp* __restrict__ ops
   const int i = op.lo[0] + b[0], j = op.lo[1] + b[1], k = op.lo[2] + b[2];
   const int64_t ed = cell_elem(D, i, j, k);
   const int64_t es = cell_elem(S, i + op.sh[0], j + op.sh[1], k + op.sh[2]);
-#pragma unroll
-  for (int v = 0; v < NVAR; ++v) A[ed + v * D.S] = A[es + v * S.S];
+  for (int v = 0; v < nv; ++v) A[ed + v * D.S] = A[es + v * S.S];
 }
 
 // dt_l = dt0 / 2^l: factor-2 subcycling of a block-structured hierarchy.
@@ -541,79 +543,138 @@ __global__ void fill_i32(int* p, int n, int v) {
 }
 
 // ------------------------------------------------------------------ launchers
-template <typename RT, int TX, int TY, int NTH, int STAGE>
+// Instantiated (NV, precision, shape) combinations: every shape for hydro; for MHD
+// (no refluxing registers: single-level tables) the shapes whose LDS fits
+// (mhd_shape_ok), so a launch of another combination returns hipErrorInvalidValue.
+template <typename RT, int NV, int TX, int TY, int NTH, int STAGE>
 static hipError_t launch_stage_t(dim3 grid, hipStream_t s, const StageArgs& a) {
   const bool th1 = a.c.theta == 1.0;
   if (a.reg) {
-    if (th1) hipLaunchKernelGGL((stage_kernel<RT, TX, TY, NTH, STAGE, true, true>), grid, dim3(NTH), 0, s, a);
-    else hipLaunchKernelGGL((stage_kernel<RT, TX, TY, NTH, STAGE, true, false>), grid, dim3(NTH), 0, s, a);
+    if constexpr (NV == NVAR) {
+      if (th1) hipLaunchKernelGGL((stage_kernel<RT, NV, TX, TY, NTH, STAGE, true, true>), grid, dim3(NTH), 0, s, a);
+      else hipLaunchKernelGGL((stage_kernel<RT, NV, TX, TY, NTH, STAGE, true, false>), grid, dim3(NTH), 0, s, a);
+    } else {
+      return hipErrorInvalidValue;
+    }
   } else {
-    if (th1) hipLaunchKernelGGL((stage_kernel<RT, TX, TY, NTH, STAGE, false, true>), grid, dim3(NTH), 0, s, a);
-    else hipLaunchKernelGGL((stage_kernel<RT, TX, TY, NTH, STAGE, false, false>), grid, dim3(NTH), 0, s, a);
+    if (th1) hipLaunchKernelGGL((stage_kernel<RT, NV, TX, TY, NTH, STAGE, false, true>), grid, dim3(NTH), 0, s, a);
+    else hipLaunchKernelGGL((stage_kernel<RT, NV, TX, TY, NTH, STAGE, false, false>), grid, dim3(NTH), 0, s, a);
   }
   return hipGetLastError();
 }
 
-template <typename RT, int TX, int TY, int NTH = NT>
+template <typename RT, int NV, int TX, int TY, int NTH = NT>
 static hipError_t launch_stage_s(int stage, dim3 grid, hipStream_t s, const StageArgs& a) {
-  return stage == 1 ? launch_stage_t<RT, TX, TY, NTH, 1>(grid, s, a) : launch_stage_t<RT, TX, TY, NTH, 2>(grid, s, a);
+  return stage == 1 ? launch_stage_t<RT, NV, TX, TY, NTH, 1>(grid, s, a)
+                    : launch_stage_t<RT, NV, TX, TY, NTH, 2>(grid, s, a);
 }
 
 template <typename RT>
 static hipError_t launch_stage_rt(int shape, int stage, dim3 grid, hipStream_t s, const StageArgs& a) {
   switch (shape) {
-    case 0: return launch_stage_s<RT, 256, 1>(stage, grid, s, a);
-    case 1: return launch_stage_s<RT, 32, 8>(stage, grid, s, a);
-    case 2: return launch_stage_s<RT, 64, 4>(stage, grid, s, a);
-    case 3: return launch_stage_s<RT, 16, 16>(stage, grid, s, a);
-    case 4: return launch_stage_s<RT, 8, 8>(stage, grid, s, a);
-    case 5: return launch_stage_s<RT, 32, 16, 512>(stage, grid, s, a);
-    case 6: return launch_stage_s<RT, 32, 12, 384>(stage, grid, s, a);
+    case 0: return launch_stage_s<RT, NVAR, 256, 1>(stage, grid, s, a);
+    case 1: return launch_stage_s<RT, NVAR, 32, 8>(stage, grid, s, a);
+    case 2: return launch_stage_s<RT, NVAR, 64, 4>(stage, grid, s, a);
+    case 3: return launch_stage_s<RT, NVAR, 16, 16>(stage, grid, s, a);
+    case 4: return launch_stage_s<RT, NVAR, 8, 8>(stage, grid, s, a);
+    case 5: return launch_stage_s<RT, NVAR, 32, 16, 512>(stage, grid, s, a);
+    case 6: return launch_stage_s<RT, NVAR, 32, 12, 384>(stage, grid, s, a);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_stage(int mixed, int shape, int stage, int grid, hipStream_t s, const StageArgs& a) {
+template <typename RT>
+static hipError_t launch_stage_mhd(int shape, int stage, dim3 grid, hipStream_t s, const StageArgs& a) {
+  switch (shape) {
+    case 0: return launch_stage_s<RT, NVAR_MHD, 256, 1>(stage, grid, s, a);
+    case 1: return launch_stage_s<RT, NVAR_MHD, 32, 8>(stage, grid, s, a);
+    case 4: return launch_stage_s<RT, NVAR_MHD, 8, 8>(stage, grid, s, a);
+    case 5:
+      if constexpr (Fast<RT>::value) return launch_stage_s<RT, NVAR_MHD, 32, 16, 512>(stage, grid, s, a);
+      else return hipErrorInvalidValue;
+    case 6:
+      if constexpr (Fast<RT>::value) return launch_stage_s<RT, NVAR_MHD, 32, 12, 384>(stage, grid, s, a);
+      else return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_stage(int nv, int mixed, int shape, int stage, int grid, hipStream_t s, const StageArgs& a) {
+  if (nv == NVAR_MHD) {
+    if (!mhd_shape_ok(mixed, shape)) return hipErrorInvalidValue;
+    if (mixed) return launch_stage_mhd<float>(shape, stage, dim3(grid), s, a);
+    return launch_stage_mhd<double>(shape, stage, dim3(grid), s, a);
+  }
   if (mixed) return launch_stage_rt<float>(shape, stage, dim3(grid), s, a);
   return launch_stage_rt<double>(shape, stage, dim3(grid), s, a);
 }
 
 // The theta = 1 instantiation with or without register recording (the theta
-// instantiations share a resource class; the recording ones have their own).
-const void* stage_kernel_ptr(int mixed, int shape, int stage, bool rec) {
-#define AMR_KP(RT, TX, TY, NTH)                                                                               \
-  (stage == 1 ? (rec ? reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, NTH, 1, true, true>)           \
-                     : reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, NTH, 1, false, true>))         \
-              : (rec ? reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, NTH, 2, true, true>)           \
-                     : reinterpret_cast<const void*>(&stage_kernel<RT, TX, TY, NTH, 2, false, true>)))
+// instantiations share a resource class; the recording ones have their own), or
+// nullptr for a combination that is not compiled.
+const void* stage_kernel_ptr(int nv, int mixed, int shape, int stage, bool rec) {
+#define AMR_KP(RT, NV, TX, TY, NTH)                                                                           \
+  (stage == 1 ? (rec ? reinterpret_cast<const void*>(&stage_kernel<RT, NV, TX, TY, NTH, 1, true, true>)       \
+                     : reinterpret_cast<const void*>(&stage_kernel<RT, NV, TX, TY, NTH, 1, false, true>))     \
+              : (rec ? reinterpret_cast<const void*>(&stage_kernel<RT, NV, TX, TY, NTH, 2, true, true>)       \
+                     : reinterpret_cast<const void*>(&stage_kernel<RT, NV, TX, TY, NTH, 2, false, true>)))
+#define AMR_KPM(RT, TX, TY, NTH)                                                                              \
+  (rec ? nullptr                                                                                             \
+       : (stage == 1 ? reinterpret_cast<const void*>(&stage_kernel<RT, NVAR_MHD, TX, TY, NTH, 1, false, true>) \
+                     : reinterpret_cast<const void*>(&stage_kernel<RT, NVAR_MHD, TX, TY, NTH, 2, false, true>)))
+  if (nv == NVAR_MHD) {
+    if (!mhd_shape_ok(mixed, shape)) return nullptr;
+    if (mixed) {
+      switch (shape) {
+        case 0: return AMR_KPM(float, 256, 1, 256);
+        case 1: return AMR_KPM(float, 32, 8, 256);
+        case 4: return AMR_KPM(float, 8, 8, 256);
+        case 5: return AMR_KPM(float, 32, 16, 512);
+        case 6: return AMR_KPM(float, 32, 12, 384);
+      }
+    } else {
+      switch (shape) {
+        case 0: return AMR_KPM(double, 256, 1, 256);
+        case 1: return AMR_KPM(double, 32, 8, 256);
+        case 4: return AMR_KPM(double, 8, 8, 256);
+      }
+    }
+    return nullptr;
+  }
   if (mixed) {
     switch (shape) {
-      case 0: return AMR_KP(float, 256, 1, 256);
-      case 1: return AMR_KP(float, 32, 8, 256);
-      case 2: return AMR_KP(float, 64, 4, 256);
-      case 3: return AMR_KP(float, 16, 16, 256);
-      case 4: return AMR_KP(float, 8, 8, 256);
-      case 5: return AMR_KP(float, 32, 16, 512);
-      case 6: return AMR_KP(float, 32, 12, 384);
+      case 0: return AMR_KP(float, NVAR, 256, 1, 256);
+      case 1: return AMR_KP(float, NVAR, 32, 8, 256);
+      case 2: return AMR_KP(float, NVAR, 64, 4, 256);
+      case 3: return AMR_KP(float, NVAR, 16, 16, 256);
+      case 4: return AMR_KP(float, NVAR, 8, 8, 256);
+      case 5: return AMR_KP(float, NVAR, 32, 16, 512);
+      case 6: return AMR_KP(float, NVAR, 32, 12, 384);
     }
   } else {
     switch (shape) {
-      case 0: return AMR_KP(double, 256, 1, 256);
-      case 1: return AMR_KP(double, 32, 8, 256);
-      case 2: return AMR_KP(double, 64, 4, 256);
-      case 3: return AMR_KP(double, 16, 16, 256);
-      case 4: return AMR_KP(double, 8, 8, 256);
-      case 5: return AMR_KP(double, 32, 16, 512);
-      case 6: return AMR_KP(double, 32, 12, 384);
+      case 0: return AMR_KP(double, NVAR, 256, 1, 256);
+      case 1: return AMR_KP(double, NVAR, 32, 8, 256);
+      case 2: return AMR_KP(double, NVAR, 64, 4, 256);
+      case 3: return AMR_KP(double, NVAR, 16, 16, 256);
+      case 4: return AMR_KP(double, NVAR, 8, 8, 256);
+      case 5: return AMR_KP(double, NVAR, 32, 16, 512);
+      case 6: return AMR_KP(double, NVAR, 32, 12, 384);
     }
   }
 #undef AMR_KP
+#undef AMR_KPM
   return nullptr;
 }
 
 hipError_t launch_cfl(int grid, hipStream_t s, const CflArgs& a) {
-  if (a.fast) hipLaunchKernelGGL(cfl_kernel<true>, dim3(grid), dim3(NT), 0, s, a);
-  else hipLaunchKernelGGL(cfl_kernel<false>, dim3(grid), dim3(NT), 0, s, a);
+  if (a.nv == NVAR_MHD) {
+    if (a.fast) hipLaunchKernelGGL((cfl_kernel<true, NVAR_MHD>), dim3(grid), dim3(NT), 0, s, a);
+    else hipLaunchKernelGGL((cfl_kernel<false, NVAR_MHD>), dim3(grid), dim3(NT), 0, s, a);
+  } else {
+    if (a.fast) hipLaunchKernelGGL((cfl_kernel<true, NVAR>), dim3(grid), dim3(NT), 0, s, a);
+    else hipLaunchKernelGGL((cfl_kernel<false, NVAR>), dim3(grid), dim3(NT), 0, s, a);
+  }
   return hipGetLastError();
 }
 hipError_t launch_cfl_finalize(hipStream_t s, const unsigned long long* smax, int lmin, int lmax, int root,
@@ -621,8 +682,8 @@ hipError_t launch_cfl_finalize(hipStream_t s, const unsigned long long* smax, in
   hipLaunchKernelGGL(cfl_finalize, dim3(1), dim3(64), 0, s, smax, lmin, lmax, root, cfl, dt);
   return hipGetLastError();
 }
-hipError_t launch_copy_ghosts(hipStream_t s, const CopyOp* ops, const Work& w, const PatchDev* p, double* A) {
-  hipLaunchKernelGGL(copy_ghosts, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, A);
+hipError_t launch_copy_ghosts(hipStream_t s, const CopyOp* ops, const Work& w, const PatchDev* p, double* A, int nv) {
+  hipLaunchKernelGGL(copy_ghosts, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, A, nv);
   return hipGetLastError();
 }
 hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, int n, unsigned long long v) {

@@ -12,15 +12,15 @@ def log(*a):
 
 
 def active_all(ps, U):
-    """(5, cells) array of the active cells of every patch (patch order)."""
-    return np.concatenate([ps.active(U, p).reshape(5, -1) for p in range(ps.npatch)], axis=1)
+    """(nvar, cells) array of the active cells of every patch (patch order)."""
+    return np.concatenate([ps.active(U, p).reshape(ps.nvar, -1) for p in range(ps.npatch)], axis=1)
 
 
 def rel_err(got, ref):
     """Per-variable max |got - ref| / max |ref| (the relative-per-cell tolerance with the
     variable's own scale, so that near-zero momenta do not make it meaningless)."""
     out = []
-    for k in range(5):
+    for k in range(len(ref)):
         scale = max(np.max(np.abs(ref[k])), 1e-300)
         out.append(float(np.max(np.abs(got[k] - ref[k])) / scale))
     return out
@@ -31,4 +31,4 @@ def l1_rel(got, ref, k=0):
 
 
 def totals(A):
-    return [math.fsum(A[k]) for k in range(5)]
+    return [math.fsum(A[k]) for k in range(len(A))]

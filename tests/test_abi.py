@@ -93,7 +93,8 @@ def _create(amr, ps, **kw):
     lambda d, ph: d[0].bc.__setitem__(0, 1),          # periodic on one side only
     lambda d, ph: setattr(d[0], "level", -1),
     lambda d, ph: d[0].reserved.__setitem__(0, 1),
-    lambda d, ph: setattr(ph, "nvar", 8),
+    lambda d, ph: setattr(ph, "nvar", 6),
+    lambda d, ph: setattr(ph, "nvar", 8),             # storage laid out for 5 variables: 8 overlap
     lambda d, ph: setattr(ph, "ndim", 4),
     lambda d, ph: setattr(ph, "gamma", 1.0),
     lambda d, ph: setattr(ph, "theta", 2.5),
@@ -155,3 +156,15 @@ def test_malformed_hierarchies_are_rejected(amr):
     descs = amr.descriptors(ps)
     ph = amr.physics(ps, periodic=7, domain=(8, 8, 8))
     assert amr.lib().amr_patch_table_create(descs, len(descs), C.byref(ph), None, C.byref(h)) == amr.AMR_EINVAL
+
+
+def test_mhd_tables_are_single_level(amr):
+    """nvar 8 (ideal MHD) is accepted by validation only for tables whose patches are all on level 0."""
+    ps = W.make_patchset(3, [[8, 8, 8], [8, 8, 8]], 2, [W.BC_EXTERNAL] * 6, level=[0, 1],
+                         lo=[[0, 0, 0], [4, 4, 4]], nvar=W.NVAR_MHD)
+    descs = amr.descriptors(ps)
+    ph = amr.physics(ps, periodic=7, domain=(8, 8, 8))
+    assert ph.nvar == 8
+    h = C.c_void_p()
+    assert amr.lib().amr_patch_table_create(descs, len(descs), C.byref(ph), None, C.byref(h)) == amr.AMR_EINVAL
+    assert not h.value
