@@ -77,7 +77,10 @@ typedef int32_t amr_status;
  *   REFLECT  ghost = mirror image across the face, normal momentum (and, for MHD,
  *            normal field) negated,
  *   EXTERNAL ghost = filled by the library from the same-level patch that
- *            covers it (sibling copy); ghost storage is read by the stencil. */
+ *            covers it (sibling copy); ghost storage is read by the stencil.
+ *            In a single-level table, a face whose ghost cells all lie in one
+ *            sibling with the same n and ng is read from that sibling's cells
+ *            directly and its ghost storage is left untouched. */
 enum { AMR_BC_OUTFLOW = 0, AMR_BC_PERIODIC = 1, AMR_BC_REFLECT = 2, AMR_BC_EXTERNAL = 3 };
 /* Face flux: AMR_FLUX_PAPER = the formula printed in Sec. 4,
  *   F = (F_L + F_R - lambda0 (U_R - U_L)) / 2, lambda0 = max(a+, a-);
@@ -234,8 +237,9 @@ amr_status amr_autotune(amr_table* table, const double* U, const double* dt_dev,
                         hipStream_t stream, float* ms_best);
 
 /* Durations of the two stage kernels of the last AMR_STEP_TIMED step (in ms,
- * from HIP events on the step's stream; summed over launches in the plain
- * form).  Waits for that step.  AMR_ESTATE if no timed step was run. */
+ * from HIP events on the step's stream around each stage's launches, so the
+ * ghost fill of the stage 2 input is in neither; summed over launches in the
+ * plain form).  Waits for that step.  AMR_ESTATE if no timed step was run. */
 amr_status amr_table_last_stage_ms(amr_table* table, float ms[2]);
 
 const char* amr_status_string(amr_status status);

@@ -71,7 +71,7 @@ struct amr_table {
   const double* fused_U = nullptr;
   int fused_level = -2;
   int occ[2][2][NSHAPES][2][2] = {};  // resident stage workgroups per CU: [mhd][mixed][shape][stage][recording]
-  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // AMR_STEP_TIMED: before/between/after the stages
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // AMR_STEP_TIMED: around each stage kernel
   bool timed_valid = false;
   // ---- hierarchy (levels > 0 present): coarse/fine coupling plans, see build_hierarchy
   std::vector<char> has_kids;                   // per level: a finer level exists
@@ -352,7 +352,8 @@ amr_status enqueue_stage(amr_table* t, TileSet* ts, int stage, const double* V, 
 // (substep+1)/2 (stage 2 input).  A level with children also writes its physical
 // ghosts into storage, keeps U^n (the snapshot its children interpolate from),
 // refills U^{n+1}'s ghosts and clears its children's registers.  With `ev`, record
-// ev[0] before stage 1, ev[1] between the stages and ev[2] after stage 2.
+// ev[0] and ev[1] around the stage 1 kernel, ev[2] and ev[3] around the stage 2 kernel
+// (the ghost fill of stage 2's input lies between ev[1] and ev[2]).
 amr_status enqueue_step(amr_table* t, double* U, const double* dt, int level, uint32_t flags, hipStream_t s,
                         hipEvent_t* ev = nullptr, int substep = 0) {
   TileSet* ts = nullptr;
@@ -375,12 +376,13 @@ amr_status enqueue_step(amr_table* t, double* U, const double* dt, int level, ui
   if (ev) HIPCHECK(hipEventRecord(ev[0], s));
   st = enqueue_stage(t, ts, 1, U, nullptr, t->U1, dt, fuse, rec, s);
   if (st != AMR_OK) return st;
+  if (ev) HIPCHECK(hipEventRecord(ev[1], s));
   st = enqueue_ghosts(t, t->U1, U, level, a2, s);
   if (st != AMR_OK) return st;
-  if (ev) HIPCHECK(hipEventRecord(ev[1], s));
+  if (ev) HIPCHECK(hipEventRecord(ev[2], s));
   st = enqueue_stage(t, ts, 2, t->U1, U, U, dt, fuse, rec, s);
   if (st != AMR_OK) return st;
-  if (ev) HIPCHECK(hipEventRecord(ev[2], s));
+  if (ev) HIPCHECK(hipEventRecord(ev[3], s));
   if (kids) {
     st = enqueue_ghosts(t, U, U, level, a2, s);
     if (st != AMR_OK) return st;
@@ -570,6 +572,7 @@ amr_status build_ghost_plan(amr_table* t, std::vector<CopyOp>& ops, std::vector<
                 cov[((size_t)z * bsz[1] + y) * bsz[0] + x]++;
               }
         };
+        const size_t first_op = ops.size();
         for (int q = 0; q < np; ++q) {
           const amr_patch_desc& Q = t->desc[q];
           if (Q.level != D.level) continue;
@@ -598,6 +601,23 @@ amr_status build_ghost_plan(amr_table* t, std::vector<CopyOp>& ops, std::vector<
           if (empty) continue;
           mark(op.lo, op.sz);
           ops.push_back(op);
+        }
+        // Single-level tables: a face whose whole ghost slab lies in one sibling of the
+        // same stored shape is read by the stage kernel from that sibling's cells (an
+        // element offset, PatchDev::nbo) and needs no copy.  (Hierarchies keep the
+        // copies: refluxing and prolongation read ghost storage.)
+        if (t->max_level == 0 && ops.size() == first_op + 1) {
+          const CopyOp& op = ops.back();
+          const amr_patch_desc& Q = t->desc[op.src];
+          bool whole = Q.ng == D.ng;
+          for (int e = 0; e < 3; ++e) whole = whole && op.sz[e] == bsz[e] && Q.n[e] == D.n[e];
+          if (whole) {
+            PatchDev& P = t->pdev[p];
+            const int f = 2 * d + side;
+            P.dmask |= 1 << f;
+            P.nbo[f] = (t->pdev[op.src].off - P.off) + ((int64_t)op.sh[2] * P.s[1] + op.sh[1]) * P.s[0] + op.sh[0];
+            ops.pop_back();
+          }
         }
         if (D.level > 0) {
           for (int q = 0; q < np; ++q) {
@@ -1220,9 +1240,9 @@ amr_status amr_table_status(amr_table* t, hipStream_t stream) {
 amr_status amr_table_last_stage_ms(amr_table* t, float ms[2]) {
   if (!t || !ms) return AMR_EINVAL;
   if (!t->timed_valid) return AMR_ESTATE;
-  HIPCHECK(hipEventSynchronize(t->ev[2]));
+  HIPCHECK(hipEventSynchronize(t->ev[3]));
   HIPCHECK(hipEventElapsedTime(&ms[0], t->ev[0], t->ev[1]));
-  HIPCHECK(hipEventElapsedTime(&ms[1], t->ev[1], t->ev[2]));
+  HIPCHECK(hipEventElapsedTime(&ms[1], t->ev[2], t->ev[3]));
   return AMR_OK;
 }
 

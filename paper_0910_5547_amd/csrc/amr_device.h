@@ -40,10 +40,14 @@ struct PatchDev {
   int s[3];      // stored cells = n + 2g
   int bc[6];     // faces -x,+x,-y,+y,-z,+z
   int level;
-  int pad;
+  int dmask;     // bit f: EXTERNAL face f reads its sibling's cells directly (nbo[f])
   double dx[3];  // cell widths at this level
   double rdx[3]; // 1/dx (mixed path)
   int64_t reg[6];  // fine-face flux register of each face (element offset), -1 = none
+  // Direct sibling faces (single-level tables): the sibling has this patch's stored
+  // shape, so the element of a ghost cell of face f in the sibling's storage is the
+  // element of the same cell in this patch's ghost storage plus nbo[f].
+  int64_t nbo[6];
 };
 
 // One unit of stage-kernel work: a TX x TY column block of one patch, marched

@@ -23,7 +23,8 @@
 //     TVD-RK2 stage combine is applied in FP64 before one store per variable.
 // Stage 2 writes U^{n+1} over U^n in place: U^n is only read at the cell being
 // written.  Boundary conditions other than EXTERNAL are index maps applied at
-// load time; EXTERNAL ghosts are read from storage (filled by copy_ghosts).
+// load time; EXTERNAL ghosts are read from storage (filled by copy_ghosts) or,
+// on a direct sibling face of a single-level table, from the sibling's cells.
 //
 // The same source serves the plain form (one launch per patch, one tile per
 // workgroup) and the batched form (one persistent launch over the tile list of
@@ -109,10 +110,13 @@ void stage_kernel(StageArgs a) {
     // The REFLECT sign flip of the normal momentum is applied where loaded values
     // are used, not at the load: a flip right after the load would make the load
     // wait for its data, and the prefetches below would stop hiding latency.
+    // (a plane beyond a direct sibling face is read in the sibling: uniform branches)
     auto load_col_raw = [&](int kz, double u[NV]) -> bool {  // true: reflect in z
       bool fz = false;
       const int kk = map_index(kz, P.n[2], P.bc[4], P.bc[5], fz);
-      const int64_t e = col0 + (int64_t)kk * pstride;
+      int64_t e = col0 + (int64_t)kk * pstride;
+      if (kz < 0 && (P.dmask & 16)) e += P.nbo[4];
+      if (kz >= P.n[2] && (P.dmask & 32)) e += P.nbo[5];
 #pragma unroll
       for (int v = 0; v < NV; ++v) u[v] = a.V[e + v * P.S];
       return fz;
@@ -186,10 +190,17 @@ void stage_kernel(StageArgs a) {
         hrow[s] = w < 2 ? w - 2 : nyT + (w - 2);
       }
       bool fx = false, fy = false;
-      const int ii = map_index(T.x0 + hcol[s], P.n[0], P.bc[0], P.bc[1], fx);
-      const int jj = map_index(T.y0 + hrow[s], P.n[1], P.bc[2], P.bc[3], fy);
+      const int iraw = T.x0 + hcol[s], jraw = T.y0 + hrow[s];
+      const int ii = map_index(iraw, P.n[0], P.bc[0], P.bc[1], fx);
+      const int jj = map_index(jraw, P.n[1], P.bc[2], P.bc[3], fy);
       hflip[s] = fx ? 1 : (fy ? 2 : 0);
       hbase[s] = P.off + (int64_t)P.g[2] * pstride + (int64_t)(jj + P.g[1]) * P.s[0] + (ii + P.g[0]);
+      // a halo cell has at most one coordinate outside the patch (cross stencil)
+      const int hf = iraw < 0 ? 0 : iraw >= P.n[0] ? 1 : jraw < 0 ? 2 : jraw >= P.n[1] ? 3 : -1;
+      if (hf == 0 && (P.dmask & 1)) hbase[s] += P.nbo[0];
+      if (hf == 1 && (P.dmask & 2)) hbase[s] += P.nbo[1];
+      if (hf == 2 && (P.dmask & 4)) hbase[s] += P.nbo[2];
+      if (hf == 3 && (P.dmask & 8)) hbase[s] += P.nbo[3];
       if (h < nhx + nhy) load_halo(s, T.z0, Hn[s]);
     }
     // Per-lane work of the slope and face passes, fixed for the tile:
