@@ -78,9 +78,9 @@ def traffic_for(workload, form, cells, tile):
 
 
 def stage_tile(kernel_name):
-    """'TXxTY' from a stage kernel's template arguments (type, TX, TY, ...)."""
+    """'TXxTY' from a stage kernel's template arguments (type, variables, TX, TY, ...)."""
     import re
-    m = re.search(r"stage_kernel<\w+, (\d+), (\d+),", kernel_name)
+    m = re.search(r"stage_kernel<\w+, \d+, (\d+), (\d+),", kernel_name)
     return f"{m.group(1)}x{m.group(2)}" if m else None
 
 

@@ -183,8 +183,9 @@ int default_shape(const amr_table* t) {
     return cols / lanes;
   };
   const double u1 = lane_use(1), us = lane_use(SHAPE_SMALL);
-  const bool big_ok = t->ph.nvar != NVAR_MHD || t->ph.precision == AMR_PREC_MIXED;  // shape 5 compiled
-  if (t->ph.ndim == 3 && big_ok && lane_use(5) >= 0.9) return 5;
+  // (MHD: 32 x 8, whose two workgroups per CU beat one 512-thread workgroup of the
+  // eight-variable 32 x 16 tile)
+  if (t->ph.ndim == 3 && t->ph.nvar == NVAR && lane_use(5) >= 0.9) return 5;
   return (u1 < 0.5 && us > u1) ? SHAPE_SMALL : 1;
 }
 
