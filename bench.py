@@ -159,6 +159,12 @@ def make_workload(name):
         desc = ("ideal MHD (8 variables), 192^3 periodic as 216 patches of 32^3 (EXTERNAL faces, ng=3), "
                 "gamma=5/3, rho=25/(36 pi), p=5/(12 pi), v=(-sin 2 pi y, sin 2 pi x, 0), B=curl A with "
                 "A=GRF(k^-2, 1<=|k|<=4, seeds 50-52), beta=1.7")
+    elif name.startswith("box") and "p" in name[3:]:
+        # boxNpP: the N^3 periodic box as (N/P)^3 patches of P^3 with EXTERNAL faces
+        N, P = (int(x) for x in name[3:].split("p"))
+        ps, U = W.periodic_turbulent_box(N=N, seed=20, kmax=min(16.0, N / 4), patch=P, ng=3)
+        kw = dict(periodic=7, domain=(N, N, N))
+        desc = f"periodic box {N}^3 as {(N // P) ** 3} patches of {P}^3 (EXTERNAL faces, ng=3)"
     elif name.startswith("box"):
         N = int(name[3:])
         ps, U = W.periodic_turbulent_box(N=N, seed=20, kmax=min(16.0, N / 4))

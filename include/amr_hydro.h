@@ -95,6 +95,11 @@ enum { AMR_PREC_FP64 = 0, AMR_PREC_MIXED = 1 };
  * persistent launch per stage over a tile list of all selected patches, the
  * whole RK2 step replayed from a captured HIP graph. */
 enum { AMR_EXEC_PLAIN = 0, AMR_EXEC_BATCHED = 1 };
+/* Second reconstructed thermodynamic variable: AMR_RECON_E = the specific internal
+ * energy e, the set (rho, e, v) the paper's flux kernel stages (Sec. 5), with the face
+ * pressure p = (gamma-1) rho e; AMR_RECON_P = the pressure p, with e = p / ((gamma-1) rho)
+ * at the face (keeps p and v exactly uniform across a contact). */
+enum { AMR_RECON_E = 0, AMR_RECON_P = 1 };
 
 /* flags of amr_hydro_rk2_step */
 #define AMR_STEP_FUSE_DT 0x1u /* stage 2 also reduces the max signal speed of U^{n+1}; the
@@ -130,7 +135,7 @@ typedef struct {
   int32_t periodic;  /* bit d set: the root domain is periodic in d, so EXTERNAL ghost
                         cells beyond the domain wrap (needs domain[d])                   */
   int32_t domain[3]; /* root-level domain extent in cells per dimension (0 = not given)  */
-  int32_t reserved0; /* must be 0                                                        */
+  int32_t recon;     /* AMR_RECON_E (the paper's primitives) or AMR_RECON_P               */
   double rho_floor;  /* > 0: floor applied to recovered density (primitives only); 0 = off */
   double e_floor;    /* > 0: floor applied to recovered specific internal energy; 0 = off */
 } amr_physics;

@@ -12,7 +12,8 @@
  *  - PLM face states use half the limited slope (the printed formula omits the
  *    factor 1/2; without it a linear profile reconstructs the neighbour value).
  *  - The reconstructed primitives are (rho, e, vx, vy, vz), the set the paper's
- *    1D flux kernel stages; the face pressure is p = (gamma-1) rho e.
+ *    1D flux kernel stages; the face pressure is p = (gamma-1) rho e.  A flag
+ *    reconstructs p instead of e (then e = p / ((gamma-1) rho) at the face).
  *  - The Riemann flux is the formula the paper prints in Sec. 4 (the symmetric
  *    one-speed form: F = (F_L + F_R - lambda0 (U_R - U_L))/2 with conserved
  *    U_R - U_L); the two-speed HLL of Harten, Lax & van Leer is a flag.
@@ -80,7 +81,7 @@ int or_prim(const or_phys* ph, const double* U, double* q) {
   double vx = U[1] / rho, vy = U[2] / rho, vz = U[3] / rho;
   double kin = 0.5 * ((U[1] * U[1] + U[2] * U[2]) + U[3] * U[3]) / rho; /* rho v^2 / 2 */
   double e;
-  if (nv == 8) {
+  if (nv >= 8) {
     double mag = 0.5 * ((U[5] * U[5] + U[6] * U[6]) + U[7] * U[7]); /* B^2 / 2 */
     e = ((U[4] - kin) - mag) / rho;
   } else {
@@ -91,17 +92,30 @@ int or_prim(const or_phys* ph, const double* U, double* q) {
   if (ph->rho_floor > 0 && rho < ph->rho_floor) rho = ph->rho_floor;
   if (ph->e_floor > 0 && e < ph->e_floor) e = ph->e_floor;
   q[0] = rho;
-  q[1] = e;
+  q[1] = ph->recon == OR_RECON_P ? (ph->gamma - 1.0) * rho * e : e;
   q[2] = vx;
   q[3] = vy;
   q[4] = vz;
-  if (nv == 8) {
+  if (nv >= 8) {
     q[5] = U[5];
     q[6] = U[6];
     q[7] = U[7];
   }
+  if (nv == 9) q[8] = U[8]; /* psi */
   q[nv] = (ph->gamma - 1.0) * rho * e;
   return bad;
+}
+
+/* Specific internal energy and pressure of a primitive state, whose slot 1 holds e
+ * (p = (gamma-1) rho e) or, with the pressure reconstruction, p (e = p / ((gamma-1) rho)). */
+static void eos(const or_phys* ph, const double* q, double* e, double* p) {
+  if (ph->recon == OR_RECON_P) {
+    *p = q[1];
+    *e = q[1] / ((ph->gamma - 1.0) * q[0]);
+  } else {
+    *e = q[1];
+    *p = (ph->gamma - 1.0) * q[0] * q[1];
+  }
 }
 
 /* Signal speed along d of a primitive state: the sound speed sqrt(gamma p / rho) for
@@ -112,9 +126,10 @@ int or_prim(const or_phys* ph, const double* U, double* q) {
  * components: the same quantity, a sum of non-negative terms, with no cancellation where
  * a = b_d. */
 double or_signal_speed(const or_phys* ph, int d, const double* q) {
-  double p = (ph->gamma - 1.0) * q[0] * q[1];
+  double e, p;
+  eos(ph, q, &e, &p);
   double a2 = ph->gamma * p / q[0];
-  if (ph->nvar != 8) return sqrt(a2);
+  if (ph->nvar < 8) return sqrt(a2);
   double b2 = ((q[5] * q[5] + q[6] * q[6]) + q[7] * q[7]) / q[0];
   int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
   double bt2 = (q[5 + t1] * q[5 + t1] + q[5 + t2] * q[5 + t2]) / q[0];
@@ -125,36 +140,38 @@ double or_signal_speed(const or_phys* ph, int d, const double* q) {
 
 /* Conserved state, pressure and signal speed along d of one primitive face state. */
 static void face_state(const or_phys* ph, int d, const double* q, double* U, double* p, double* c) {
-  double rho = q[0], e = q[1], vx = q[2], vy = q[3], vz = q[4];
-  *p = (ph->gamma - 1.0) * rho * e;
+  double rho = q[0], vx = q[2], vy = q[3], vz = q[4], e;
+  eos(ph, q, &e, p);
   *c = or_signal_speed(ph, d, q);
   U[0] = rho;
   U[1] = rho * vx;
   U[2] = rho * vy;
   U[3] = rho * vz;
   U[4] = rho * (e + 0.5 * ((vx * vx + vy * vy) + vz * vz));
-  if (ph->nvar == 8) {
+  if (ph->nvar >= 8) {
     U[4] = U[4] + 0.5 * ((q[5] * q[5] + q[6] * q[6]) + q[7] * q[7]); /* + B^2/2 */
     U[5] = q[5];
     U[6] = q[6];
     U[7] = q[7];
   }
+  if (ph->nvar == 9) U[8] = q[8];
 }
 
 void or_phys_flux(const or_phys* ph, int d, const double* q, double* F) {
   /* Sec. 4 flux vectors: F^d = (rho v_d, rho v_d v + p e_d, rho (v^2/2 + h) v_d),
    * with rho (v^2/2 + h) = rho E_h + p, E_h = v^2/2 + e, since h = e + p/rho.
-   * MHD fluxes (psi = 0): momentum rho v_d v_j + (p + B^2/2) delta_jd - B_j B_d;
-   * energy rho (v^2/2 + h) v_d + B^2 v_d - B_d (B . v); induction v_d B_j - v_j B_d
-   * for j != d (the x flux as printed; the printed y and z induction entries are
-   * permuted, and the axis-permutation invariance of the system fixes them) and
-   * psi = 0 for j = d. */
+   * MHD fluxes: momentum rho v_d v_j + (p + B^2/2) delta_jd - B_j B_d; energy
+   * rho (v^2/2 + h) v_d + B^2 v_d - B_d (B . v); induction v_d B_j - v_j B_d for j != d
+   * (the x flux as printed; the printed y and z induction entries are permuted, and the
+   * axis-permutation invariance of the system fixes them) and psi for j = d (0 with 8
+   * variables); with 9 variables the psi flux is c_h^2 B_d (GLM). */
   double U[OR_NVMAX], p, c;
   face_state(ph, d, q, U, &p, &c);
-  double vd = q[2 + d];
-  double rEh = q[0] * (q[1] + 0.5 * ((q[2] * q[2] + q[3] * q[3]) + q[4] * q[4]));
+  double vd = q[2 + d], e, pe;
+  eos(ph, q, &e, &pe);
+  double rEh = q[0] * (e + 0.5 * ((q[2] * q[2] + q[3] * q[3]) + q[4] * q[4]));
   F[0] = U[1 + d];
-  if (ph->nvar != 8) {
+  if (ph->nvar < 8) {
     for (int j = 0; j < 3; ++j) F[1 + j] = U[1 + d] * q[2 + j] + (j == d ? p : 0.0);
     F[4] = (rEh + p) * vd;
     return;
@@ -166,6 +183,10 @@ void or_phys_flux(const or_phys* ph, int d, const double* q, double* F) {
     F[1 + j] = (U[1 + d] * q[2 + j] + (j == d ? p + 0.5 * B2 : 0.0)) - q[5 + j] * Bd;
   F[4] = ((rEh + p) * vd + B2 * vd) - Bd * Bv;
   for (int j = 0; j < 3; ++j) F[5 + j] = j == d ? 0.0 : vd * q[5 + j] - q[2 + j] * Bd;
+  if (ph->nvar == 9) { /* GLM: the normal field is carried by psi, psi by c_h^2 B_d */
+    F[5 + d] = q[8];
+    F[8] = ph->ch * ph->ch * Bd;
+  }
 }
 
 void or_face_flux(const or_phys* ph, int d, const double* qL, const double* qR, double* F) {
@@ -182,6 +203,10 @@ void or_face_flux(const or_phys* ph, int d, const double* qL, const double* qR, 
   double vL = qL[2 + d], vR = qR[2 + d];
   double ap = fmax(0.0, fmax(vL + cL, vR + cR));
   double am = fmax(0.0, fmax(-(vL - cL), -(vR - cR)));
+  if (nv == 9) { /* the (B_d, psi) pair travels at -c_h and +c_h */
+    ap = fmax(ap, ph->ch);
+    am = fmax(am, ph->ch);
+  }
   if (ph->flux == OR_FLUX_HLL2) {
     /* Two-speed HLL (Harten, Lax & van Leer 1983) with S_R = a+, S_L = -a-. */
     for (int k = 0; k < nv; ++k)
@@ -331,7 +356,7 @@ int or_fill_ghosts_amr(int32_t np, const int32_t* meta, const int64_t* off, cons
               cs[d] = si; cs[a] = ia; cs[b] = ib;
               for (int k = 0; k < ph->nvar; ++k) {
                 double v = V[at(&G, k, cs)];
-                if (k == 1 + d || (ph->nvar == 8 && k == 5 + d)) v = sgn * v; /* normal v and B */
+                if (k == 1 + d || (ph->nvar >= 8 && k == 5 + d)) v = sgn * v; /* normal v and B */
                 V[at(&G, k, cg)] = v;
               }
             }
@@ -488,8 +513,11 @@ double or_max_speed(int32_t np, const int32_t* meta, const int64_t* off, const o
           for (int k = 0; k < ph->nvar; ++k) Uc[k] = U[at(&G, k, c)];
           bad |= or_prim(ph, Uc, w);
           double s = 0.0;
-          for (int d = 0; d < ph->ndim; ++d)
-            s = s + (fabs(w[2 + d]) + or_signal_speed(ph, d, w)) / ldexp(ph->dx0[d], -G.level);
+          for (int d = 0; d < ph->ndim; ++d) {
+            double sd = fabs(w[2 + d]) + or_signal_speed(ph, d, w);
+            if (ph->nvar == 9) sd = fmax(sd, ph->ch); /* the GLM waves */
+            s = s + sd / ldexp(ph->dx0[d], -G.level);
+          }
           if (s > smax) smax = s;
         }
   }

@@ -15,7 +15,8 @@
  * Variables (nvar = 5) are the conserved U = (rho, rho vx, rho vy, rho vz, rho E)
  * of the paper's Sec. 4, with rho E the total energy density; for ideal MHD
  * (nvar = 8) they are (rho, rho v, rho E + B^2/2, Bx, By, Bz), the paper's MHD
- * variables with the divergence-cleaning field psi held at zero.
+ * variables with the divergence-cleaning field psi held at zero; for GLM-MHD (nvar = 9)
+ * psi follows B, with the cleaning speed ch of the physics block.
  *
  * Patch metadata is an int32 array of OR_META entries per patch:
  *   [0] level, [1..3] lo (lower active index in level space), [4..6] n,
@@ -26,17 +27,22 @@
 #include <stdint.h>
 
 #define OR_META 16
-#define OR_NVMAX 8 /* hydro: 5 variables; ideal MHD (Sec. 5 of the MHD extension): 8 */
+#define OR_NVMAX 9 /* hydro: 5 variables; ideal MHD: 8; GLM-MHD (with the cleaning field psi): 9 */
 enum { OR_BC_OUTFLOW = 0, OR_BC_PERIODIC = 1, OR_BC_REFLECT = 2, OR_BC_EXTERNAL = 3 };
 enum { OR_FLUX_PAPER = 0, OR_FLUX_HLL2 = 1 };
+/* Second reconstructed thermodynamic variable: specific internal energy e (the set the
+ * paper's flux kernel stages), or pressure p. */
+enum { OR_RECON_E = 0, OR_RECON_P = 1 };
 
 typedef struct {
   int32_t nvar, ndim;
   double gamma, theta;
   double dx0[3];
   int32_t flux, periodic;  /* periodic: bit d = root domain periodic in d (EXTERNAL ghosts wrap) */
-  int32_t domain[3], pad;  /* root-level domain extent in cells */
+  int32_t domain[3];       /* root-level domain extent in cells */
+  int32_t recon;           /* OR_RECON_E or OR_RECON_P */
   double rho_floor, e_floor;
+  double ch;               /* GLM cleaning speed c_h (nvar = 9) */
 } or_phys;
 
 #ifdef __cplusplus
@@ -47,7 +53,7 @@ extern "C" {
 double or_minmod3(double a, double b, double c);
 /* Conserved -> primitives for one cell; returns 1 if unphysical.
  * nvar 5: q = (rho, e, vx, vy, vz), q[5] = p.  nvar 8: q = (rho, e, vx, vy, vz, Bx, By, Bz),
- * q[8] = p.  (nvar + 1 entries are written.) */
+ * q[8] = p.  (nvar + 1 entries are written.)  With recon = OR_RECON_P, q[1] holds p. */
 int or_prim(const or_phys* ph, const double* U, double* q);
 /* Face flux in direction d (nvar entries) from primitive face states qL, qR (nvar entries). */
 void or_face_flux(const or_phys* ph, int d, const double* qL, const double* qR, double* F);

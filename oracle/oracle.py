@@ -19,13 +19,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
 FLUX_PAPER, FLUX_HLL2 = 0, 1
+RECON_E, RECON_P = 0, 1
 
 
 class Phys(C.Structure):
     _fields_ = [("nvar", C.c_int32), ("ndim", C.c_int32), ("gamma", C.c_double), ("theta", C.c_double),
                 ("dx0", C.c_double * 3), ("flux", C.c_int32), ("periodic", C.c_int32),
-                ("domain", C.c_int32 * 3), ("pad", C.c_int32),
-                ("rho_floor", C.c_double), ("e_floor", C.c_double)]
+                ("domain", C.c_int32 * 3), ("recon", C.c_int32),
+                ("rho_floor", C.c_double), ("e_floor", C.c_double), ("ch", C.c_double)]
 
 
 def lib():
@@ -71,10 +72,14 @@ def _dp(a):
 
 
 def phys(gamma=1.4, theta=1.0, ndim=3, dx0=(1.0, 1.0, 1.0), flux=FLUX_PAPER, rho_floor=0.0, e_floor=0.0,
-         periodic=0, domain=(0, 0, 0), nvar=5):
-    """nvar 5: hydro (Sec. 4).  nvar 8: ideal MHD with the cleaning field held at zero."""
-    assert nvar in (5, 8)
+         periodic=0, domain=(0, 0, 0), nvar=5, recon=RECON_E, ch=0.0):
+    """nvar 5: hydro (Sec. 4).  nvar 8: ideal MHD with the cleaning field held at zero.
+    nvar 9: GLM-MHD with cleaning speed ch.
+    recon: RECON_E reconstructs e (the paper's set), RECON_P reconstructs p."""
+    assert nvar in (5, 8, 9) and recon in (RECON_E, RECON_P)
     ph = Phys()
+    ph.recon = recon
+    ph.ch = ch
     ph.nvar, ph.ndim, ph.gamma, ph.theta = nvar, ndim, gamma, theta
     ph.periodic = periodic
     for d in range(3):
@@ -124,10 +129,11 @@ def signal_speed(ph, d, q):
 class Oracle:
     """Oracle bound to one patch table.  All arrays are FP64 arenas laid out as ``ps``."""
 
-    def __init__(self, ps, flux=FLUX_PAPER, rho_floor=0.0, e_floor=0.0, theta=None, periodic=0, domain=(0, 0, 0)):
+    def __init__(self, ps, flux=FLUX_PAPER, rho_floor=0.0, e_floor=0.0, theta=None, periodic=0, domain=(0, 0, 0),
+                 recon=RECON_E, ch=0.0):
         self.ps = ps
         self.ph = phys(ps.gamma, ps.theta if theta is None else theta, ps.ndim, ps.dx0, flux, rho_floor, e_floor,
-                       periodic, domain, ps.nvar)
+                       periodic, domain, ps.nvar, recon, ch)
         self.meta = np.ascontiguousarray(ps.meta(), np.int32)
         self.off = np.ascontiguousarray(ps.offset, np.int64)
         self._W = None
@@ -188,9 +194,11 @@ class AmrOracle:
     * coarse cells covered by a fine patch become the mean of their children.
     """
 
-    def __init__(self, ps, periodic=0, domain=(0, 0, 0), flux=FLUX_PAPER, rho_floor=0.0, e_floor=0.0):
+    def __init__(self, ps, periodic=0, domain=(0, 0, 0), flux=FLUX_PAPER, rho_floor=0.0, e_floor=0.0,
+                 recon=RECON_E):
         self.ps = ps
-        self.o = Oracle(ps, flux=flux, rho_floor=rho_floor, e_floor=e_floor, periodic=periodic, domain=domain)
+        self.o = Oracle(ps, flux=flux, rho_floor=rho_floor, e_floor=e_floor, periodic=periodic, domain=domain,
+                        recon=recon)
         self.periodic, self.domain = periodic, domain
         self.nlev = int(ps.level.max()) + 1
         L = lib()

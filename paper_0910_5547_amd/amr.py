@@ -23,6 +23,7 @@ AMR_BC_OUTFLOW, AMR_BC_PERIODIC, AMR_BC_REFLECT, AMR_BC_EXTERNAL = 0, 1, 2, 3
 AMR_FLUX_PAPER, AMR_FLUX_HLL2 = 0, 1
 AMR_PREC_FP64, AMR_PREC_MIXED = 0, 1
 AMR_EXEC_PLAIN, AMR_EXEC_BATCHED = 0, 1
+AMR_RECON_E, AMR_RECON_P = 0, 1
 AMR_STEP_FUSE_DT = 0x1
 AMR_STEP_TIMED = 0x2
 AMR_STEP_SUBSTEP1 = 0x4
@@ -41,7 +42,7 @@ class amr_patch_desc(C.Structure):
 class amr_physics(C.Structure):
     _fields_ = [("nvar", C.c_int32), ("ndim", C.c_int32), ("gamma", C.c_double), ("theta", C.c_double),
                 ("dx0", C.c_double * 3), ("flux", C.c_int32), ("precision", C.c_int32), ("exec", C.c_int32),
-                ("periodic", C.c_int32), ("domain", C.c_int32 * 3), ("reserved0", C.c_int32),
+                ("periodic", C.c_int32), ("domain", C.c_int32 * 3), ("recon", C.c_int32),
                 ("rho_floor", C.c_double), ("e_floor", C.c_double)]
 
 
@@ -132,7 +133,7 @@ def descriptors(ps):
 
 
 def physics(ps, precision=AMR_PREC_FP64, exec_form=AMR_EXEC_BATCHED, flux=AMR_FLUX_PAPER, theta=None,
-            periodic=0, domain=(0, 0, 0), rho_floor=0.0, e_floor=0.0):
+            periodic=0, domain=(0, 0, 0), rho_floor=0.0, e_floor=0.0, recon=AMR_RECON_E):
     ph = amr_physics()
     ph.nvar, ph.ndim = int(getattr(ps, "nvar", 5)), ps.ndim
     ph.gamma = ps.gamma
@@ -142,6 +143,7 @@ def physics(ps, precision=AMR_PREC_FP64, exec_form=AMR_EXEC_BATCHED, flux=AMR_FL
         ph.domain[d] = int(domain[d])
     ph.flux, ph.precision, ph.exec, ph.periodic = flux, precision, exec_form, periodic
     ph.rho_floor, ph.e_floor = rho_floor, e_floor
+    ph.recon = recon
     return ph
 
 
@@ -225,11 +227,11 @@ class Table:
     """Owns one amr_table for a PatchSet; U arenas are float64 device tensors."""
 
     def __init__(self, ps, precision=AMR_PREC_FP64, exec_form=AMR_EXEC_BATCHED, flux=AMR_FLUX_PAPER, theta=None,
-                 periodic=0, domain=(0, 0, 0), rho_floor=0.0, e_floor=0.0, device="cuda"):
+                 periodic=0, domain=(0, 0, 0), rho_floor=0.0, e_floor=0.0, recon=AMR_RECON_E, device="cuda"):
         self.ps = ps
         self.device = torch.device(device)
         self.descs = descriptors(ps)
-        self.phys = physics(ps, precision, exec_form, flux, theta, periodic, domain, rho_floor, e_floor)
+        self.phys = physics(ps, precision, exec_form, flux, theta, periodic, domain, rho_floor, e_floor, recon)
         self.h = amr_patch_table_create(self.descs, self.phys)
         self.arena = amr_table_arena_elems(self.h)
         self.dt = torch.zeros(1, dtype=torch.float64, device=self.device)

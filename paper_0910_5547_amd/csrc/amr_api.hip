@@ -275,6 +275,7 @@ Consts consts_of(const amr_table* t) {
   c.e_floor = t->ph.e_floor;
   c.ndim = t->ph.ndim;
   c.flux = t->ph.flux;
+  c.recon = t->ph.recon;
   return c;
 }
 
@@ -446,7 +447,8 @@ amr_status validate(const amr_patch_desc* P, int32_t np, const amr_physics* ph) 
   if (ph->flux != AMR_FLUX_PAPER && ph->flux != AMR_FLUX_HLL2) return AMR_EINVAL;
   if (ph->precision != AMR_PREC_FP64 && ph->precision != AMR_PREC_MIXED) return AMR_EINVAL;
   if (ph->exec != AMR_EXEC_PLAIN && ph->exec != AMR_EXEC_BATCHED) return AMR_EINVAL;
-  if (ph->reserved0 != 0 || ph->periodic < 0 || ph->periodic > 7) return AMR_EINVAL;
+  if ((ph->recon != AMR_RECON_E && ph->recon != AMR_RECON_P) || ph->periodic < 0 || ph->periodic > 7)
+    return AMR_EINVAL;
   for (int d = 0; d < 3; ++d)
     if (((ph->periodic >> d) & 1) && ph->domain[d] < 1) return AMR_EINVAL;
   if (ph->rho_floor < 0 || ph->e_floor < 0) return AMR_EINVAL;

@@ -30,6 +30,7 @@ constexpr int MAX_LEVELS = 32;
 
 enum { BC_OUTFLOW = 0, BC_PERIODIC = 1, BC_REFLECT = 2, BC_EXTERNAL = 3 };
 enum { FLUX_PAPER = 0, FLUX_HLL2 = 1 };
+enum { RECON_E = 0, RECON_P = 1 };
 
 // One patch as the kernels see it (built on the host from amr_patch_desc).
 struct PatchDev {
@@ -144,6 +145,7 @@ __device__ __forceinline__ void box_cell(const int sz[3], int c, int b[3]) {
 struct Consts {
   double gamma, gm1, gg1, theta, rho_floor, e_floor;  // gg1 = gamma (gamma - 1)
   int ndim, flux;
+  int recon, pad;  // recon: RECON_E (slot 1 of the primitives holds e) or RECON_P (it holds p)
 };
 
 // Reconstruction-type traits: the mixed path is evaluated for speed.
@@ -258,7 +260,7 @@ __device__ __forceinline__ bool cons2prim(const double u[NV], const Consts& c, R
   if (c.rho_floor > 0 && r < c.rho_floor) r = c.rho_floor;
   if (c.e_floor > 0 && e < c.e_floor) e = c.e_floor;
   q[0] = (RT)r;
-  q[1] = (RT)e;
+  q[1] = c.recon == RECON_P ? (RT)(c.gm1 * r * e) : (RT)e;
   q[2] = (RT)vx;
   q[3] = (RT)vy;
   q[4] = (RT)vz;
@@ -304,7 +306,7 @@ __device__ __forceinline__ double cell_speed(const double u[NV], const Consts& c
   if constexpr (FAST) {
     float q[NV];
     bad |= cons2prim<float, NV>(u, c, q) ? 1 : 0;
-    const float a2 = (float)c.gg1 * q[1];
+    const float a2 = c.recon == RECON_P ? (float)c.gamma * q[1] * __builtin_amdgcn_rcpf(q[0]) : (float)c.gg1 * q[1];
     double cx, cy, cz;
     if constexpr (MHD) {
       cx = (double)fast_speed<float, 0>(q, a2);
@@ -320,7 +322,7 @@ __device__ __forceinline__ double cell_speed(const double u[NV], const Consts& c
   } else {
     double q[NV];
     bad |= cons2prim<double, NV>(u, c, q) ? 1 : 0;
-    const double p = c.gm1 * q[0] * q[1];
+    const double p = c.recon == RECON_P ? q[1] : c.gm1 * q[0] * q[1];
     const double a2 = c.gamma * p / q[0];
     double cx, cy, cz;
     if constexpr (MHD) {
@@ -399,13 +401,29 @@ __device__ __forceinline__ RT plm_slope_t(RT qm, RT q0, RT qp, RT theta) {
 template <typename RT>
 struct FaceConsts {
   RT gamma, gm1, gg1;
+  int recon;
 };
+
+// Specific internal energy e and pressure p of a face state whose slot 1 holds e
+// (p = (gamma-1) rho e) or, with the pressure reconstruction, p (e = p / ((gamma-1) rho)).
+template <typename RT>
+__device__ __forceinline__ void face_eos(const RT* q, const FaceConsts<RT>& k, RT& e, RT& p) {
+  if (k.recon == RECON_P) {
+    p = q[1];
+    if constexpr (Fast<RT>::value) e = q[1] * __builtin_amdgcn_rcpf(k.gm1 * q[0]);
+    else e = q[1] / (k.gm1 * q[0]);
+  } else {
+    e = q[1];
+    p = k.gm1 * q[0] * q[1];
+  }
+}
 
 // Conserved state U(q), pressure and sound speed of one face state.
 template <typename RT>
 __device__ __forceinline__ void face_state(const RT q[NVAR], const FaceConsts<RT>& k, RT U[NVAR], RT& p, RT& c) {
-  const RT rho = q[0], e = q[1], vx = q[2], vy = q[3], vz = q[4];
-  p = k.gm1 * rho * e;
+  const RT rho = q[0], vx = q[2], vy = q[3], vz = q[4];
+  RT e;
+  face_eos<RT>(q, k, e, p);
   U[0] = rho;
   U[1] = rho * vx;
   U[2] = rho * vy;
@@ -429,8 +447,9 @@ __device__ __forceinline__ void face_state(const RT q[NVAR], const FaceConsts<RT
 template <typename RT, int D>
 __device__ __forceinline__ void mhd_face(const RT q[NVAR_MHD], const FaceConsts<RT>& k, RT U[NVAR_MHD],
                                          RT F[NVAR_MHD], RT& c) {
-  const RT rho = q[0], e = q[1], vx = q[2], vy = q[3], vz = q[4], Bx = q[5], By = q[6], Bz = q[7];
-  const RT p = k.gm1 * rho * e;
+  const RT rho = q[0], vx = q[2], vy = q[3], vz = q[4], Bx = q[5], By = q[6], Bz = q[7];
+  RT e, p;
+  face_eos<RT>(q, k, e, p);
   const RT vd = q[2 + D], Bd = q[5 + D];
   U[0] = rho;
   U[1] = rho * vx;

@@ -37,7 +37,9 @@ namespace amr {
 // Occupancy target: three 256-lane workgroups per CU for the FP32-reconstruction
 // instantiations (<= 168 VGPRs), two for FP64 (LDS-bound at two per CU anyway).
 // REC: record fine-face fluxes into the refluxing registers (patches of levels > 0).
-// TH1: the limiter parameter is 1 (the two-argument minmod, see plm_slope_t).
+// TH1: the default scheme - limiter parameter 1 (the two-argument minmod, see
+// plm_slope_t) and e reconstructed - known at compile time; the other instantiation
+// takes theta and the reconstructed variable at run time.
 // A tile of TX x TY = 256 columns is the whole workgroup's; a tile of 64 columns
 // (small patches) is one wavefront's, each of the four wavefronts walking its own
 // tiles and synchronising only with itself.
@@ -69,8 +71,9 @@ void stage_kernel(StageArgs a) {
   constexpr bool RING = FAST && WPB == 1 && NV == NVAR;
   __shared__ double sV[RING ? 2 : 1][NV][RING ? NTH : 1];
 
-  const Consts C = a.c;
-  const FaceConsts<RT> K{(RT)C.gamma, (RT)C.gm1, (RT)C.gg1};
+  Consts C = a.c;
+  if constexpr (TH1) C.recon = RECON_E;  // (folds the reconstruction branches away)
+  const FaceConsts<RT> K{(RT)C.gamma, (RT)C.gm1, (RT)C.gg1, C.recon};
   const RT theta = (RT)C.theta;
   const int kind = C.flux;
   const int sub = WPB == 1 ? 0 : (int)threadIdx.x / TL;  // this lane's tile slot in the workgroup
@@ -559,7 +562,7 @@ __global__ void fill_i32(int* p, int n, int v) {
 // (mhd_shape_ok), so a launch of another combination returns hipErrorInvalidValue.
 template <typename RT, int NV, int TX, int TY, int NTH, int STAGE>
 static hipError_t launch_stage_t(dim3 grid, hipStream_t s, const StageArgs& a) {
-  const bool th1 = a.c.theta == 1.0;
+  const bool th1 = a.c.theta == 1.0 && a.c.recon == RECON_E;
   if (a.reg) {
     if constexpr (NV == NVAR) {
       if (th1) hipLaunchKernelGGL((stage_kernel<RT, NV, TX, TY, NTH, STAGE, true, true>), grid, dim3(NTH), 0, s, a);

@@ -41,6 +41,7 @@ import numpy as np
 BC_OUTFLOW, BC_PERIODIC, BC_REFLECT, BC_EXTERNAL = 0, 1, 2, 3
 NVAR = 5       # hydro: (rho, rho v, rho E)
 NVAR_MHD = 8   # ideal MHD: (rho, rho v, rho E + B^2/2, B), the divergence-cleaning field held at 0
+NVAR_GLM = 9   # GLM-MHD: (rho, rho v, rho E + B^2/2, B, psi)
 
 
 @dataclasses.dataclass
@@ -137,6 +138,12 @@ def conserved_mhd(rho, vx, vy, vz, p, Bx, By, Bz, gamma):
     return np.stack(np.broadcast_arrays(rho, rho * vx, rho * vy, rho * vz, E, Bx, By, Bz)).astype(np.float64)
 
 
+def conserved_glm(rho, vx, vy, vz, p, Bx, By, Bz, psi, gamma):
+    """GLM-MHD conserved variables: the ideal-MHD set followed by the cleaning field psi."""
+    U8 = conserved_mhd(rho, vx, vy, vz, p, Bx, By, Bz, gamma)
+    return np.concatenate([U8, np.broadcast_to(np.asarray(psi, np.float64), U8.shape[1:])[None]])
+
+
 def new_arena(ps: PatchSet, fill=np.nan) -> np.ndarray:
     """An arena whose ghost cells hold ``fill`` (NaN: any read of an unfilled ghost shows)."""
     return np.full(ps.arena, fill, np.float64)
@@ -219,6 +226,25 @@ def alfven_wave(N, ng=2, gamma=5.0 / 3.0, theta=1.0, amp=0.1, p=0.1, ndim=1, axi
     v[b1], v[b2] = -B[b1], -B[b2]
     U = new_arena(ps)
     ps.active(U, 0)[...] = conserved_mhd(np.ones(shape), v[0], v[1], v[2], p, B[0], B[1], B[2], gamma)
+    return ps, U
+
+
+def glm_wave(N, ch=2.0, eps=1e-4, ng=2, gamma=5.0 / 3.0, theta=1.0, ndim=1, axis=0):
+    """GLM cleaning wave on the periodic unit box: rho = 1, p = 1, v = 0, the field along ``axis``
+    B_a = eps sin(2 pi x_a), psi = 0, no other field.  To first order in eps the pair (B_a, psi)
+    obeys the wave equation with speed ch: B_a = eps sin(2 pi x) cos(2 pi ch t),
+    psi = -ch eps cos(2 pi x) sin(2 pi ch t) (a standing wave)."""
+    n = [N if d < ndim else 1 for d in range(3)]
+    dx0 = tuple(1.0 / N if d < ndim else 1.0 for d in range(3))
+    ps = make_patchset(ndim, [n], ng, [BC_PERIODIC] * 6, gamma=gamma, theta=theta, dx0=dx0, nvar=NVAR_GLM)
+    shape = (n[2], n[1], n[0])
+    xc = (np.arange(N) + 0.5) / N
+    sh = [1, 1, 1]
+    sh[2 - axis] = N
+    B = [np.zeros(shape) for _ in range(3)]
+    B[axis] = np.broadcast_to(eps * np.sin(2 * np.pi * xc.reshape(sh)), shape)
+    U = new_arena(ps)
+    ps.active(U, 0)[...] = conserved_glm(np.ones(shape), 0.0, 0.0, 0.0, 1.0, B[0], B[1], B[2], 0.0, gamma)
     return ps, U
 
 
@@ -384,6 +410,9 @@ def random_state(ps: PatchSet, seed, U=None, amp=0.3, vamp=0.5, shocks=0.0, bamp
         if ps.nvar == NVAR_MHD:
             B = [bamp * S() for _ in range(3)]
             ps.active(U, p)[...] = conserved_mhd(rho, vel[0], vel[1], vel[2], pr, B[0], B[1], B[2], g)
+        elif ps.nvar == NVAR_GLM:
+            B = [bamp * S() for _ in range(3)]
+            ps.active(U, p)[...] = conserved_glm(rho, vel[0], vel[1], vel[2], pr, B[0], B[1], B[2], bamp * S(), g)
         else:
             ps.active(U, p)[...] = conserved(rho, vel[0], vel[1], vel[2], pr, g)
     return U
