@@ -12,6 +12,7 @@ Workloads (seeded, synthetic; see paper_0910_5547_amd.workloads):
   patches4000  4000 independent patches, sizes 8..32 per dimension, 3 ghost
                layers, smooth states with random planar shocks in 20%
   sedov        deep-AMR octant Sedov hierarchy (7 levels, subcycled root steps)
+  glm192       the mhd192 box with the GLM cleaning field (9 variables, c_h = 3)
   mhd192       ideal MHD (8 variables), 192^3 periodic box as 216 patches of 32^3
                with EXTERNAL faces: Orszag-Tang-like vortex velocity, B = curl of
                a seeded GRF vector potential (divergence-free), plasma beta 1.7
@@ -159,6 +160,17 @@ def make_workload(name):
         desc = ("ideal MHD (8 variables), 192^3 periodic as 216 patches of 32^3 (EXTERNAL faces, ng=3), "
                 "gamma=5/3, rho=25/(36 pi), p=5/(12 pi), v=(-sin 2 pi y, sin 2 pi x, 0), B=curl A with "
                 "A=GRF(k^-2, 1<=|k|<=4, seeds 50-52), beta=1.7")
+    elif name == "glm192":
+        ps8, U8 = W.mhd_vortex_box(N=192, patch=32, seed=50)
+        ps = W.make_patchset(3, ps8.n, ps8.ng, ps8.bc, lo=ps8.lo, gamma=ps8.gamma, dx0=ps8.dx0, nvar=W.NVAR_GLM)
+        U = W.new_arena(ps)
+        for p in range(ps.npatch):
+            ps.active(U, p)[:8] = ps8.active(U8, p)
+            ps.active(U, p)[8] = 0.0
+        del U8
+        kw = dict(periodic=7, domain=(192, 192, 192), ch=3.0)
+        desc = ("GLM-MHD (9 variables, cleaning speed c_h = 3), the mhd192 vortex box with psi = 0: 192^3 "
+                "periodic as 216 patches of 32^3 (EXTERNAL faces, ng=3)")
     elif name.startswith("box") and "p" in name[3:]:
         # boxNpP: the N^3 periodic box as (N/P)^3 patches of P^3 with EXTERNAL faces
         N, P = (int(x) for x in name[3:].split("p"))
@@ -259,7 +271,7 @@ def cpu_baseline(ps_full, U_full, kw, budget_s=12.0):
     from oracle import oracle as O
     from paper_0910_5547_amd import workloads as W
     nv = ps_full.nvar
-    kw = {k: v for k, v in kw.items() if k not in ("periodic", "domain")}
+    kw = {k: v for k, v in kw.items() if k not in ("periodic", "domain")}  # the sample has outflow faces
     if ps_full.npatch == 1:
         B = 64
         a = ps_full.active(U_full, 0)[:, :B, :B, :B]
@@ -310,7 +322,7 @@ def main():
     args = ap.parse_args()
     if args.summarize_pmc:
         from paper_0910_5547_amd import workloads as W
-        cells, nvar = {"box256": (256 ** 3, 5), "mhd192": (192 ** 3, 8)}.get(args.workload, (None, 5))
+        cells, nvar = {"box256": (256 ** 3, 5), "mhd192": (192 ** 3, 8), "glm192": (192 ** 3, 9)}.get(args.workload, (None, 5))
         if cells is None:
             cells = make_workload(args.workload)[0].active_cells()
         form = args.forms.split(",")[-1]

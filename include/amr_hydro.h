@@ -18,8 +18,11 @@
  * induction entries v_d B_j - v_j B_d (its x flux; the printed y and z induction
  * entries have their components permuted), the signal speed in the Riemann
  * flux and in the CFL rule is the fast magnetosonic speed along the face
- * normal, and REFLECT also negates the normal field.  MHD tables are single
- * level (every patch at level 0).
+ * normal, and REFLECT also negates the normal field.  With nvar = 9 the
+ * cleaning field psi follows B (the paper's GLM system): the B_d entry of the
+ * d-flux is psi, the psi entry c_h^2 B_d, and the pair's wave speeds -c_h and
+ * +c_h join the Riemann flux's a+ and a- and the CFL rule (no damping source:
+ * the paper writes none).  MHD tables are single level (every patch at level 0).
  *
  * Conventions shared by every entry point
  *   - Every function returns an amr_status: AMR_OK (0) or a negative code.
@@ -124,7 +127,8 @@ typedef struct {
 } amr_patch_desc;
 
 typedef struct {
-  int32_t nvar;      /* conserved variables: 5 (hydro, Sec. 4) or 8 (ideal MHD, psi = 0)  */
+  int32_t nvar;      /* conserved variables: 5 (hydro, Sec. 4), 8 (ideal MHD, psi = 0) or
+                        9 (GLM-MHD: psi follows B)                                        */
   int32_t ndim;      /* 1, 2 or 3 active dimensions                                      */
   double gamma;      /* adiabatic index of p = (gamma-1) rho e, > 1                      */
   double theta;      /* PLM limiter parameter, 0 <= theta <= 2 (Sec. 4)                  */
@@ -138,6 +142,7 @@ typedef struct {
   int32_t recon;     /* AMR_RECON_E (the paper's primitives) or AMR_RECON_P               */
   double rho_floor;  /* > 0: floor applied to recovered density (primitives only); 0 = off */
   double e_floor;    /* > 0: floor applied to recovered specific internal energy; 0 = off */
+  double ch;         /* nvar 9: GLM cleaning speed c_h >= 0 (ignored otherwise)           */
 } amr_physics;
 
 typedef struct amr_table amr_table; /* opaque, library-owned */
@@ -145,8 +150,8 @@ typedef struct amr_table amr_table; /* opaque, library-owned */
 /* Create a table for `npatch` patches (Sec. 3 hierarchy as a flat list).
  * Copies the descriptors, validates them (AMR_EINVAL on: npatch < 1, n < 1,
  * ng out of range in an active dimension, n > 1 in an absent dimension,
- * overlapping storage, unknown bc/flux/precision/exec, nvar not 5 or 8, a patch
- * of level > 0 with nvar 8,
+ * overlapping storage, unknown bc/flux/precision/exec/recon, nvar not 5, 8 or 9,
+ * a patch of level > 0 with nvar 8 or 9, ch negative or not finite,
  * gamma <= 1, theta outside [0,2], dx0 <= 0, a PERIODIC face whose opposite
  * face is not PERIODIC), allocates the device-side copy, the stage scratch
  * arena U^(1) (same size as the U arena) and the reduction/flag words, builds
@@ -225,7 +230,7 @@ amr_status amr_table_status(amr_table* table, hipStream_t stream);
  *   zslab (>= 1; 0 = automatic: the slab length that fills whole rounds of the
  *   persistent launch); invalidates a captured graph.  AMR_EINVAL for a shape
  *   the table cannot run: shape 0 is the 1D shape and the only one for ndim 1;
- *   MHD tables (nvar 8) have shapes 0, 1 and 4, and 5 and 6 in mixed precision
+ *   MHD tables (nvar 8 and 9) have shapes 0, 1 and 4, and 5 and 6 in mixed precision
  *   (in FP64 the larger tiles' LDS does not hold eight variables).
  * amr_table_get_tiling: current id and (resolved) zslab.
  * amr_table_tiling_shape: the (TX, TY) cells per tile of shape `id`. */

@@ -43,7 +43,7 @@ class amr_physics(C.Structure):
     _fields_ = [("nvar", C.c_int32), ("ndim", C.c_int32), ("gamma", C.c_double), ("theta", C.c_double),
                 ("dx0", C.c_double * 3), ("flux", C.c_int32), ("precision", C.c_int32), ("exec", C.c_int32),
                 ("periodic", C.c_int32), ("domain", C.c_int32 * 3), ("recon", C.c_int32),
-                ("rho_floor", C.c_double), ("e_floor", C.c_double)]
+                ("rho_floor", C.c_double), ("e_floor", C.c_double), ("ch", C.c_double)]
 
 
 class AmrError(RuntimeError):
@@ -133,7 +133,7 @@ def descriptors(ps):
 
 
 def physics(ps, precision=AMR_PREC_FP64, exec_form=AMR_EXEC_BATCHED, flux=AMR_FLUX_PAPER, theta=None,
-            periodic=0, domain=(0, 0, 0), rho_floor=0.0, e_floor=0.0, recon=AMR_RECON_E):
+            periodic=0, domain=(0, 0, 0), rho_floor=0.0, e_floor=0.0, recon=AMR_RECON_E, ch=0.0):
     ph = amr_physics()
     ph.nvar, ph.ndim = int(getattr(ps, "nvar", 5)), ps.ndim
     ph.gamma = ps.gamma
@@ -144,6 +144,7 @@ def physics(ps, precision=AMR_PREC_FP64, exec_form=AMR_EXEC_BATCHED, flux=AMR_FL
     ph.flux, ph.precision, ph.exec, ph.periodic = flux, precision, exec_form, periodic
     ph.rho_floor, ph.e_floor = rho_floor, e_floor
     ph.recon = recon
+    ph.ch = ch
     return ph
 
 
@@ -227,11 +228,12 @@ class Table:
     """Owns one amr_table for a PatchSet; U arenas are float64 device tensors."""
 
     def __init__(self, ps, precision=AMR_PREC_FP64, exec_form=AMR_EXEC_BATCHED, flux=AMR_FLUX_PAPER, theta=None,
-                 periodic=0, domain=(0, 0, 0), rho_floor=0.0, e_floor=0.0, recon=AMR_RECON_E, device="cuda"):
+                 periodic=0, domain=(0, 0, 0), rho_floor=0.0, e_floor=0.0, recon=AMR_RECON_E, ch=0.0,
+                 device="cuda"):
         self.ps = ps
         self.device = torch.device(device)
         self.descs = descriptors(ps)
-        self.phys = physics(ps, precision, exec_form, flux, theta, periodic, domain, rho_floor, e_floor, recon)
+        self.phys = physics(ps, precision, exec_form, flux, theta, periodic, domain, rho_floor, e_floor, recon, ch)
         self.h = amr_patch_table_create(self.descs, self.phys)
         self.arena = amr_table_arena_elems(self.h)
         self.dt = torch.zeros(1, dtype=torch.float64, device=self.device)

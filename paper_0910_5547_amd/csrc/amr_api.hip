@@ -70,7 +70,7 @@ struct amr_table {
   // fused dt bookkeeping
   const double* fused_U = nullptr;
   int fused_level = -2;
-  int occ[2][2][NSHAPES][2][2] = {};  // resident stage workgroups per CU: [mhd][mixed][shape][stage][recording]
+  int occ[3][2][NSHAPES][2][2] = {};  // resident stage workgroups per CU: [5/8/9 variables][mixed][shape][stage][recording]
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // AMR_STEP_TIMED: around each stage kernel
   bool timed_valid = false;
   // ---- hierarchy (levels > 0 present): coarse/fine coupling plans, see build_hierarchy
@@ -121,7 +121,7 @@ bool shape_valid(int ndim, int shape) {
 // variable count and precision.
 bool shape_ok(const amr_table* t, int shape) {
   if (!shape_valid(t->ph.ndim, shape)) return false;
-  return t->ph.nvar != NVAR_MHD || mhd_shape_ok(t->ph.precision == AMR_PREC_MIXED, shape);
+  return t->ph.nvar == NVAR || mhd_shape_ok(t->ph.precision == AMR_PREC_MIXED, shape);
 }
 
 int occupancy_grid(amr_table* t, int stage, int ntiles, bool rec);
@@ -276,6 +276,8 @@ Consts consts_of(const amr_table* t) {
   c.ndim = t->ph.ndim;
   c.flux = t->ph.flux;
   c.recon = t->ph.recon;
+  c.ch = t->ph.nvar == NVAR_GLM ? t->ph.ch : 0.0;
+  c.ch2 = c.ch * c.ch;
   return c;
 }
 
@@ -285,8 +287,8 @@ Consts consts_of(const amr_table* t) {
 int occupancy_grid(amr_table* t, int stage, int ntiles, bool rec) {
   if (ntiles < 1) ntiles = 1;
   const int mixed = t->ph.precision == AMR_PREC_MIXED;
-  const int mhd = t->ph.nvar == NVAR_MHD;
-  int& per_cu = t->occ[mhd][mixed][t->shape][stage - 1][rec ? 1 : 0];
+  const int vk = t->ph.nvar == NVAR_MHD ? 1 : t->ph.nvar == NVAR_GLM ? 2 : 0;
+  int& per_cu = t->occ[vk][mixed][t->shape][stage - 1][rec ? 1 : 0];
   if (per_cu <= 0) {
     const void* k = stage_kernel_ptr(t->ph.nvar, mixed, t->shape, stage, rec);
     if (!k) {  // not compiled (MHD recording kernels): never launched, nothing to size
@@ -440,7 +442,9 @@ void drop_graph(amr_table* t) {
 
 amr_status validate(const amr_patch_desc* P, int32_t np, const amr_physics* ph) {
   if (!P || !ph || np < 1) return AMR_EINVAL;
-  if ((ph->nvar != NVAR && ph->nvar != NVAR_MHD) || ph->ndim < 1 || ph->ndim > 3) return AMR_EINVAL;
+  if ((ph->nvar != NVAR && ph->nvar != NVAR_MHD && ph->nvar != NVAR_GLM) || ph->ndim < 1 || ph->ndim > 3)
+    return AMR_EINVAL;
+  if (!(ph->ch >= 0.0 && ph->ch < 1e300)) return AMR_EINVAL;
   if (!(ph->gamma > 1.0) || !(ph->theta >= 0.0 && ph->theta <= 2.0)) return AMR_EINVAL;
   for (int d = 0; d < 3; ++d)
     if (!(ph->dx0[d] > 0)) return AMR_EINVAL;
@@ -456,7 +460,7 @@ amr_status validate(const amr_patch_desc* P, int32_t np, const amr_physics* ph) 
   for (int p = 0; p < np; ++p) {
     const amr_patch_desc& D = P[p];
     if (D.level < 0 || D.level >= MAX_LEVELS || D.offset < 0 || D.reserved[0] || D.reserved[1]) return AMR_EINVAL;
-    if (ph->nvar == NVAR_MHD && D.level != 0) return AMR_EINVAL;  // MHD: single-level tables
+    if (ph->nvar != NVAR && D.level != 0) return AMR_EINVAL;  // MHD: single-level tables
     if (D.ng < 2 || D.ng > 8) return AMR_EINVAL;
     int64_t S = 1;
     for (int d = 0; d < 3; ++d) {

@@ -2,7 +2,7 @@
 // of the MOL hydro update (Wang, Abel & Kaehler, Sec. 4), for gfx950, and of its
 // ideal-MHD variant (the paper's MHD section with the cleaning field psi held at
 // zero): NV = 5 conserved variables (rho, rho v, rho E) or NV = 8
-// (rho, rho v, rho E + B^2/2, B).
+// (rho, rho v, rho E + B^2/2, B), and of the GLM system with psi (NV = 9).
 //
 // RT is the reconstruction type: double for the FP64 path, float for the mixed
 // path (FP32 reconstruction and face flux).  The conserved->primitive
@@ -25,6 +25,7 @@ namespace amr {
 
 constexpr int NVAR = 5;      // hydro
 constexpr int NVAR_MHD = 8;  // ideal MHD
+constexpr int NVAR_GLM = 9;  // GLM-MHD: the ideal-MHD set and the cleaning field psi
 constexpr int NT = 256;  // threads per workgroup of the stage kernel (4 wave64s)
 constexpr int MAX_LEVELS = 32;
 
@@ -144,6 +145,7 @@ __device__ __forceinline__ void box_cell(const int sz[3], int c, int b[3]) {
 
 struct Consts {
   double gamma, gm1, gg1, theta, rho_floor, e_floor;  // gg1 = gamma (gamma - 1)
+  double ch, ch2;  // GLM cleaning speed c_h and c_h^2 (NV = 9)
   int ndim, flux;
   int recon, pad;  // recon: RECON_E (slot 1 of the primitives holds e) or RECON_P (it holds p)
 };
@@ -193,7 +195,7 @@ __device__ __forceinline__ int map_index(int i, int n, int bclo, int bchi, bool&
 template <int NV>
 __device__ __forceinline__ void reflect_flip(double* u, int d) {
   u[1 + d] = -u[1 + d];
-  if constexpr (NV == NVAR_MHD) u[5 + d] = -u[5 + d];
+  if constexpr (NV >= NVAR_MHD) u[5 + d] = -u[5 + d];
 }
 
 // Conserved state of cell (i,j,k) (active-relative; at most one coordinate may be
@@ -220,7 +222,7 @@ __device__ __forceinline__ void load_cons(const double* __restrict__ A, const Pa
 // so they are never done in FP32).  Returns true for an unphysical state.
 template <typename RT, int NV = NVAR>
 __device__ __forceinline__ bool cons2prim(const double u[NV], const Consts& c, RT q[NV]) {
-  constexpr bool MHD = NV == NVAR_MHD;
+  constexpr bool MHD = NV >= NVAR_MHD;
   const double rho = u[0];
   double vx, vy, vz, e;
   if constexpr (Fast<RT>::value) {
@@ -269,6 +271,7 @@ __device__ __forceinline__ bool cons2prim(const double u[NV], const Consts& c, R
     q[6] = (RT)u[6];
     q[7] = (RT)u[7];
   }
+  if constexpr (NV == NVAR_GLM) q[8] = (RT)u[8];
   return bad;
 }
 
@@ -302,7 +305,7 @@ __device__ __forceinline__ RT fast_speed(const RT* q, RT a2) {
 // and by the fused reduction in stage 2).
 template <bool FAST, int NV = NVAR>
 __device__ __forceinline__ double cell_speed(const double u[NV], const Consts& c, const PatchDev& P, int& bad) {
-  constexpr bool MHD = NV == NVAR_MHD;
+  constexpr bool MHD = NV >= NVAR_MHD;
   if constexpr (FAST) {
     float q[NV];
     bad |= cons2prim<float, NV>(u, c, q) ? 1 : 0;
@@ -315,9 +318,15 @@ __device__ __forceinline__ double cell_speed(const double u[NV], const Consts& c
     } else {
       cx = cy = cz = (double)__builtin_amdgcn_sqrtf(a2);
     }
-    double s = (fabs((double)q[2]) + cx) * P.rdx[0];
-    if (c.ndim > 1) s = fma(fabs((double)q[3]) + cy, P.rdx[1], s);
-    if (c.ndim > 2) s = fma(fabs((double)q[4]) + cz, P.rdx[2], s);
+    double sx = fabs((double)q[2]) + cx, sy = fabs((double)q[3]) + cy, sz = fabs((double)q[4]) + cz;
+    if constexpr (NV == NVAR_GLM) {  // the cleaning waves travel at c_h
+      sx = fmax(sx, c.ch);
+      sy = fmax(sy, c.ch);
+      sz = fmax(sz, c.ch);
+    }
+    double s = sx * P.rdx[0];
+    if (c.ndim > 1) s = fma(sy, P.rdx[1], s);
+    if (c.ndim > 2) s = fma(sz, P.rdx[2], s);
     return s;
   } else {
     double q[NV];
@@ -332,10 +341,16 @@ __device__ __forceinline__ double cell_speed(const double u[NV], const Consts& c
     } else {
       cx = cy = cz = sqrt(a2);
     }
+    double sx = fabs(q[2]) + cx, sy = fabs(q[3]) + cy, sz = fabs(q[4]) + cz;
+    if constexpr (NV == NVAR_GLM) {
+      sx = fmax(sx, c.ch);
+      sy = fmax(sy, c.ch);
+      sz = fmax(sz, c.ch);
+    }
     double s = 0.0;
-    s = s + (fabs(q[2]) + cx) / P.dx[0];
-    if (c.ndim > 1) s = s + (fabs(q[3]) + cy) / P.dx[1];
-    if (c.ndim > 2) s = s + (fabs(q[4]) + cz) / P.dx[2];
+    s = s + sx / P.dx[0];
+    if (c.ndim > 1) s = s + sy / P.dx[1];
+    if (c.ndim > 2) s = s + sz / P.dx[2];
     return s;
   }
 }
@@ -402,6 +417,7 @@ template <typename RT>
 struct FaceConsts {
   RT gamma, gm1, gg1;
   int recon;
+  RT ch, ch2;  // GLM cleaning speed and its square
 };
 
 // Specific internal energy e and pressure p of a face state whose slot 1 holds e
@@ -443,10 +459,10 @@ __device__ __forceinline__ void face_state(const RT q[NVAR], const FaceConsts<RT
 // magnetosonic speed c along D.  The FP64 path evaluates each entry in the order
 //   momentum  (rho v_D v_j + [j = D] (p + B^2/2)) - B_j B_D
 //   energy    ((rho E_h + p) v_D + B^2 v_D) - B_D (B . v)
-// with rho E_h = rho (e + v^2/2) the gas part of the energy variable.
-template <typename RT, int D>
-__device__ __forceinline__ void mhd_face(const RT q[NVAR_MHD], const FaceConsts<RT>& k, RT U[NVAR_MHD],
-                                         RT F[NVAR_MHD], RT& c) {
+// with rho E_h = rho (e + v^2/2) the gas part of the energy variable.  GLM (NV = 9):
+// the B_D entry is psi and the psi entry c_h^2 B_D.
+template <typename RT, int D, int NV>
+__device__ __forceinline__ void mhd_face(const RT q[NV], const FaceConsts<RT>& k, RT U[NV], RT F[NV], RT& c) {
   const RT rho = q[0], vx = q[2], vy = q[3], vz = q[4], Bx = q[5], By = q[6], Bz = q[7];
   RT e, p;
   face_eos<RT>(q, k, e, p);
@@ -460,6 +476,11 @@ __device__ __forceinline__ void mhd_face(const RT q[NVAR_MHD], const FaceConsts<
   U[7] = Bz;
   F[0] = U[1 + D];
   F[5 + D] = RT(0);
+  if constexpr (NV == NVAR_GLM) {
+    U[8] = q[8];
+    F[5 + D] = q[8];
+    F[8] = k.ch2 * Bd;
+  }
   if constexpr (Fast<RT>::value) {
     const RT a2 = k.gg1 * e;  // gamma p / rho
     c = fast_speed<RT, D>(q, a2);
@@ -500,9 +521,9 @@ template <typename RT, int D, int NV = NVAR>
 __device__ __forceinline__ void riemann_flux(const RT qL[NV], const RT qR[NV], const FaceConsts<RT>& k, int kind,
                                              RT F[NV]) {
   RT UL[NV], UR[NV], FL[NV], FR[NV], cL, cR;
-  if constexpr (NV == NVAR_MHD) {
-    mhd_face<RT, D>(qL, k, UL, FL, cL);
-    mhd_face<RT, D>(qR, k, UR, FR, cR);
+  if constexpr (NV >= NVAR_MHD) {
+    mhd_face<RT, D, NV>(qL, k, UL, FL, cL);
+    mhd_face<RT, D, NV>(qR, k, UR, FR, cR);
   } else {
     RT pL, pR;
     face_state<RT>(qL, k, UL, pL, cL);
@@ -518,8 +539,12 @@ __device__ __forceinline__ void riemann_flux(const RT qL[NV], const RT qR[NV], c
     FR[4] = (UR[4] + pR) * qR[2 + D];
   }
   const RT vL = qL[2 + D], vR = qR[2 + D];
-  const RT ap = fmax(RT(0), fmax(vL + cL, vR + cR));
-  const RT am = fmax(RT(0), fmax(-(vL - cL), -(vR - cR)));
+  RT ap = fmax(RT(0), fmax(vL + cL, vR + cR));
+  RT am = fmax(RT(0), fmax(-(vL - cL), -(vR - cR)));
+  if constexpr (NV == NVAR_GLM) {  // the (B_D, psi) pair travels at -c_h and +c_h
+    ap = fmax(ap, k.ch);
+    am = fmax(am, k.ch);
+  }
   if (kind == FLUX_HLL2) {
     const RT apm = ap * am, den = ap + am;
     if constexpr (Fast<RT>::value) {
@@ -553,7 +578,7 @@ __device__ __forceinline__ void riemann_flux_xy(RT qL[NV], RT qR[NV], bool ydir,
   if (ydir) {
     swap(qL[2], qL[3]);
     swap(qR[2], qR[3]);
-    if constexpr (NV == NVAR_MHD) {
+    if constexpr (NV >= NVAR_MHD) {
       swap(qL[5], qL[6]);
       swap(qR[5], qR[6]);
     }
@@ -561,7 +586,7 @@ __device__ __forceinline__ void riemann_flux_xy(RT qL[NV], RT qR[NV], bool ydir,
   riemann_flux<RT, 0, NV>(qL, qR, k, kind, F);
   if (ydir) {
     swap(F[1], F[2]);
-    if constexpr (NV == NVAR_MHD) swap(F[5], F[6]);
+    if constexpr (NV >= NVAR_MHD) swap(F[5], F[6]);
   }
 }
 

@@ -45,11 +45,11 @@ namespace amr {
 // tiles and synchronising only with itself.
 // NTH: threads per workgroup (256; 512 for the 32 x 16 tile, whose LDS allows one
 // workgroup per CU; 384 for 32 x 12, two per CU).
-// MHD (NV = 8): two waves per SIMD in FP32; one in FP64, whose eight-variable LDS
+// MHD (NV = 8, and 9 with the GLM field): two waves per SIMD in FP32; one in FP64, whose eight-variable LDS
 // tiles leave one workgroup per CU, so the kernel may use the whole register file.
 template <typename RT, int NV, int TX, int TY, int NTH, int STAGE, bool REC, bool TH1>
 __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(
-    NV == NVAR_MHD ? (Fast<RT>::value ? 2 : 1) : (Fast<RT>::value && !REC && NTH != 512 ? 3 : 2))))
+    NV >= NVAR_MHD ? (Fast<RT>::value ? 2 : 1) : (Fast<RT>::value && !REC && NTH != 512 ? 3 : 2))))
 void stage_kernel(StageArgs a) {
   constexpr int TL = TX * TY;  // lanes (columns) per tile
   static_assert(TL == NTH || TL == 64, "a tile is the workgroup or one wavefront");
@@ -73,7 +73,7 @@ void stage_kernel(StageArgs a) {
 
   Consts C = a.c;
   if constexpr (TH1) C.recon = RECON_E;  // (folds the reconstruction branches away)
-  const FaceConsts<RT> K{(RT)C.gamma, (RT)C.gm1, (RT)C.gg1, C.recon};
+  const FaceConsts<RT> K{(RT)C.gamma, (RT)C.gm1, (RT)C.gg1, C.recon, (RT)C.ch, (RT)C.ch2};
   const RT theta = (RT)C.theta;
   const int kind = C.flux;
   const int sub = WPB == 1 ? 0 : (int)threadIdx.x / TL;  // this lane's tile slot in the workgroup
@@ -597,27 +597,31 @@ static hipError_t launch_stage_rt(int shape, int stage, dim3 grid, hipStream_t s
   }
 }
 
-template <typename RT>
+template <typename RT, int NV>
 static hipError_t launch_stage_mhd(int shape, int stage, dim3 grid, hipStream_t s, const StageArgs& a) {
   switch (shape) {
-    case 0: return launch_stage_s<RT, NVAR_MHD, 256, 1>(stage, grid, s, a);
-    case 1: return launch_stage_s<RT, NVAR_MHD, 32, 8>(stage, grid, s, a);
-    case 4: return launch_stage_s<RT, NVAR_MHD, 8, 8>(stage, grid, s, a);
+    case 0: return launch_stage_s<RT, NV, 256, 1>(stage, grid, s, a);
+    case 1: return launch_stage_s<RT, NV, 32, 8>(stage, grid, s, a);
+    case 4: return launch_stage_s<RT, NV, 8, 8>(stage, grid, s, a);
     case 5:
-      if constexpr (Fast<RT>::value) return launch_stage_s<RT, NVAR_MHD, 32, 16, 512>(stage, grid, s, a);
+      if constexpr (Fast<RT>::value) return launch_stage_s<RT, NV, 32, 16, 512>(stage, grid, s, a);
       else return hipErrorInvalidValue;
     case 6:
-      if constexpr (Fast<RT>::value) return launch_stage_s<RT, NVAR_MHD, 32, 12, 384>(stage, grid, s, a);
+      if constexpr (Fast<RT>::value) return launch_stage_s<RT, NV, 32, 12, 384>(stage, grid, s, a);
       else return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_stage(int nv, int mixed, int shape, int stage, int grid, hipStream_t s, const StageArgs& a) {
-  if (nv == NVAR_MHD) {
+  if (nv == NVAR_MHD || nv == NVAR_GLM) {
     if (!mhd_shape_ok(mixed, shape)) return hipErrorInvalidValue;
-    if (mixed) return launch_stage_mhd<float>(shape, stage, dim3(grid), s, a);
-    return launch_stage_mhd<double>(shape, stage, dim3(grid), s, a);
+    if (nv == NVAR_GLM) {
+      if (mixed) return launch_stage_mhd<float, NVAR_GLM>(shape, stage, dim3(grid), s, a);
+      return launch_stage_mhd<double, NVAR_GLM>(shape, stage, dim3(grid), s, a);
+    }
+    if (mixed) return launch_stage_mhd<float, NVAR_MHD>(shape, stage, dim3(grid), s, a);
+    return launch_stage_mhd<double, NVAR_MHD>(shape, stage, dim3(grid), s, a);
   }
   if (mixed) return launch_stage_rt<float>(shape, stage, dim3(grid), s, a);
   return launch_stage_rt<double>(shape, stage, dim3(grid), s, a);
@@ -632,28 +636,33 @@ const void* stage_kernel_ptr(int nv, int mixed, int shape, int stage, bool rec) 
                      : reinterpret_cast<const void*>(&stage_kernel<RT, NV, TX, TY, NTH, 1, false, true>))     \
               : (rec ? reinterpret_cast<const void*>(&stage_kernel<RT, NV, TX, TY, NTH, 2, true, true>)       \
                      : reinterpret_cast<const void*>(&stage_kernel<RT, NV, TX, TY, NTH, 2, false, true>)))
-#define AMR_KPM(RT, TX, TY, NTH)                                                                              \
-  (rec ? nullptr                                                                                             \
-       : (stage == 1 ? reinterpret_cast<const void*>(&stage_kernel<RT, NVAR_MHD, TX, TY, NTH, 1, false, true>) \
-                     : reinterpret_cast<const void*>(&stage_kernel<RT, NVAR_MHD, TX, TY, NTH, 2, false, true>)))
-  if (nv == NVAR_MHD) {
+#define AMR_KPM(RT, NV, TX, TY, NTH)                                                                    \
+  (rec ? nullptr                                                                                       \
+       : (stage == 1 ? reinterpret_cast<const void*>(&stage_kernel<RT, NV, TX, TY, NTH, 1, false, true>) \
+                     : reinterpret_cast<const void*>(&stage_kernel<RT, NV, TX, TY, NTH, 2, false, true>)))
+#define AMR_KPM_NV(NV)                                                     \
+  if (mixed) {                                                             \
+    switch (shape) {                                                       \
+      case 0: return AMR_KPM(float, NV, 256, 1, 256);                      \
+      case 1: return AMR_KPM(float, NV, 32, 8, 256);                       \
+      case 4: return AMR_KPM(float, NV, 8, 8, 256);                        \
+      case 5: return AMR_KPM(float, NV, 32, 16, 512);                      \
+      case 6: return AMR_KPM(float, NV, 32, 12, 384);                      \
+    }                                                                      \
+  } else {                                                                 \
+    switch (shape) {                                                       \
+      case 0: return AMR_KPM(double, NV, 256, 1, 256);                     \
+      case 1: return AMR_KPM(double, NV, 32, 8, 256);                      \
+      case 4: return AMR_KPM(double, NV, 8, 8, 256);                       \
+    }                                                                      \
+  }                                                                        \
+  return nullptr;
+  if (nv == NVAR_MHD || nv == NVAR_GLM) {
     if (!mhd_shape_ok(mixed, shape)) return nullptr;
-    if (mixed) {
-      switch (shape) {
-        case 0: return AMR_KPM(float, 256, 1, 256);
-        case 1: return AMR_KPM(float, 32, 8, 256);
-        case 4: return AMR_KPM(float, 8, 8, 256);
-        case 5: return AMR_KPM(float, 32, 16, 512);
-        case 6: return AMR_KPM(float, 32, 12, 384);
-      }
-    } else {
-      switch (shape) {
-        case 0: return AMR_KPM(double, 256, 1, 256);
-        case 1: return AMR_KPM(double, 32, 8, 256);
-        case 4: return AMR_KPM(double, 8, 8, 256);
-      }
+    if (nv == NVAR_GLM) {
+      AMR_KPM_NV(NVAR_GLM)
     }
-    return nullptr;
+    AMR_KPM_NV(NVAR_MHD)
   }
   if (mixed) {
     switch (shape) {
@@ -678,6 +687,7 @@ const void* stage_kernel_ptr(int nv, int mixed, int shape, int stage, bool rec) 
   }
 #undef AMR_KP
 #undef AMR_KPM
+#undef AMR_KPM_NV
   return nullptr;
 }
 
@@ -685,6 +695,9 @@ hipError_t launch_cfl(int grid, hipStream_t s, const CflArgs& a) {
   if (a.nv == NVAR_MHD) {
     if (a.fast) hipLaunchKernelGGL((cfl_kernel<true, NVAR_MHD>), dim3(grid), dim3(NT), 0, s, a);
     else hipLaunchKernelGGL((cfl_kernel<false, NVAR_MHD>), dim3(grid), dim3(NT), 0, s, a);
+  } else if (a.nv == NVAR_GLM) {
+    if (a.fast) hipLaunchKernelGGL((cfl_kernel<true, NVAR_GLM>), dim3(grid), dim3(NT), 0, s, a);
+    else hipLaunchKernelGGL((cfl_kernel<false, NVAR_GLM>), dim3(grid), dim3(NT), 0, s, a);
   } else {
     if (a.fast) hipLaunchKernelGGL((cfl_kernel<true, NVAR>), dim3(grid), dim3(NT), 0, s, a);
     else hipLaunchKernelGGL((cfl_kernel<false, NVAR>), dim3(grid), dim3(NT), 0, s, a);

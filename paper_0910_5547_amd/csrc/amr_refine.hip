@@ -105,7 +105,7 @@ __global__ __launch_bounds__(NT) void copy_ranges(const int64_t* __restrict__ ra
 template <typename RT>
 __device__ void coarse_face_flux(const double* S, const PatchDev& Q, int d, int f, const int c[3],
                                  const Consts& C, RT F[NVAR], int& bad) {
-  const FaceConsts<RT> K{(RT)C.gamma, (RT)C.gm1, (RT)C.gg1, C.recon};
+  const FaceConsts<RT> K{(RT)C.gamma, (RT)C.gm1, (RT)C.gg1, C.recon, (RT)C.ch, (RT)C.ch2};
   const RT theta = (RT)C.theta;
   RT q[4][NVAR];
   for (int m = 0; m < 4; ++m) {

@@ -58,7 +58,7 @@ int main(void) {
   F(amr_patch_desc, offset) F(amr_patch_desc, bc) F(amr_patch_desc, reserved)
   F(amr_physics, gamma) F(amr_physics, theta) F(amr_physics, dx0) F(amr_physics, flux)
   F(amr_physics, precision) F(amr_physics, exec) F(amr_physics, periodic) F(amr_physics, domain)
-  F(amr_physics, recon) F(amr_physics, rho_floor) F(amr_physics, e_floor)
+  F(amr_physics, recon) F(amr_physics, rho_floor) F(amr_physics, e_floor) F(amr_physics, ch)
   return 0;
 }''')
     exe = tmp_path / "layout"
@@ -103,6 +103,7 @@ def _create(amr, ps, **kw):
     lambda d, ph: setattr(ph, "precision", 3),
     lambda d, ph: setattr(ph, "exec", 2),
     lambda d, ph: setattr(ph, "recon", 2),
+    lambda d, ph: setattr(ph, "ch", -1.0),
     lambda d, ph: setattr(ph, "periodic", 1),         # periodic root domain without extent
 ])
 def test_invalid_tables_are_rejected_on_the_host(amr, mutate):
