@@ -13,6 +13,8 @@ Workloads (seeded, synthetic; see paper_0910_5547_amd.workloads):
                layers, smooth states with random planar shocks in 20%
   sedov        deep-AMR octant Sedov hierarchy (7 levels, subcycled root steps)
   glm192       the mhd192 box with the GLM cleaning field (9 variables, c_h = 3)
+  sedovN       centred blast on a uniform N^3 grid (one patch); mhdsedovN: the same
+               with 8 MHD variables and a uniform field (the MHD blast timing series)
   mhd192       ideal MHD (8 variables), 192^3 periodic box as 216 patches of 32^3
                with EXTERNAL faces: Orszag-Tang-like vortex velocity, B = curl of
                a seeded GRF vector potential (divergence-free), plasma beta 1.7
@@ -171,6 +173,15 @@ def make_workload(name):
         kw = dict(periodic=7, domain=(192, 192, 192), ch=3.0)
         desc = ("GLM-MHD (9 variables, cleaning speed c_h = 3), the mhd192 vortex box with psi = 0: 192^3 "
                 "periodic as 216 patches of 32^3 (EXTERNAL faces, ng=3)")
+    elif name.startswith("sedov") or name.startswith("mhdsedov"):
+        # sedovN / mhdsedovN: the centred blast on a uniform N^3 grid (one patch), from the
+        # self-similar profile at t = 0.01; the MHD form carries the uniform field (0.01, 0, 0)
+        mhd = name.startswith("mhd")
+        N = int(name[8:] if mhd else name[5:])
+        ps, U, _ = W.sedov_uniform(N, t0=0.01, nvar=W.NVAR_MHD if mhd else W.NVAR, B0=0.01 if mhd else 0.0)
+        desc = (f"{'ideal-MHD ' if mhd else ''}blast on a uniform {N}^3 grid of [-1/2,1/2]^3, outflow faces, "
+                f"E=1, rho=1, p=1e-5, gamma=5/3, self-similar profile at t=0.01"
+                + (", B=(0.01,0,0)" if mhd else ""))
     elif name.startswith("box") and "p" in name[3:]:
         # boxNpP: the N^3 periodic box as (N/P)^3 patches of P^3 with EXTERNAL faces
         N, P = (int(x) for x in name[3:].split("p"))
@@ -273,12 +284,12 @@ def cpu_baseline(ps_full, U_full, kw, budget_s=12.0):
     nv = ps_full.nvar
     kw = {k: v for k, v in kw.items() if k not in ("periodic", "domain")}  # the sample has outflow faces
     if ps_full.npatch == 1:
-        B = 64
+        B = min(64, int(ps_full.n[0].min()))
         a = ps_full.active(U_full, 0)[:, :B, :B, :B]
-        ps = W.make_patchset(3, [[B, B, B]], 2, [W.BC_PERIODIC] * 6, gamma=ps_full.gamma, dx0=ps_full.dx0, nvar=nv)
+        ps = W.make_patchset(3, [[B, B, B]], 2, ps_full.bc[0], gamma=ps_full.gamma, dx0=ps_full.dx0, nvar=nv)
         U = W.new_arena(ps)
         ps.active(U, 0)[...] = a
-        what = f"{B}^3 periodic sub-box of the workload's field"
+        what = f"{B}^3 corner sub-box of the workload's field (its boundary conditions)"
     else:
         k = 64 if nv == W.NVAR else 8
         sel = list(range(k))

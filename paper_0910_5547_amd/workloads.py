@@ -661,6 +661,64 @@ class SedovSolution:
         return rho, vel, p
 
 
+def sedov_uniform(N=64, t0=0.01, E=1.0, gamma=5.0 / 3.0, rho1=1.0, p1=1e-5, nvar=NVAR, B0=0.0, ng=2, sub=2):
+    """Point explosion on a uniform N^3 grid of the cube [-1/2, 1/2]^3 (one patch, outflow faces),
+    initialised with the self-similar profile at time t0 (blast energy E at the centre), each cell
+    the mean of sub^3 samples.  nvar 8 makes an ideal-MHD set-up with the uniform field (B0, 0, 0)
+    (the uniform-grid MHD blast of the paper's MHD section); B0 = 0 keeps the hydro solution.
+    Returns (PatchSet, U, SedovSolution)."""
+    sol = SedovSolution(gamma)
+    ps = make_patchset(3, [[N, N, N]], ng, [BC_OUTFLOW] * 6, gamma=gamma, dx0=(1.0 / N,) * 3, nvar=nvar)
+    off = (np.arange(sub) + 0.5) / sub - 0.5
+    xc = (np.arange(N) + 0.5) / N - 0.5
+    rho = np.zeros((N, N, N))
+    mom = np.zeros((3, N, N, N))
+    En = np.zeros((N, N, N))
+    for oz in off:
+        for oy in off:
+            for ox in off:
+                Z, Y, X = np.meshgrid(xc + oz / N, xc + oy / N, xc + ox / N, indexing="ij")
+                r = np.sqrt(X * X + Y * Y + Z * Z)
+                d, vr, p = sol.state(r, E, t0, rho1, p1)
+                rs = np.maximum(r, 1e-300)
+                rho += d
+                for k, c in enumerate((X, Y, Z)):
+                    mom[k] += d * vr * c / rs
+                En += p / (gamma - 1.0) + 0.5 * d * vr * vr
+    n = float(sub ** 3)
+    rho, mom, En = rho / n, mom / n, En / n
+    U = new_arena(ps)
+    a = ps.active(U, 0)
+    a[0], a[1], a[2], a[3], a[4] = rho, mom[0], mom[1], mom[2], En
+    if nvar == NVAR_MHD:
+        a[4] += 0.5 * B0 * B0
+        a[5], a[6], a[7] = B0, 0.0, 0.0
+    return ps, U, sol
+
+
+def shock_radius(ps, U):
+    """Shock radius of a centred blast on a single-patch cube: the shell-averaged density profile
+    (shells one cell wide) is followed outward from its peak to where it falls half way to the
+    ambient density, interpolated linearly between shells."""
+    a = ps.active(U, 0)
+    N = int(ps.n[0, 0])
+    xc = (np.arange(N) + 0.5) / N - 0.5
+    Z, Y, X = np.meshgrid(xc, xc, xc, indexing="ij")
+    r = np.sqrt(X * X + Y * Y + Z * Z).ravel()
+    k = np.minimum((r * N).astype(int), N)
+    cnt = np.bincount(k, minlength=N + 1).astype(float)
+    prof = np.bincount(k, weights=a[0].ravel(), minlength=N + 1) / np.maximum(cnt, 1.0)
+    rmid = (np.arange(N + 1) + 0.5) / N
+    valid = np.nonzero(rmid < 0.5)[0]
+    i0 = int(valid[np.argmax(prof[valid])])
+    amb = prof[valid[-1]]
+    half = 0.5 * (prof[i0] + amb)
+    for i in range(i0, valid[-1]):
+        if prof[i] >= half > prof[i + 1]:
+            return float(rmid[i] + (prof[i] - half) / (prof[i] - prof[i + 1]) / N)
+    return float("nan")
+
+
 # Floors on recovered primitives for the Sedov set-up (ambient specific internal energy is
 # 1.5e-5).  A fixed hierarchy lets the Mach > 1000 shock cross coarse/fine interfaces,
 # where prolongation and refluxing can leave a cell with negative internal energy; the

@@ -96,3 +96,19 @@ def test_sedov_hierarchy_refines_the_shock_on_level_one(hierarchy):
         cov[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = True
     covered = cov[::2, ::2, ::2]
     assert covered[near].all()
+
+
+def test_uniform_sedov_shock_radius_follows_the_similarity_law(oracle_lib):
+    """Centred blast on a uniform grid, initialised with the self-similar profile at t = 0.01 and
+    advanced by the oracle to t = 0.02: the shock radius (half way down the shell-averaged density
+    front) lies within one cell of R(t) = xi0 (E t^2 / rho)^(1/5), and the error falls with the cell
+    size (the front is smeared over a few cells, so the estimate converges at first order)."""
+    errs = []
+    for N in (16, 32):
+        ps, U, sol = W.sedov_uniform(N, t0=0.01)
+        assert abs(W.shock_radius(ps, U) - sol.radius(1.0, 0.01)) <= 0.5 / N
+        o = oracle_lib.Oracle(ps)
+        o.run(U, 0.01, cfl=0.8)
+        errs.append(abs(W.shock_radius(ps, U) - sol.radius(1.0, 0.02)))
+        assert errs[-1] <= 1.0 / N, (N, errs[-1] * N)
+    assert errs[1] < errs[0]
