@@ -252,6 +252,49 @@ amr_status amr_autotune(amr_table* table, const double* U, const double* dt_dev,
  * plain form).  Waits for that step.  AMR_ESTATE if no timed step was run. */
 amr_status amr_table_last_stage_ms(amr_table* table, float ms[2]);
 
+/* Refinement flags (the steps beside the update that build a dynamic hierarchy; the
+ * paper does this on the host, Sec. 3).
+ * amr_table_cells: active cells of `level` (-1 = all levels), -1 for a bad argument.
+ * amr_flag_cells: one byte per active cell of `level` (-1 = all) into flags_dev (device
+ *   memory of amr_table_cells(level) bytes), patches in table order, cells x fastest:
+ *   1 where the density jumps by more than eps relative to the smaller value,
+ *   |rho_n - rho_c| / min(rho_n, rho_c) > eps, to a face neighbour n, else 0 (the
+ *   criterion that places the deep-AMR configuration's levels).  Neighbours across
+ *   patch faces follow the boundary conditions; EXTERNAL ghosts of the flagged level
+ *   and of every coarser level are refilled first from U's current state (this
+ *   writes U's EXTERNAL ghost storage, as a step does).  AMR_EINVAL for null
+ *   pointers, a level out of range or a negative eps.  Asynchronous. */
+int64_t amr_table_cells(const amr_table* table, int32_t level);
+amr_status amr_flag_cells(amr_table* table, double* U, int32_t level, double eps, uint8_t* flags_dev,
+                          hipStream_t stream);
+
+/* Fill the active cells of U (arena of `table`, a new hierarchy) from U_old (arena of
+ * old_table, the hierarchy it replaces): level by level from the root, a cell that an
+ * old patch of the same level holds is copied, any other is prolonged (conservative,
+ * minmod-limited linear, as for ghost cells) from the new level below, whose ghosts are
+ * filled first.  The root level must be covered by the old root patches, and every new
+ * box to be prolonged must lie in one patch of the level below (proper nesting).  Same
+ * nvar and ndim in both tables; hierarchies are hydro only (nvar 5).  Synchronises
+ * `stream` (the op lists are temporary device memory).  AMR_EINVAL otherwise. */
+amr_status amr_regrid_fill(const amr_table* old_table, const double* U_old, amr_table* table, double* U,
+                           hipStream_t stream);
+
+/* Host-side clustering of the flags of level `level` (host bytes, the layout of
+ * amr_flag_cells for the patches of that level in the given descriptor order) into the
+ * boxes of level `level`+1 (refinement 2), written to boxes[6 i .. 6 i + 5] = lo[3], n[3]
+ * in level+1 index space, sorted by lo then extent; *nboxes receives their count.  Each
+ * flagged cell, dilated by one cell along each axis, marks the fine bricks (brick^3
+ * fine cells, aligned) holding its children; a marked brick is kept when its level-l
+ * footprint dilated by one coarse cell (clipped to the root domain `domain` << level)
+ * lies on level l (proper nesting); kept bricks are grouped per aligned block^3 fine
+ * block into the group's bounding box if that box is nested, else into half-block
+ * bounding boxes, else single bricks.  Requires brick-aligned level-l patches, block a
+ * multiple of 2 brick.  AMR_EINVAL for bad arguments or more boxes than max_boxes (then
+ * *nboxes is the number needed).  No device work. */
+amr_status amr_cluster_flags(const amr_patch_desc* patches, int32_t npatch, int32_t ndim, const int32_t domain[3],
+                             int32_t level, const uint8_t* flags, int32_t brick, int32_t block, int32_t* boxes,
+                             int32_t max_boxes, int32_t* nboxes);
+
 const char* amr_status_string(amr_status status);
 
 #ifdef __cplusplus

@@ -531,3 +531,33 @@ double or_cfl_dt(int32_t np, const int32_t* meta, const int64_t* off, const or_p
   double s = or_max_speed(np, meta, off, ph, U, level, &bad);
   return cfl / s;
 }
+
+/* ---------------------------------------------------------------- flagging */
+int64_t or_flag_cells(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph, const double* V,
+                      int32_t level, double eps, uint8_t* flags) {
+  /* A cell is flagged for refinement where its density jumps by more than eps, relative to
+   * the smaller of the two, to any face neighbour: |rho_n - rho_c| / min(rho_n, rho_c) > eps.
+   * Neighbours across a patch face are read from ghost storage (filled beforehand). */
+  int64_t w = 0;
+  for (int p = 0; p < np; ++p) {
+    const int32_t* m = meta + (size_t)p * OR_META;
+    if (!is_level(m, level)) continue;
+    geom G = get_geom(m, off[p], ph->ndim);
+    for (int k3 = 0; k3 < G.n[2]; ++k3)
+      for (int j = 0; j < G.n[1]; ++j)
+        for (int i = 0; i < G.n[0]; ++i) {
+          int c[3] = {i, j, k3};
+          double rc = V[at(&G, 0, c)];
+          int f = 0;
+          for (int d = 0; d < ph->ndim; ++d)
+            for (int s = -1; s <= 1; s += 2) {
+              int nb[3] = {i, j, k3};
+              nb[d] += s;
+              double rn = V[at(&G, 0, nb)];
+              if (fabs(rn - rc) / fmin(rn, rc) > eps) f = 1;
+            }
+          flags[w++] = (uint8_t)f;
+        }
+  }
+  return w;
+}

@@ -98,6 +98,11 @@ int or_rk2_step(int32_t np, const int32_t* meta, const int64_t* off, const or_ph
  * sound speed (hydro) or the fast magnetosonic speed along d (MHD). */
 double or_max_speed(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph,
                     const double* U, int32_t level, int* flag);
+/* Refinement flags of the active cells of `level` (-1 = all), patch order, x fastest: 1 where
+ * |rho_n - rho_c| / min(rho_n, rho_c) > eps for a face neighbour n (ghosts of V filled
+ * beforehand).  Returns the number of flags written. */
+int64_t or_flag_cells(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph, const double* V,
+                      int32_t level, double eps, uint8_t* flags);
 /* dt = cfl / max speed (one level or a single-level table). */
 double or_cfl_dt(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph,
                  const double* U, double cfl, int32_t level);

@@ -60,6 +60,8 @@ def lib():
         L.or_rk2_step.argtypes = [C.c_int32, ip, lp, pp, dp, dp, C.c_double, C.c_int32]
         L.or_max_speed.restype = C.c_double
         L.or_max_speed.argtypes = [C.c_int32, ip, lp, pp, dp, C.c_int32, C.POINTER(C.c_int)]
+        L.or_flag_cells.restype = C.c_int64
+        L.or_flag_cells.argtypes = [C.c_int32, ip, lp, pp, dp, C.c_int32, C.c_double, C.POINTER(C.c_uint8)]
         L.or_cfl_dt.restype = C.c_double
         L.or_cfl_dt.argtypes = [C.c_int32, ip, lp, pp, dp, C.c_double, C.c_int32]
         _LIB = L
@@ -162,6 +164,15 @@ class Oracle:
     def cfl_dt(self, U, cfl, level=-1):
         return lib().or_cfl_dt(*self._args(), _dp(U), cfl, level)
 
+    def flag_cells(self, U, eps, level=-1):
+        """Refinement flags (uint8, one per active cell of `level`, patch order): ghosts of U are
+        filled first, so U's ghost storage is overwritten."""
+        self.fill_ghosts(U, level)
+        out = np.zeros(self.ps.active_cells(level), np.uint8)
+        n = lib().or_flag_cells(*self._args(), _dp(U), level, eps, out.ctypes.data_as(C.POINTER(C.c_uint8)))
+        assert n == out.size
+        return out
+
     def run(self, U, t_end, cfl=0.8, max_steps=10 ** 7):
         """Advance U (in place) to t_end with dt = cfl_dt, the last step clipped to t_end."""
         t, steps = 0.0, 0
@@ -220,6 +231,16 @@ class AmrOracle:
     def fill(self, V, level, Cold=None, Cnew=None, alpha=0.0):
         lib().or_fill_ghosts_amr(*self._args(), _dp(V), level, _dp(Cold) if Cold is not None else None,
                                  _dp(Cnew) if Cnew is not None else None, alpha)
+
+    def flag_cells(self, U, eps, level):
+        """Refinement flags of one level, its EXTERNAL ghosts filled from siblings and from the
+        coarse level's current state (the coarser levels' ghosts are filled first)."""
+        for lv in range(level + 1):
+            self.fill(U, lv, U, U, 1.0)
+        out = np.zeros(self.ps.active_cells(level), np.uint8)
+        n = lib().or_flag_cells(*self._args(), _dp(U), level, eps, out.ctypes.data_as(C.POINTER(C.c_uint8)))
+        assert n == out.size
+        return out
 
     def _stage(self, V, U0, out, dt, stage, level, rec):
         bad = lib().or_stage_rec(*self._args(), _dp(V), _dp(U0) if U0 is not None else None, _dp(out), dt, stage,

@@ -31,7 +31,8 @@ AMR_STEP_SUBSTEP1 = 0x4
 EXPORTED = ("amr_patch_table_create", "amr_patch_table_destroy", "amr_table_arena_elems", "amr_cfl_dt",
             "amr_hydro_rk2_step", "amr_flux_correct", "amr_table_status", "amr_table_num_tilings",
             "amr_table_set_tiling", "amr_table_get_tiling", "amr_table_tiling_shape", "amr_autotune",
-            "amr_table_last_stage_ms", "amr_hydro_advance", "amr_status_string")
+            "amr_table_last_stage_ms", "amr_hydro_advance", "amr_status_string", "amr_table_cells",
+            "amr_flag_cells", "amr_cluster_flags", "amr_regrid_fill")
 
 
 class amr_patch_desc(C.Structure):
@@ -81,8 +82,14 @@ def lib():
         L.amr_table_last_stage_ms.argtypes = [vp, C.POINTER(C.c_float)]
         L.amr_status_string.argtypes = [i32]
         L.amr_status_string.restype = C.c_char_p
+        L.amr_table_cells.argtypes = [vp, i32]
+        L.amr_table_cells.restype = i64
+        L.amr_flag_cells.argtypes = [vp, vp, i32, C.c_double, vp, vp]
+        L.amr_regrid_fill.argtypes = [vp, vp, vp, vp, vp]
+        L.amr_cluster_flags.argtypes = [C.POINTER(amr_patch_desc), i32, i32, C.POINTER(i32), i32,
+                                         C.POINTER(C.c_uint8), i32, i32, C.POINTER(i32), i32, C.POINTER(i32)]
         for name in EXPORTED:
-            if name not in ("amr_table_arena_elems", "amr_status_string"):
+            if name not in ("amr_table_arena_elems", "amr_status_string", "amr_table_cells"):
                 getattr(L, name).restype = i32
         _LIB = L
     return _LIB
@@ -215,6 +222,42 @@ def amr_autotune(h, U, dt_dev, level=-1, reps=3, stream=None):
     _check(lib().amr_autotune(h, _ptr(U), _ptr(dt_dev), int(level), int(reps), _stream(stream), C.byref(ms)),
            "amr_autotune")
     return ms.value
+
+
+def amr_table_cells(h, level=-1):
+    return int(lib().amr_table_cells(h, level))
+
+
+def amr_flag_cells(h, U, level, eps, flags, stream=None):
+    """Refinement flags of `level` into the uint8 device tensor `flags` (amr_table_cells(level) bytes)."""
+    if not (flags.dtype == torch.uint8 and flags.is_cuda and flags.is_contiguous()
+            and flags.numel() >= amr_table_cells(h, level)):
+        raise ValueError("flags must be a contiguous uint8 GPU tensor of amr_table_cells(level) bytes")
+    _check(lib().amr_flag_cells(h, _ptr(U), level, float(eps), C.c_void_p(flags.data_ptr()), _stream(stream)),
+           "amr_flag_cells")
+
+
+def amr_regrid_fill(h_old, U_old, h_new, U_new, stream=None):
+    _check(lib().amr_regrid_fill(h_old, _ptr(U_old), h_new, _ptr(U_new), _stream(stream)), "amr_regrid_fill")
+
+
+def amr_cluster_flags(descs, ndim, domain, level, flags, brick=8, block=32):
+    """Boxes (lo[3], n[3]) of level+1 clustered from the host uint8 flags of `level` (host work)."""
+    flags = np.ascontiguousarray(flags, np.uint8)
+    dom = (C.c_int32 * 3)(*[int(x) for x in domain])
+    n = C.c_int32(0)
+    cap = 1024
+    while True:
+        out = np.zeros(6 * cap, np.int32)
+        st = lib().amr_cluster_flags(descs, len(descs), ndim, dom, level,
+                                     flags.ctypes.data_as(C.POINTER(C.c_uint8)), brick, block,
+                                     out.ctypes.data_as(C.POINTER(C.c_int32)), cap, C.byref(n))
+        if st == AMR_OK:
+            return out[:6 * n.value].reshape(-1, 6)
+        if n.value > cap:
+            cap = n.value
+            continue
+        _check(st, "amr_cluster_flags")
 
 
 def amr_table_last_stage_ms(h):

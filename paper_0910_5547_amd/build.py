@@ -11,7 +11,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libamrhydro.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("amr_kernels.hip", "amr_refine.hip", "amr_api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("amr_kernels.hip", "amr_refine.hip", "amr_regrid.hip",
+                                                       "amr_api.hip", "amr_cluster.cpp")]
 ARCH = os.environ.get("AMR_OFFLOAD_ARCH", "gfx950")
 
 

@@ -44,6 +44,14 @@ struct WorkList {
   int blk_base = 0, nblk = 0;
 };
 
+// The patches of a level scope and the prefix sums of their active cells (flagging).
+struct CellList {
+  int* plist = nullptr;
+  int64_t* cofs = nullptr;
+  int npl = 0;
+  int64_t ncells = 0;
+};
+
 }  // namespace
 
 struct amr_table {
@@ -98,6 +106,7 @@ struct amr_table {
   int* blk_d = nullptr;
   std::vector<WorkList> w_copy, w_prol, w_phys, w_rst;
   std::vector<std::vector<WorkList>> w_fix;
+  std::map<int, CellList> cell_lists;           // per level scope (-1 = all), built on first use
 };
 
 #define HIPCHECK(x)                                     \
@@ -307,15 +316,16 @@ int occupancy_grid(amr_table* t, int stage, int ntiles, bool rec) {
 // between its snapshot and its state in U at fraction alpha.
 Work work_of(const amr_table* t, const WorkList& w) { return Work{t->segs_d, t->blk_d + w.blk_base, w.nblk, 0}; }
 
-amr_status enqueue_ghosts(amr_table* t, double* A, const double* U, int level, double alpha, hipStream_t s) {
+amr_status enqueue_ghosts(amr_table* t, double* A, const double* U, int level, double alpha, hipStream_t s,
+                          const double* Cold = nullptr) {
   const int l0 = level < 0 ? 0 : level, l1 = level < 0 ? t->max_level : level;
   for (int l = l0; l <= l1; ++l)
     if (t->w_copy[l].nblk > 0)
       HIPCHECK(launch_copy_ghosts(s, t->ops_d + t->ops_level_first[l], work_of(t, t->w_copy[l]), t->pdev_d, A,
                                   t->ph.nvar));
   if (level > 0 && t->w_prol[level].nblk > 0)
-    HIPCHECK(launch_prolong(s, t->prol_d + t->prol_first[level], work_of(t, t->w_prol[level]), t->pdev_d, A, t->snap,
-                            U, alpha, t->ph.ndim));
+    HIPCHECK(launch_prolong(s, t->prol_d + t->prol_first[level], work_of(t, t->w_prol[level]), t->pdev_d, A,
+                            Cold ? Cold : t->snap, U, alpha, t->ph.ndim));
   return AMR_OK;
 }
 
@@ -1049,6 +1059,10 @@ amr_status amr_patch_table_destroy(amr_table* t) {
   drop_graph(t);
   for (auto& kv : t->tiles)
     if (kv.second.d) (void)hipFree(kv.second.d);
+  for (auto& kv : t->cell_lists) {
+    if (kv.second.plist) (void)hipFree(kv.second.plist);
+    if (kv.second.cofs) (void)hipFree(kv.second.cofs);
+  }
   if (t->pdev_d) (void)hipFree(t->pdev_d);
   if (t->U1) (void)hipFree(t->U1);
   if (t->flag_d) (void)hipFree(t->flag_d);
@@ -1343,6 +1357,200 @@ amr_status amr_autotune(amr_table* t, const double* U, const double* dt_dev, int
     // the candidate runs may have latched a flag on the copy; report through status as usual
   }
   return st;
+}
+
+amr_status amr_regrid_fill(const amr_table* old_t, const double* U_old, amr_table* t, double* U,
+                           hipStream_t stream) {
+  if (!old_t || !U_old || !t || !U || old_t == t || old_t->ph.nvar != t->ph.nvar || old_t->ph.ndim != t->ph.ndim)
+    return AMR_EINVAL;
+  if (t->max_level > 0 && t->ph.nvar != NVAR) return AMR_EINVAL;
+  const int nd = t->ph.ndim;
+  std::vector<CopyOp> cops;
+  std::vector<ProlongOp> pops;
+  std::vector<int> cfirst(t->max_level + 2, 0), pfirst(t->max_level + 2, 0);
+  for (int l = 0; l <= t->max_level; ++l) {
+    cfirst[l] = (int)cops.size();
+    pfirst[l] = (int)pops.size();
+    for (size_t p = 0; p < t->desc.size(); ++p) {
+      const amr_patch_desc& D = t->desc[p];
+      if (D.level != l) continue;
+      std::vector<char> need((size_t)D.n[0] * D.n[1] * D.n[2], 1);
+      for (size_t q = 0; q < old_t->desc.size(); ++q) {
+        const amr_patch_desc& Q = old_t->desc[q];
+        if (Q.level != l) continue;
+        CopyOp op{};
+        op.dst = (int)p;
+        op.src = (int)q;
+        bool empty = false;
+        for (int e = 0; e < 3; ++e) {
+          const int lo = std::max(D.lo[e], Q.lo[e]), hi = std::min(D.lo[e] + D.n[e], Q.lo[e] + Q.n[e]);
+          if (e >= nd) {
+            op.lo[e] = 0;
+            op.sz[e] = 1;
+            op.sh[e] = 0;
+            continue;
+          }
+          if (hi <= lo) {
+            empty = true;
+            break;
+          }
+          op.lo[e] = lo - D.lo[e];
+          op.sz[e] = hi - lo;
+          op.sh[e] = D.lo[e] - Q.lo[e];
+        }
+        if (empty) continue;
+        for (int k = 0; k < op.sz[2]; ++k)
+          for (int j = 0; j < op.sz[1]; ++j)
+            for (int i = 0; i < op.sz[0]; ++i)
+              need[((size_t)(op.lo[2] + k) * D.n[1] + op.lo[1] + j) * D.n[0] + op.lo[0] + i] = 0;
+        cops.push_back(op);
+      }
+      bool any = false;
+      for (char c : need) any = any || c;
+      if (!any) continue;
+      if (l == 0) return AMR_EINVAL;  // a new root cell that no old root patch holds
+      // the rest is prolonged from the new table's level l-1: boxes of it under each coarse patch
+      for (size_t q = 0; q < t->desc.size(); ++q) {
+        const amr_patch_desc& Q = t->desc[q];
+        if (Q.level != l - 1) continue;
+        int ilo[3], isz[3];  // part of D under Q, D-local
+        bool empty = false;
+        for (int e = 0; e < 3; ++e) {
+          if (e >= nd) {
+            ilo[e] = 0;
+            isz[e] = 1;
+            continue;
+          }
+          const int lo = std::max(D.lo[e], 2 * Q.lo[e]), hi = std::min(D.lo[e] + D.n[e], 2 * (Q.lo[e] + Q.n[e]));
+          if (hi <= lo) {
+            empty = true;
+            break;
+          }
+          ilo[e] = lo - D.lo[e];
+          isz[e] = hi - lo;
+        }
+        if (empty) continue;
+        std::vector<char> sub((size_t)isz[0] * isz[1] * isz[2]);
+        for (int k = 0; k < isz[2]; ++k)
+          for (int j = 0; j < isz[1]; ++j)
+            for (int i = 0; i < isz[0]; ++i) {
+              char& m = need[((size_t)(ilo[2] + k) * D.n[1] + ilo[1] + j) * D.n[0] + ilo[0] + i];
+              sub[((size_t)k * isz[1] + j) * isz[0] + i] = m;
+              m = 0;
+            }
+        cover_boxes(isz, sub, [&](const int lo[3], const int sz[3]) {
+          ProlongOp op{};
+          op.dst = (int)p;
+          op.src = (int)q;
+          for (int e = 0; e < 3; ++e) {
+            op.lo[e] = ilo[e] + lo[e];
+            op.sz[e] = sz[e];
+            op.foff[e] = e < nd ? D.lo[e] : 0;
+            op.clo[e] = e < nd ? Q.lo[e] : 0;
+          }
+          pops.push_back(op);
+        });
+      }
+      amr_status bad = AMR_OK;
+      for (char c : need)
+        if (c) bad = AMR_EINVAL;  // a fine cell over no coarse patch
+      if (bad != AMR_OK) return bad;
+    }
+  }
+  cfirst[t->max_level + 1] = (int)cops.size();
+  pfirst[t->max_level + 1] = (int)pops.size();
+  // device copies of the op lists and their work lists (freed when the fill has run)
+  std::vector<Seg> segs;
+  std::vector<int> blk;
+  std::vector<WorkList> wc(t->max_level + 1), wp(t->max_level + 1);
+  for (int l = 0; l <= t->max_level; ++l) {
+    wc[l] = add_work(segs, blk, cops.data() + cfirst[l], cfirst[l + 1] - cfirst[l]);
+    wp[l] = add_work(segs, blk, pops.data() + pfirst[l], pfirst[l + 1] - pfirst[l]);
+  }
+  CopyOp* cops_d = nullptr;
+  ProlongOp* pops_d = nullptr;
+  Seg* segs_d = nullptr;
+  int* blk_d = nullptr;
+  amr_status st = AMR_OK;
+  auto up = [&](auto** dst, const auto& v) -> bool {
+    if (v.empty()) return true;
+    using T = typename std::remove_reference<decltype(v)>::type::value_type;
+    if (hipMalloc(dst, sizeof(T) * v.size()) != hipSuccess) return false;
+    return hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) == hipSuccess;
+  };
+  if (!up(&cops_d, cops) || !up(&pops_d, pops) || !up(&segs_d, segs) || !up(&blk_d, blk)) st = AMR_ENOMEM;
+  for (int l = 0; l <= t->max_level && st == AMR_OK; ++l) {
+    const Work w1{segs_d, blk_d + wc[l].blk_base, wc[l].nblk, 0};
+    if (wc[l].nblk > 0 && launch_copy_cells_x(stream, cops_d + cfirst[l], w1, t->pdev_d, old_t->pdev_d, U, U_old,
+                                              t->ph.nvar) != hipSuccess)
+      st = AMR_EHIP;
+    const Work w2{segs_d, blk_d + wp[l].blk_base, wp[l].nblk, 0};
+    if (st == AMR_OK && wp[l].nblk > 0 &&
+        launch_prolong(stream, pops_d + pfirst[l], w2, t->pdev_d, U, U, U, 0.0, nd) != hipSuccess)
+      st = AMR_EHIP;
+    // this level's ghosts, read by its children's prolongation stencils
+    if (st == AMR_OK && l < t->max_level) {
+      st = enqueue_ghosts(t, U, U, l, 0.0, stream, U);
+      if (st == AMR_OK && t->has_kids[l] && t->w_phys[l].nblk > 0 &&
+          launch_phys(stream, t->phys_d + t->phys_first[l], work_of(t, t->w_phys[l]), t->pdev_d, U) != hipSuccess)
+        st = AMR_EHIP;
+    }
+  }
+  if (hipStreamSynchronize(stream) != hipSuccess && st == AMR_OK) st = AMR_EHIP;
+  for (void* q : {(void*)cops_d, (void*)pops_d, (void*)segs_d, (void*)blk_d})
+    if (q) (void)hipFree(q);
+  return st;
+}
+
+int64_t amr_table_cells(const amr_table* t, int32_t level) {
+  if (!t || level < -1 || level > t->max_level) return -1;
+  int64_t n = 0;
+  for (const PatchDev& P : t->pdev)
+    if (level < 0 || P.level == level) n += (int64_t)P.n[0] * P.n[1] * P.n[2];
+  return n;
+}
+
+amr_status amr_flag_cells(amr_table* t, double* U, int32_t level, double eps, uint8_t* flags_dev,
+                          hipStream_t stream) {
+  if (!t || !U || !flags_dev || level < -1 || level > t->max_level || !(eps >= 0.0 && eps < 1e300))
+    return AMR_EINVAL;
+  auto it = t->cell_lists.find(level);
+  if (it == t->cell_lists.end()) {
+    CellList cl;
+    std::vector<int> pl;
+    std::vector<int64_t> co{0};
+    for (size_t p = 0; p < t->pdev.size(); ++p) {
+      const PatchDev& P = t->pdev[p];
+      if (level >= 0 && P.level != level) continue;
+      pl.push_back((int)p);
+      co.push_back(co.back() + (int64_t)P.n[0] * P.n[1] * P.n[2]);
+    }
+    cl.npl = (int)pl.size();
+    cl.ncells = co.back();
+    if (cl.npl > 0) {
+      if (hipMalloc(&cl.plist, sizeof(int) * pl.size()) != hipSuccess) return AMR_ENOMEM;
+      if (hipMalloc(&cl.cofs, sizeof(int64_t) * co.size()) != hipSuccess) {
+        (void)hipFree(cl.plist);
+        return AMR_ENOMEM;
+      }
+      HIPCHECK(hipMemcpy(cl.plist, pl.data(), sizeof(int) * pl.size(), hipMemcpyHostToDevice));
+      HIPCHECK(hipMemcpy(cl.cofs, co.data(), sizeof(int64_t) * co.size(), hipMemcpyHostToDevice));
+    }
+    it = t->cell_lists.emplace(level, cl).first;
+  }
+  const CellList& cl = it->second;
+  if (cl.ncells == 0) return AMR_OK;
+  // current ghosts of the flagged levels and of every coarser level (prolongation stencils)
+  const int lmax = level < 0 ? t->max_level : level;
+  for (int l = 0; l <= lmax; ++l) {
+    amr_status st = enqueue_ghosts(t, U, U, l, 1.0, stream, U);  // coarse data: U itself
+    if (st != AMR_OK) return st;
+    if (l < t->max_level && t->has_kids[l] && t->w_phys[l].nblk > 0)
+      HIPCHECK(launch_phys(stream, t->phys_d + t->phys_first[l], work_of(t, t->w_phys[l]), t->pdev_d, U));
+  }
+  HIPCHECK(launch_flag_cells(stream, cl.plist, cl.cofs, cl.npl, cl.ncells, t->pdev_d, U, eps, flags_dev,
+                             t->ph.ndim));
+  return AMR_OK;
 }
 
 }  // extern "C"

@@ -77,6 +77,10 @@ hipError_t launch_flux_fix(int mixed, hipStream_t s, const FixOp* ops, const Wor
 hipError_t launch_restrict(hipStream_t s, const RestrictOp* ops, const Work& w, const PatchDev* p, double* U,
                            int ndim);
 hipError_t launch_scale_dt(hipStream_t s, const double* dt0, double* dtl, int nlev);
+hipError_t launch_copy_cells_x(hipStream_t s, const CopyOp* ops, const Work& w, const PatchDev* pdst,
+                               const PatchDev* psrc, double* Adst, const double* Asrc, int nv);
+hipError_t launch_flag_cells(hipStream_t s, const int* plist, const int64_t* cofs, int npl, int64_t ncells,
+                             const PatchDev* patches, const double* U, double eps, uint8_t* flags, int ndim);
 
 // Compiled tile shapes; shape 0 is the 1D shape.  TX x TY = workgroup size: one
 // tile per workgroup (256 threads; 512 for 32 x 16, shape 5, and 384 for 32 x 12,
