@@ -22,7 +22,11 @@
  * cleaning field psi follows B (the paper's GLM system): the B_d entry of the
  * d-flux is psi, the psi entry c_h^2 B_d, and the pair's wave speeds -c_h and
  * +c_h join the Riemann flux's a+ and a- and the CFL rule (no damping source:
- * the paper writes none).  MHD tables are single level (every patch at level 0).
+ * the paper writes none).  On a hierarchy the coarse/fine coupling (ghost
+ * prolongation, restriction, refluxing) treats every conserved variable alike,
+ * B and psi included: the prolonged and restricted field keeps the totals but is
+ * not divergence-free in general (the paper's GLM field is what transports such
+ * divergence away).
  *
  * Conventions shared by every entry point
  *   - Every function returns an amr_status: AMR_OK (0) or a negative code.
@@ -151,7 +155,7 @@ typedef struct amr_table amr_table; /* opaque, library-owned */
  * Copies the descriptors, validates them (AMR_EINVAL on: npatch < 1, n < 1,
  * ng out of range in an active dimension, n > 1 in an absent dimension,
  * overlapping storage, unknown bc/flux/precision/exec/recon, nvar not 5, 8 or 9,
- * a patch of level > 0 with nvar 8 or 9, ch negative or not finite,
+ * ch negative or not finite,
  * gamma <= 1, theta outside [0,2], dx0 <= 0, a PERIODIC face whose opposite
  * face is not PERIODIC), allocates the device-side copy, the stage scratch
  * arena U^(1) (same size as the U arena) and the reduction/flag words, builds
@@ -274,7 +278,7 @@ amr_status amr_flag_cells(amr_table* table, double* U, int32_t level, double eps
  * minmod-limited linear, as for ghost cells) from the new level below, whose ghosts are
  * filled first.  The root level must be covered by the old root patches, and every new
  * box to be prolonged must lie in one patch of the level below (proper nesting).  Same
- * nvar and ndim in both tables; hierarchies are hydro only (nvar 5).  Synchronises
+ * nvar and ndim in both tables.  Synchronises
  * `stream` (the op lists are temporary device memory).  AMR_EINVAL otherwise. */
 amr_status amr_regrid_fill(const amr_table* old_table, const double* U_old, amr_table* table, double* U,
                            hipStream_t stream);

@@ -206,10 +206,10 @@ class AmrOracle:
     """
 
     def __init__(self, ps, periodic=0, domain=(0, 0, 0), flux=FLUX_PAPER, rho_floor=0.0, e_floor=0.0,
-                 recon=RECON_E):
+                 recon=RECON_E, ch=0.0):
         self.ps = ps
         self.o = Oracle(ps, flux=flux, rho_floor=rho_floor, e_floor=e_floor, periodic=periodic, domain=domain,
-                        recon=recon)
+                        recon=recon, ch=ch)
         self.periodic, self.domain = periodic, domain
         self.nlev = int(ps.level.max()) + 1
         L = lib()

@@ -300,7 +300,7 @@ int occupancy_grid(amr_table* t, int stage, int ntiles, bool rec) {
   int& per_cu = t->occ[vk][mixed][t->shape][stage - 1][rec ? 1 : 0];
   if (per_cu <= 0) {
     const void* k = stage_kernel_ptr(t->ph.nvar, mixed, t->shape, stage, rec);
-    if (!k) {  // not compiled (MHD recording kernels): never launched, nothing to size
+    if (!k) {  // not compiled for this shape: never launched, nothing to size
       per_cu = 1;
     } else if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, SHAPE_NT[t->shape], 0) != hipSuccess ||
                per_cu < 1) {
@@ -325,7 +325,7 @@ amr_status enqueue_ghosts(amr_table* t, double* A, const double* U, int level, d
                                   t->ph.nvar));
   if (level > 0 && t->w_prol[level].nblk > 0)
     HIPCHECK(launch_prolong(s, t->prol_d + t->prol_first[level], work_of(t, t->w_prol[level]), t->pdev_d, A,
-                            Cold ? Cold : t->snap, U, alpha, t->ph.ndim));
+                            Cold ? Cold : t->snap, U, alpha, t->ph.ndim, t->ph.nvar));
   return AMR_OK;
 }
 
@@ -383,7 +383,8 @@ amr_status enqueue_step(amr_table* t, double* U, const double* dt, int level, ui
   if (st != AMR_OK) return st;
   if (kids) {
     if (t->w_phys[level].nblk > 0)
-      HIPCHECK(launch_phys(s, t->phys_d + t->phys_first[level], work_of(t, t->w_phys[level]), t->pdev_d, U));
+      HIPCHECK(launch_phys(s, t->phys_d + t->phys_first[level], work_of(t, t->w_phys[level]), t->pdev_d, U,
+                                 t->ph.nvar));
     HIPCHECK(launch_copy_ranges(s, t->snap_d + 2 * t->snap_first[level], t->snap_count[level],
                                 t->snap_maxlen[level], U, t->snap));
   }
@@ -401,7 +402,8 @@ amr_status enqueue_step(amr_table* t, double* U, const double* dt, int level, ui
     st = enqueue_ghosts(t, U, U, level, a2, s);
     if (st != AMR_OK) return st;
     if (t->w_phys[level].nblk > 0)
-      HIPCHECK(launch_phys(s, t->phys_d + t->phys_first[level], work_of(t, t->w_phys[level]), t->pdev_d, U));
+      HIPCHECK(launch_phys(s, t->phys_d + t->phys_first[level], work_of(t, t->w_phys[level]), t->pdev_d, U,
+                                 t->ph.nvar));
     const int64_t len = t->reg_len[level + 1];
     if (len > 0) {
       for (int64_t o = 0; o < len; o += (int64_t)1 << 30)
@@ -418,10 +420,12 @@ amr_status enqueue_correct(amr_table* t, double* U, int l, hipStream_t s) {
   const int mixed = t->ph.precision == AMR_PREC_MIXED;
   for (size_t c = 0; c < t->fix_colors[l].size(); ++c)
     if (t->w_fix[l][c].nblk > 0)
-      HIPCHECK(launch_flux_fix(mixed, s, t->fix_d + t->fix_colors[l][c].first, work_of(t, t->w_fix[l][c]), t->pdev_d,
-                               U, t->snap, t->U1, t->reg, t->last_dt[l], consts_of(t), t->flag_d));
+      HIPCHECK(launch_flux_fix(mixed, t->ph.nvar, s, t->fix_d + t->fix_colors[l][c].first,
+                               work_of(t, t->w_fix[l][c]), t->pdev_d, U, t->snap, t->U1, t->reg, t->last_dt[l],
+                               consts_of(t), t->flag_d));
   if (t->w_rst[l].nblk > 0)
-    HIPCHECK(launch_restrict(s, t->rst_d + t->rst_first[l], work_of(t, t->w_rst[l]), t->pdev_d, U, t->ph.ndim));
+    HIPCHECK(launch_restrict(s, t->rst_d + t->rst_first[l], work_of(t, t->w_rst[l]), t->pdev_d, U, t->ph.ndim,
+                             t->ph.nvar));
   return AMR_OK;
 }
 
@@ -470,7 +474,6 @@ amr_status validate(const amr_patch_desc* P, int32_t np, const amr_physics* ph) 
   for (int p = 0; p < np; ++p) {
     const amr_patch_desc& D = P[p];
     if (D.level < 0 || D.level >= MAX_LEVELS || D.offset < 0 || D.reserved[0] || D.reserved[1]) return AMR_EINVAL;
-    if (ph->nvar != NVAR && D.level != 0) return AMR_EINVAL;  // MHD: single-level tables
     if (D.ng < 2 || D.ng > 8) return AMR_EINVAL;
     int64_t S = 1;
     for (int d = 0; d < 3; ++d) {
@@ -1363,7 +1366,6 @@ amr_status amr_regrid_fill(const amr_table* old_t, const double* U_old, amr_tabl
                            hipStream_t stream) {
   if (!old_t || !U_old || !t || !U || old_t == t || old_t->ph.nvar != t->ph.nvar || old_t->ph.ndim != t->ph.ndim)
     return AMR_EINVAL;
-  if (t->max_level > 0 && t->ph.nvar != NVAR) return AMR_EINVAL;
   const int nd = t->ph.ndim;
   std::vector<CopyOp> cops;
   std::vector<ProlongOp> pops;
@@ -1486,13 +1488,14 @@ amr_status amr_regrid_fill(const amr_table* old_t, const double* U_old, amr_tabl
       st = AMR_EHIP;
     const Work w2{segs_d, blk_d + wp[l].blk_base, wp[l].nblk, 0};
     if (st == AMR_OK && wp[l].nblk > 0 &&
-        launch_prolong(stream, pops_d + pfirst[l], w2, t->pdev_d, U, U, U, 0.0, nd) != hipSuccess)
+        launch_prolong(stream, pops_d + pfirst[l], w2, t->pdev_d, U, U, U, 0.0, nd, t->ph.nvar) != hipSuccess)
       st = AMR_EHIP;
     // this level's ghosts, read by its children's prolongation stencils
     if (st == AMR_OK && l < t->max_level) {
       st = enqueue_ghosts(t, U, U, l, 0.0, stream, U);
       if (st == AMR_OK && t->has_kids[l] && t->w_phys[l].nblk > 0 &&
-          launch_phys(stream, t->phys_d + t->phys_first[l], work_of(t, t->w_phys[l]), t->pdev_d, U) != hipSuccess)
+          launch_phys(stream, t->phys_d + t->phys_first[l], work_of(t, t->w_phys[l]), t->pdev_d, U, t->ph.nvar) !=
+              hipSuccess)
         st = AMR_EHIP;
     }
   }
@@ -1546,7 +1549,7 @@ amr_status amr_flag_cells(amr_table* t, double* U, int32_t level, double eps, ui
     amr_status st = enqueue_ghosts(t, U, U, l, 1.0, stream, U);  // coarse data: U itself
     if (st != AMR_OK) return st;
     if (l < t->max_level && t->has_kids[l] && t->w_phys[l].nblk > 0)
-      HIPCHECK(launch_phys(stream, t->phys_d + t->phys_first[l], work_of(t, t->w_phys[l]), t->pdev_d, U));
+      HIPCHECK(launch_phys(stream, t->phys_d + t->phys_first[l], work_of(t, t->w_phys[l]), t->pdev_d, U, t->ph.nvar));
   }
   HIPCHECK(launch_flag_cells(stream, cl.plist, cl.cofs, cl.npl, cl.ncells, t->pdev_d, U, eps, flags_dev,
                              t->ph.ndim));

@@ -1,5 +1,6 @@
 // amr_internal.h - kernel argument blocks and launcher declarations shared by
-// the kernels (amr_kernels.hip) and the host library (amr_api.hip).
+// the kernels (amr_kernels.hip, amr_stage*.hip, amr_refine.hip, amr_regrid.hip) and the
+// host library (amr_api.hip).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -59,6 +60,15 @@ __device__ __forceinline__ void wave_max_to(unsigned long long* dst, double v) {
 
 hipError_t launch_stage(int nv, int mixed, int shape, int stage, int grid, hipStream_t s, const StageArgs& a);
 const void* stage_kernel_ptr(int nv, int mixed, int shape, int stage, bool rec);
+// per translation unit of the stage kernel (amr_stage_*.hip)
+hipError_t launch_stage_hydro_f32(int shape, int stage, int grid, hipStream_t s, const StageArgs& a);
+hipError_t launch_stage_hydro_f64(int shape, int stage, int grid, hipStream_t s, const StageArgs& a);
+hipError_t launch_stage_mhd8(int mixed, int shape, int stage, int grid, hipStream_t s, const StageArgs& a);
+hipError_t launch_stage_glm9(int mixed, int shape, int stage, int grid, hipStream_t s, const StageArgs& a);
+const void* stage_kernel_ptr_hydro_f32(int shape, int stage, bool rec);
+const void* stage_kernel_ptr_hydro_f64(int shape, int stage, bool rec);
+const void* stage_kernel_ptr_mhd8(int mixed, int shape, int stage, bool rec);
+const void* stage_kernel_ptr_glm9(int mixed, int shape, int stage, bool rec);
 hipError_t launch_cfl(int grid, hipStream_t s, const CflArgs& a);
 hipError_t launch_cfl_finalize(hipStream_t s, const unsigned long long* smax, int lmin, int lmax, int root,
                                double cfl, double* dt);
@@ -67,15 +77,15 @@ hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, int n, unsigned
 hipError_t launch_fill_i32(hipStream_t s, int* p, int n, int v);
 
 hipError_t launch_prolong(hipStream_t s, const ProlongOp* ops, const Work& w, const PatchDev* p, double* A,
-                          const double* Cold, const double* Cnew, double alpha, int ndim);
-hipError_t launch_phys(hipStream_t s, const PhysOp* ops, const Work& w, const PatchDev* p, double* A);
+                          const double* Cold, const double* Cnew, double alpha, int ndim, int nv);
+hipError_t launch_phys(hipStream_t s, const PhysOp* ops, const Work& w, const PatchDev* p, double* A, int nv);
 hipError_t launch_copy_ranges(hipStream_t s, const int64_t* ranges, int nr, int64_t maxlen, const double* src,
                               double* dst);
-hipError_t launch_flux_fix(int mixed, hipStream_t s, const FixOp* ops, const Work& w, const PatchDev* p, double* U,
-                           const double* S1, const double* S2, const double* reg, const double* dtc, const Consts& C,
-                           int* flag);
+hipError_t launch_flux_fix(int mixed, int nv, hipStream_t s, const FixOp* ops, const Work& w, const PatchDev* p,
+                           double* U, const double* S1, const double* S2, const double* reg, const double* dtc,
+                           const Consts& C, int* flag);
 hipError_t launch_restrict(hipStream_t s, const RestrictOp* ops, const Work& w, const PatchDev* p, double* U,
-                           int ndim);
+                           int ndim, int nv);
 hipError_t launch_scale_dt(hipStream_t s, const double* dt0, double* dtl, int nlev);
 hipError_t launch_copy_cells_x(hipStream_t s, const CopyOp* ops, const Work& w, const PatchDev* pdst,
                                const PatchDev* psrc, double* Adst, const double* Asrc, int nv);

@@ -35,7 +35,7 @@ __device__ __forceinline__ double at_time(const double* Cold, const double* Cnew
 __global__ __launch_bounds__(NT) void prolong_ghosts(const ProlongOp* __restrict__ ops, Work w,
                                                      const PatchDev* __restrict__ patches, double* A,
                                                      const double* Cold, const double* Cnew, double alpha,
-                                                     int ndim) {
+                                                     int ndim, int nv) {
   int c;
   const int o = work_item(w, c);
   if (o < 0) return;
@@ -54,8 +54,7 @@ __global__ __launch_bounds__(NT) void prolong_ghosts(const ProlongOp* __restrict
   const int64_t e0 = cell_elem(Q, cq[0], cq[1], cq[2]);
   const int64_t DS = D.S, QS = Q.S;
   const int64_t qs[3] = {1, (int64_t)Q.s[0], (int64_t)Q.s[0] * Q.s[1]};
-#pragma unroll
-  for (int v = 0; v < NVAR; ++v) {
+  for (int v = 0; v < nv; ++v) {
     const int64_t ev = e0 + v * QS;
     const double u0 = at_time(Cold, Cnew, alpha, ev);
     double val = u0;
@@ -71,6 +70,7 @@ __global__ __launch_bounds__(NT) void prolong_ghosts(const ProlongOp* __restrict
 }
 
 // ---------------------------------------------------------------- physical ghosts
+template <int NV>
 __global__ __launch_bounds__(NT) void fill_phys_ghosts(const PhysOp* __restrict__ ops, Work w,
                                                        const PatchDev* __restrict__ patches, double* A) {
   int c;
@@ -81,11 +81,11 @@ __global__ __launch_bounds__(NT) void fill_phys_ghosts(const PhysOp* __restrict_
   int b[3];
   box_cell(op.sz, c, b);
   const int i = op.lo[0] + b[0], j = op.lo[1] + b[1], k = op.lo[2] + b[2];
-  double u[NVAR];
-  load_cons(A, P, i, j, k, u);  // the boundary condition's index map
+  double u[NV];
+  load_cons<NV>(A, P, i, j, k, u);  // the boundary condition's index map
   const int64_t e = cell_elem(P, i, j, k);
 #pragma unroll
-  for (int v = 0; v < NVAR; ++v) A[e + v * P.S] = u[v];
+  for (int v = 0; v < NV; ++v) A[e + v * P.S] = u[v];
 }
 
 // ---------------------------------------------------------------- snapshot
@@ -102,23 +102,23 @@ __global__ __launch_bounds__(NT) void copy_ranges(const int64_t* __restrict__ ra
 // Face flux of coarse patch Q at face f along d (between Q-local cells f-1 and f),
 // at the other coordinates of c, from stage input S: the same reconstruction and
 // Riemann flux, with the same operations, as the stage kernel's face of that patch.
-template <typename RT>
+template <typename RT, int NV>
 __device__ void coarse_face_flux(const double* S, const PatchDev& Q, int d, int f, const int c[3],
-                                 const Consts& C, RT F[NVAR], int& bad) {
+                                 const Consts& C, RT F[NV], int& bad) {
   const FaceConsts<RT> K{(RT)C.gamma, (RT)C.gm1, (RT)C.gg1, C.recon, (RT)C.ch, (RT)C.ch2};
   const RT theta = (RT)C.theta;
-  RT q[4][NVAR];
+  RT q[4][NV];
   for (int m = 0; m < 4; ++m) {
     int x[3] = {c[0], c[1], c[2]};
     x[d] = f - 2 + m;
-    double u[NVAR];
-    load_cons(S, Q, x[0], x[1], x[2], u);
-    bad |= cons2prim<RT>(u, C, q[m]) ? 1 : 0;
+    double u[NV];
+    load_cons<NV>(S, Q, x[0], x[1], x[2], u);
+    bad |= cons2prim<RT, NV>(u, C, q[m]) ? 1 : 0;
   }
-  RT qL[NVAR], qR[NVAR];
+  RT qL[NV], qR[NV];
   const bool th1 = C.theta == 1.0;  // the stage kernel's limiter form (same values)
 #pragma unroll
-  for (int v = 0; v < NVAR; ++v) {
+  for (int v = 0; v < NV; ++v) {
     const RT s1 = th1 ? plm_slope_t<RT, true>(q[0][v], q[1][v], q[2][v], theta)
                       : plm_slope_t<RT, false>(q[0][v], q[1][v], q[2][v], theta);
     const RT s2 = th1 ? plm_slope_t<RT, true>(q[1][v], q[2][v], q[3][v], theta)
@@ -126,15 +126,15 @@ __device__ void coarse_face_flux(const double* S, const PatchDev& Q, int d, int 
     qL[v] = madd(RT(0.5), s1, q[1][v]);
     qR[v] = madd(RT(-0.5), s2, q[2][v]);
   }
-  if (d == 2) riemann_flux<RT, 2>(qL, qR, K, C.flux, F);
-  else riemann_flux_xy<RT>(qL, qR, d == 1, K, C.flux, F);
+  if (d == 2) riemann_flux<RT, 2, NV>(qL, qR, K, C.flux, F);
+  else riemann_flux_xy<RT, NV>(qL, qR, d == 1, K, C.flux, F);
 }
 
 // U_c += s (R_c - <R_f>) / dx_c with R_c = dt_c/2 (F(S1) + F(S2)) the coarse
 // interface flux of the two stages and <R_f> the mean of the fine registers of the
 // 2^(ndim-1) fine faces under it; s = +1 where the interface is the coarse cell's
 // high face (side 0), -1 where it is its low face.
-template <typename RT>
+template <typename RT, int NV>
 __global__ __launch_bounds__(NT) void flux_fix(const FixOp* __restrict__ ops, Work w,
                                                const PatchDev* __restrict__ patches, double* U,
                                                const double* S1, const double* S2, const double* __restrict__ reg,
@@ -152,9 +152,9 @@ __global__ __launch_bounds__(NT) void flux_fix(const FixOp* __restrict__ ops, Wo
   box_cell(op.sz, c, b);
   const int cc[3] = {op.lo[0] + b[0], op.lo[1] + b[1], op.lo[2] + b[2]};
   const int fl = cc[d] + (op.side == 0 ? 1 : 0);
-  RT F1[NVAR], F2[NVAR];
-  coarse_face_flux<RT>(S1, Q, d, fl, cc, C, F1, bad);
-  coarse_face_flux<RT>(S2, Q, d, fl, cc, C, F2, bad);
+  RT F1[NV], F2[NV];
+  coarse_face_flux<RT, NV>(S1, Q, d, fl, cc, C, F1, bad);
+  coarse_face_flux<RT, NV>(S2, Q, d, fl, cc, C, F2, bad);
   // fine faces under this coarse face: 2 per active tangential dimension, summed
   // with dimension (d+2)%3 outer and (d+1)%3 inner; the register of a face is
   // laid out [v][upper tangential dim][lower tangential dim]
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(NT) void flux_fix(const FixOp* __restrict__ ops, Wo
   const int64_t e = cell_elem(Q, cc[0], cc[1], cc[2]);
   const double sgn = op.side == 0 ? 1.0 : -1.0;
 #pragma unroll
-  for (int v = 0; v < NVAR; ++v) {
+  for (int v = 0; v < NV; ++v) {
     double Rf = 0.0;
     for (int yb = 0; yb < nb; ++yb)
       for (int xa = 0; xa < na; ++xa)
@@ -188,7 +188,8 @@ __global__ __launch_bounds__(NT) void flux_fix(const FixOp* __restrict__ ops, Wo
 
 // ---------------------------------------------------------------- restriction
 __global__ __launch_bounds__(NT) void restrict_cells(const RestrictOp* __restrict__ ops, Work w,
-                                                     const PatchDev* __restrict__ patches, double* U, int ndim) {
+                                                     const PatchDev* __restrict__ patches, double* U, int ndim,
+                                                     int nv) {
   int c;
   const int o = work_item(w, c);
   if (o < 0) return;
@@ -203,8 +204,7 @@ __global__ __launch_bounds__(NT) void restrict_cells(const RestrictOp* __restric
   int f0[3] = {0, 0, 0};
   for (int d = 0; d < ndim; ++d) f0[d] = 2 * cc[d] + op.fo[d];
   const int64_t e = cell_elem(Q, cc[0], cc[1], cc[2]);
-#pragma unroll
-  for (int v = 0; v < NVAR; ++v) {
+  for (int v = 0; v < nv; ++v) {
     double acc = 0.0;
     for (int dz = 0; dz < mz; ++dz)
       for (int dy = 0; dy < my; ++dy)
@@ -215,12 +215,14 @@ __global__ __launch_bounds__(NT) void restrict_cells(const RestrictOp* __restric
 
 // ---------------------------------------------------------------- launchers
 hipError_t launch_prolong(hipStream_t s, const ProlongOp* ops, const Work& w, const PatchDev* p, double* A,
-                          const double* Cold, const double* Cnew, double alpha, int ndim) {
-  hipLaunchKernelGGL(prolong_ghosts, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, A, Cold, Cnew, alpha, ndim);
+                          const double* Cold, const double* Cnew, double alpha, int ndim, int nv) {
+  hipLaunchKernelGGL(prolong_ghosts, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, A, Cold, Cnew, alpha, ndim, nv);
   return hipGetLastError();
 }
-hipError_t launch_phys(hipStream_t s, const PhysOp* ops, const Work& w, const PatchDev* p, double* A) {
-  hipLaunchKernelGGL(fill_phys_ghosts, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, A);
+hipError_t launch_phys(hipStream_t s, const PhysOp* ops, const Work& w, const PatchDev* p, double* A, int nv) {
+  if (nv == NVAR_MHD) hipLaunchKernelGGL(fill_phys_ghosts<NVAR_MHD>, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, A);
+  else if (nv == NVAR_GLM) hipLaunchKernelGGL(fill_phys_ghosts<NVAR_GLM>, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, A);
+  else hipLaunchKernelGGL(fill_phys_ghosts<NVAR>, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, A);
   return hipGetLastError();
 }
 hipError_t launch_copy_ranges(hipStream_t s, const int64_t* ranges, int nr, int64_t maxlen, const double* src,
@@ -229,16 +231,26 @@ hipError_t launch_copy_ranges(hipStream_t s, const int64_t* ranges, int nr, int6
   hipLaunchKernelGGL(copy_ranges, dim3(std::max(gx, 1), std::min(nr, 65535)), dim3(NT), 0, s, ranges, nr, src, dst);
   return hipGetLastError();
 }
-hipError_t launch_flux_fix(int mixed, hipStream_t s, const FixOp* ops, const Work& w, const PatchDev* p, double* U,
-                           const double* S1, const double* S2, const double* reg, const double* dtc, const Consts& C,
-                           int* flag) {
-  if (mixed) hipLaunchKernelGGL(flux_fix<float>, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, U, S1, S2, reg, dtc, C, flag);
-  else hipLaunchKernelGGL(flux_fix<double>, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, U, S1, S2, reg, dtc, C, flag);
+template <int NV>
+static void launch_flux_fix_nv(int mixed, hipStream_t s, const FixOp* ops, const Work& w, const PatchDev* p,
+                               double* U, const double* S1, const double* S2, const double* reg, const double* dtc,
+                               const Consts& C, int* flag) {
+  if (mixed)
+    hipLaunchKernelGGL((flux_fix<float, NV>), dim3(w.nblk), dim3(NT), 0, s, ops, w, p, U, S1, S2, reg, dtc, C, flag);
+  else
+    hipLaunchKernelGGL((flux_fix<double, NV>), dim3(w.nblk), dim3(NT), 0, s, ops, w, p, U, S1, S2, reg, dtc, C, flag);
+}
+hipError_t launch_flux_fix(int mixed, int nv, hipStream_t s, const FixOp* ops, const Work& w, const PatchDev* p,
+                           double* U, const double* S1, const double* S2, const double* reg, const double* dtc,
+                           const Consts& C, int* flag) {
+  if (nv == NVAR_MHD) launch_flux_fix_nv<NVAR_MHD>(mixed, s, ops, w, p, U, S1, S2, reg, dtc, C, flag);
+  else if (nv == NVAR_GLM) launch_flux_fix_nv<NVAR_GLM>(mixed, s, ops, w, p, U, S1, S2, reg, dtc, C, flag);
+  else launch_flux_fix_nv<NVAR>(mixed, s, ops, w, p, U, S1, S2, reg, dtc, C, flag);
   return hipGetLastError();
 }
 hipError_t launch_restrict(hipStream_t s, const RestrictOp* ops, const Work& w, const PatchDev* p, double* U,
-                           int ndim) {
-  hipLaunchKernelGGL(restrict_cells, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, U, ndim);
+                           int ndim, int nv) {
+  hipLaunchKernelGGL(restrict_cells, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, U, ndim, nv);
   return hipGetLastError();
 }
 

@@ -437,8 +437,27 @@ def uneven_patches(npatch=4000, seed=30, sizes=(8, 16, 24, 32), ng=3, gamma=5.0 
     return ps, U
 
 
+def _with_fields(rho, vel, pr, gamma, nvar, field, bamp, uniform):
+    """Conserved state of the smooth set-ups: hydro (nvar 5), or with a magnetic field
+    B = B0 + bamp * field() per component, B0 = (0.6, -0.4, 0.3) (nvar 8), and a cleaning
+    field psi = 0.1 * field() (nvar 9).  The draws follow the hydro ones, so the hydro
+    state of a seed is the same for every nvar; a uniform set-up has B = B0, psi = 0."""
+    if nvar == NVAR:
+        return conserved(rho, vel[0], vel[1], vel[2], pr, gamma)
+    B0 = (0.6, -0.4, 0.3)
+    if uniform:
+        B = [np.full(rho.shape, b) for b in B0]
+        psi = np.zeros(rho.shape)
+    else:
+        B = [b + bamp * field() for b in B0]
+        psi = 0.1 * field() if nvar == NVAR_GLM else None
+    if nvar == NVAR_MHD:
+        return conserved_mhd(rho, vel[0], vel[1], vel[2], pr, B[0], B[1], B[2], gamma)
+    return conserved_glm(rho, vel[0], vel[1], vel[2], pr, B[0], B[1], B[2], psi, gamma)
+
+
 def two_level_box(Nc=16, fine_lo=(4, 4, 4), fine_n=(8, 8, 8), ng=3, gamma=5.0 / 3.0, theta=1.0, seed=40,
-                  ndim=3, amp=0.2, vamp=0.4, uniform=False, coarse_split=1):
+                  ndim=3, amp=0.2, vamp=0.4, uniform=False, coarse_split=1, nvar=NVAR, bamp=0.3):
     """A periodic box of Nc^ndim root cells with one level-1 patch (refinement 2).
 
     The fine patch covers root cells [fine_lo, fine_lo + fine_n) (even bounds).
@@ -447,6 +466,7 @@ def two_level_box(Nc=16, fine_lo=(4, 4, 4), fine_n=(8, 8, 8), ng=3, gamma=5.0 / 
     hierarchy is consistent.  Root patches: the box cut into coarse_split^ndim
     patches with EXTERNAL faces (periodic root domain); the fine patch has
     EXTERNAL faces everywhere (ghosts from the root level by prolongation).
+    nvar 8 / 9: MHD / GLM-MHD, B (and psi) smooth fields of the same kind (see _mhd_fields).
     Returns (PatchSet, U, periodic_mask, domain).
     """
     Nf = 2 * Nc
@@ -475,7 +495,7 @@ def two_level_box(Nc=16, fine_lo=(4, 4, 4), fine_n=(8, 8, 8), ng=3, gamma=5.0 / 
         rho = 1.0 + amp * field()
         vel = [vamp * field() if d < ndim else np.zeros(shape_f) for d in range(3)]
         pr = 1.0 + amp * field()
-    Uf = conserved(rho, vel[0], vel[1], vel[2], pr, gamma)
+    Uf = _with_fields(rho, vel, pr, gamma, nvar, field, bamp, uniform)
     # root field: mean of the 2^ndim children
     Uc = Uf
     for ax in range(ndim):
@@ -502,7 +522,8 @@ def two_level_box(Nc=16, fine_lo=(4, 4, 4), fine_n=(8, 8, 8), ng=3, gamma=5.0 / 
     ns.append(fn)
     levels.append(1)
     dx0 = tuple(1.0 / Nc if d < ndim else 1.0 for d in range(3))
-    ps = make_patchset(ndim, ns, ng, [BC_EXTERNAL] * 6, level=levels, lo=los, gamma=gamma, theta=theta, dx0=dx0)
+    ps = make_patchset(ndim, ns, ng, [BC_EXTERNAL] * 6, level=levels, lo=los, gamma=gamma, theta=theta, dx0=dx0,
+                       nvar=nvar)
     U = new_arena(ps)
     for p in range(ps.npatch):
         lo, n = ps.lo[p], ps.n[p]
@@ -514,10 +535,10 @@ def two_level_box(Nc=16, fine_lo=(4, 4, 4), fine_n=(8, 8, 8), ng=3, gamma=5.0 / 
 
 
 def composite_totals(ps, U):
-    """Totals of the 5 conserved variables over the composite grid (cells not covered
+    """Totals of the conserved variables over the composite grid (cells not covered
     by a finer patch), each cell weighted by its volume."""
     nd = ps.ndim
-    tot = np.zeros(5)
+    tot = np.zeros(ps.nvar)
     lo = ps.lo.astype(np.int64)
     hi = lo + ps.n.astype(np.int64)
     for p in range(ps.npatch):
@@ -536,12 +557,12 @@ def composite_totals(ps, U):
                 sl = [slice(int(olo[q, d] - lo[p, d]), int(ohi[q, d] - lo[p, d])) if d < nd else slice(None)
                       for d in range(3)]
                 mask[sl[2], sl[1], sl[0]] = False
-        tot += vol * np.array([math.fsum(a[k][mask].ravel()) for k in range(5)])
+        tot += vol * np.array([math.fsum(a[k][mask].ravel()) for k in range(ps.nvar)])
     return tot
 
 
 def nested_box(Nc=16, boxes=((4, 12), (12, 20)), ng=3, gamma=5.0 / 3.0, theta=1.0, seed=48, ndim=3, amp=0.2,
-               vamp=0.4):
+               vamp=0.4, nvar=NVAR, bamp=0.3):
     """A periodic root box of Nc^ndim cells with a chain of nested refined patches.
 
     boxes[i] = (lo, hi): level i+1 patch covering level-i cells [lo, hi) in every
@@ -570,7 +591,7 @@ def nested_box(Nc=16, boxes=((4, 12), (12, 20)), ng=3, gamma=5.0 / 3.0, theta=1.
     rho = 1.0 + amp * field()
     vel = [vamp * field() if d < ndim else np.zeros(shape_f) for d in range(3)]
     pr = 1.0 + amp * field()
-    fields = [conserved(rho, vel[0], vel[1], vel[2], pr, gamma)]  # finest first
+    fields = [_with_fields(rho, vel, pr, gamma, nvar, field, bamp, False)]  # finest first
     for _ in range(nlev - 1):
         Uc = fields[-1]
         for ax in range(ndim):
@@ -588,7 +609,8 @@ def nested_box(Nc=16, boxes=((4, 12), (12, 20)), ng=3, gamma=5.0 / 3.0, theta=1.
         ns.append([2 * (hi - lo) if d < ndim else 1 for d in range(3)])
         levels.append(i + 1)
     dx0 = tuple(1.0 / Nc if d < ndim else 1.0 for d in range(3))
-    ps = make_patchset(ndim, ns, ng, [BC_EXTERNAL] * 6, level=levels, lo=los, gamma=gamma, theta=theta, dx0=dx0)
+    ps = make_patchset(ndim, ns, ng, [BC_EXTERNAL] * 6, level=levels, lo=los, gamma=gamma, theta=theta, dx0=dx0,
+                       nvar=nvar)
     U = new_arena(ps)
     for p in range(ps.npatch):
         lo, n = ps.lo[p], ps.n[p]

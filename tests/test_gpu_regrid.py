@@ -62,10 +62,12 @@ def test_linear_field_is_prolonged_exactly(env):
         assert np.max(np.abs(kids - par)) <= 1e-14 * max(1.0, np.abs(par).max()), k
 
 
-def test_regrid_copies_old_fine_cells_and_conserves(env):
+@pytest.mark.parametrize("nvar", [5, 8, 9])
+def test_regrid_copies_old_fine_cells_and_conserves(env, nvar):
     torch, A = env
-    log("case regrid two-level")
-    psA, UA, per, dom = W.two_level_box(Nc=16, fine_lo=(4, 6, 4), fine_n=(8, 6, 8), coarse_split=2, seed=51)
+    log(f"case regrid two-level nvar={nvar}")
+    psA, UA, per, dom = W.two_level_box(Nc=16, fine_lo=(4, 6, 4), fine_n=(8, 6, 8), coarse_split=2, seed=51,
+                                        nvar=nvar)
     # the same root patches with a larger fine patch that overlaps the old one
     root = [p for p in range(psA.npatch) if psA.level[p] == 0]
     fine_lo, fine_n = np.array([6, 8, 4]), np.array([12, 10, 12])
@@ -73,8 +75,8 @@ def test_regrid_copies_old_fine_cells_and_conserves(env):
     lo = [list(psA.lo[p]) for p in root] + [list(fine_lo)]
     bc = [list(psA.bc[p]) for p in root] + [[W.BC_EXTERNAL] * 6]
     psB = W.make_patchset(3, n, int(psA.ng[0]), bc, level=[0] * len(root) + [1], lo=lo, gamma=psA.gamma,
-                          dx0=psA.dx0)
-    kw = dict(periodic=per, domain=dom)
+                          dx0=psA.dx0, nvar=nvar)
+    kw = dict(periodic=per, domain=dom, ch=1.0 if nvar == 9 else 0.0)
     UB = _fill(env, psA, UA, psB, kw)
     for i, p in enumerate(root):
         assert np.array_equal(psB.active(UB, i), psA.active(UA, p))
