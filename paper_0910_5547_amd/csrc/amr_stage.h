@@ -66,8 +66,12 @@ void stage_kernel(StageArgs a) {
   constexpr int HMAX = HASY ? (4 * (TX + TY) + TL - 1) / TL : 1;  // halo cells per lane
   // face slots: x faces first, slot row*(nxT+1) + f, then y faces, slot nfx + f*nxT + col
   constexpr int NSLOT = TY * (TX + 1) + (HASY ? YR * TX : 0);
+  // DB: face states double-buffered by plane parity (FP32 hydro on 512-lane tiles, the one
+  // workgroup per CU whose LDS has room): plane k+1's primitives then go to LDS during
+  // plane k's face pass, and two workgroup barriers per plane suffice instead of three
+  constexpr bool DB = WPB == 1 && Fast<RT>::value && NV == NVAR && NTH == 512;
   __shared__ RT sP[WPB][NV][PR][TX + 4];        // primitives of the plane (+ face halo)
-  __shared__ RT sFL[WPB][NV][NSLOT], sFR[WPB][NV][NSLOT];  // face states; sFL then holds the flux
+  __shared__ RT sFL[DB ? 2 : WPB][NV][NSLOT], sFR[DB ? 2 : WPB][NV][NSLOT];  // face states; sFL then the flux
   // conserved state of this lane's cell in planes k and k+1 (3D), for the update:
   // lane-private, kept in LDS rather than registers or a second read (FP32
   // instantiations with workgroup tiles; the others re-read the cell, their LDS
@@ -251,13 +255,8 @@ void stage_kernel(StageArgs a) {
       }
     }
 
-    for (int k = T.z0; k < T.z1; ++k) {
-      // this step's HBM read first: plane k+2 of the column in 3D (consumed by the z
-      // flux after the x-y work), plane k itself in 1D/2D.  Issued by every lane
-      // without a branch, so that nothing between here and the use waits for it.
-      double Vn2[NV];
-      const bool fz2 = load_col_raw(hasz ? k + 2 : k, Vn2);
-      // halo of plane k (prefetched) into LDS, then prefetch the halo of plane k+1
+    // halo of plane k (prefetched) into LDS, then prefetch the halo of plane k+1
+    auto halo_to_lds = [&](int k) {
 #pragma unroll
       for (int s = 0; s < HMAX; ++s) {
         if (tid + s * TL < nhx + nhy) {
@@ -270,11 +269,42 @@ void stage_kernel(StageArgs a) {
           if (k + 1 < T.z1) load_halo(s, k + 1, Hn[s]);
         }
       }
-      // (every lane computes; inactive lanes of ragged tiles hold a copy of an active
-      // column and only skip the shared and global writes: a branch around loads or
-      // their uses would leave loads pending on one path, and the next iteration would
-      // wait for all memory at its first prefetch)
-      {
+    };
+    auto own_to_lds = [&](const RT qc[NV]) {
+      if (act) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sP[buf][v][cy + RO][cx + 2] = qc[v];
+      }
+    };
+    if constexpr (DB) {  // plane z0 into LDS ahead of the plane loop
+      halo_to_lds(T.z0);
+      if (hasz) {
+        own_to_lds(qz);
+      } else {
+        double u[NV];
+        RT qc[NV];
+        load_col(T.z0, u);
+        bad |= cons2prim<RT, NV>(u, C, qc);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sV[T.z0 & 1][v][threadIdx.x] = u[v];
+        own_to_lds(qc);
+      }
+      tile_sync();
+    }
+
+    for (int k = T.z0; k < T.z1; ++k) {
+      const int fb = DB ? (k & 1) : buf;  // face-state buffer of this plane
+      // this step's HBM read first: plane k+2 of the column in 3D (consumed by the z
+      // flux after the x-y work), plane k itself in 1D/2D.  Issued by every lane
+      // without a branch, so that nothing between here and the use waits for it.
+      double Vn2[NV];
+      const bool fz2 = load_col_raw(hasz ? k + 2 : k, Vn2);
+      if constexpr (!DB) {
+        halo_to_lds(k);
+        // (every lane computes; inactive lanes of ragged tiles hold a copy of an active
+        // column and only skip the shared and global writes: a branch around loads or
+        // their uses would leave loads pending on one path, and the next iteration would
+        // wait for all memory at its first prefetch)
         RT qc[NV];
         if (hasz) {
 #pragma unroll
@@ -291,12 +321,9 @@ void stage_kernel(StageArgs a) {
             for (int v = 0; v < NV; ++v) sV[k & 1][v][threadIdx.x] = Vn2[v];
           }
         }
-        if (act) {
-#pragma unroll
-          for (int v = 0; v < NV; ++v) sP[buf][v][cy + RO][cx + 2] = qc[v];
-        }
+        own_to_lds(qc);
+        tile_sync();  // (A) plane primitives ready; previous plane's fluxes consumed
       }
-      tile_sync();  // (A) plane primitives ready; previous plane's fluxes consumed
 
       // (1) slopes, once per cell, as face states
       if (act) {
@@ -305,17 +332,17 @@ void stage_kernel(StageArgs a) {
           const RT* pl = &sP[buf][v][0][0];
           const RT q0 = pl[pc_own];
           const RT sx = plm_slope_t<RT, TH1>(pl[pc_own - 1], q0, pl[pc_own + 1], theta);
-          sFR[buf][v][xs_own] = madd(RT(-0.5), sx, q0);     // right state of its low x face
-          sFL[buf][v][xs_own + 1] = madd(RT(0.5), sx, q0);  // left state of its high x face
+          sFR[fb][v][xs_own] = madd(RT(-0.5), sx, q0);     // right state of its low x face
+          sFL[fb][v][xs_own + 1] = madd(RT(0.5), sx, q0);  // left state of its high x face
           if constexpr (HASY) {
             const RT sy = plm_slope_t<RT, TH1>(pl[pc_own - (TX + 4)], q0, pl[pc_own + (TX + 4)], theta);
-            sFR[buf][v][ys_own] = madd(RT(-0.5), sy, q0);
-            sFL[buf][v][ys_own + nxT] = madd(RT(0.5), sy, q0);
+            sFR[fb][v][ys_own] = madd(RT(-0.5), sy, q0);
+            sFL[fb][v][ys_own + nxT] = madd(RT(0.5), sy, q0);
           }
         }
       }
       if (tid < nhs) {
-        RT* dst = left_h ? &sFL[buf][0][slot_h] : &sFR[buf][0][slot_h];
+        RT* dst = left_h ? &sFL[fb][0][slot_h] : &sFR[fb][0][slot_h];
         const RT hs = left_h ? RT(0.5) : RT(-0.5);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -356,8 +383,8 @@ void stage_kernel(StageArgs a) {
       auto face_at = [&](int slot, RT qL[NV], RT qR[NV]) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          qL[v] = sFL[buf][v][slot];
-          qR[v] = sFR[buf][v][slot];
+          qL[v] = sFL[fb][v][slot];
+          qR[v] = sFR[fb][v][slot];
         }
       };
       if (act) {
@@ -365,7 +392,7 @@ void stage_kernel(StageArgs a) {
         face_at(xs_own, qL, qR);
         riemann_flux<RT, 0, NV>(qL, qR, K, kind, F);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sFL[buf][v][xs_own] = F[v];
+        for (int v = 0; v < NV; ++v) sFL[fb][v][xs_own] = F[v];
         if constexpr (HASY) {
           face_at(ys_own, qL, qR);
           // (the x-frame evaluation, as for every y face: riemann_flux<RT, 1> sums the
@@ -373,7 +400,7 @@ void stage_kernel(StageArgs a) {
           // would differ from the coarse level's recomputed flux in refluxing)
           riemann_flux_xy<RT, NV>(qL, qR, true, K, kind, F);
 #pragma unroll
-          for (int v = 0; v < NV; ++v) sFL[buf][v][ys_own] = F[v];
+          for (int v = 0; v < NV; ++v) sFL[fb][v][ys_own] = F[v];
         }
       }
       if (tid < nfe) {
@@ -381,7 +408,7 @@ void stage_kernel(StageArgs a) {
         face_at(slot_e, qL, qR);
         riemann_flux_xy<RT, NV>(qL, qR, ydir_e, K, kind, F);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sFL[buf][v][slot_e] = F[v];
+        for (int v = 0; v < NV; ++v) sFL[fb][v][slot_e] = F[v];
       }
       // z-face flux F_{k+1/2} of this column from the register queue
       RT Fzp[NV], qn2[NV], sg1[NV];
@@ -397,7 +424,13 @@ void stage_kernel(StageArgs a) {
         }
         riemann_flux<RT, 2, NV>(qL, qR, K, kind, Fzp);
       }
-      tile_sync();  // (C) fluxes ready
+      if constexpr (DB) {  // plane k+1 into LDS: plane k's slope pass is done with sP
+        if (k + 1 < T.z1) {
+          halo_to_lds(k + 1);
+          own_to_lds(qz1);  // (3D: plane loops of 1D/2D tiles have one plane)
+        }
+      }
+      tile_sync();  // (C) fluxes ready (DB: and the next plane's primitives)
       if constexpr (WPB > 1) {
         load_u0();
         load_vc();
@@ -427,7 +460,7 @@ void stage_kernel(StageArgs a) {
         };
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          const double fl = (double)sFL[buf][v][sx], fh = (double)sFL[buf][v][sx + 1];
+          const double fl = (double)sFL[fb][v][sx], fh = (double)sFL[fb][v][sx + 1];
           const double d = fh - fl;
           if constexpr (FAST) L[v] = -d * P.rdx[0];
           else L[v] = 0.0 - d / P.dx[0];
@@ -436,7 +469,7 @@ void stage_kernel(StageArgs a) {
         if (hasy) {
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
-            const double fl = (double)sFL[buf][v][sy], fh = (double)sFL[buf][v][sy + nxT];
+            const double fl = (double)sFL[fb][v][sy], fh = (double)sFL[fb][v][sy + nxT];
             const double d = fh - fl;
             if constexpr (FAST) L[v] = fma(-d, P.rdx[1], L[v]);
             else L[v] = L[v] - d / P.dx[1];
