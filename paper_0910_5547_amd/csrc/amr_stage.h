@@ -66,12 +66,16 @@ void stage_kernel(StageArgs a) {
   constexpr int HMAX = HASY ? (4 * (TX + TY) + TL - 1) / TL : 1;  // halo cells per lane
   // face slots: x faces first, slot row*(nxT+1) + f, then y faces, slot nfx + f*nxT + col
   constexpr int NSLOT = TY * (TX + 1) + (HASY ? YR * TX : 0);
-  // DB: face states double-buffered by plane parity (FP32 hydro on 512-lane tiles, the one
-  // workgroup per CU whose LDS has room): plane k+1's primitives then go to LDS during
-  // plane k's face pass, and two workgroup barriers per plane suffice instead of three
-  constexpr bool DB = WPB == 1 && Fast<RT>::value && NV == NVAR && NTH == 512;
-  __shared__ RT sP[WPB][NV][PR][TX + 4];        // primitives of the plane (+ face halo)
-  __shared__ RT sFL[DB ? 2 : WPB][NV][NSLOT], sFR[DB ? 2 : WPB][NV][NSLOT];  // face states; sFL then the flux
+  // SB (FP32 hydro on 512-lane tiles, one workgroup per CU): one workgroup barrier per
+  // plane instead of three.  Each lane forms both states of its low x and y faces from
+  // the primitive plane itself (the limited slopes of the cells on either side), so no
+  // face states pass through LDS; the primitive plane and the fluxes are double-buffered
+  // by plane parity, and plane k+1's primitives go to LDS during plane k's face pass.
+  constexpr bool SB = WPB == 1 && Fast<RT>::value && NV == NVAR && NTH == 512;
+  constexpr int PB = SB ? 2 : WPB;
+  __shared__ RT sP[PB][NV][PR][TX + 4];  // primitives of the plane (+ face halo)
+  // face states; sFL then holds the flux (SB: the flux only)
+  __shared__ RT sFL[PB][NV][NSLOT], sFR[SB ? 1 : WPB][NV][SB ? 1 : NSLOT];
   // conserved state of this lane's cell in planes k and k+1 (3D), for the update:
   // lane-private, kept in LDS rather than registers or a second read (FP32
   // instantiations with workgroup tiles; the others re-read the cell, their LDS
@@ -244,19 +248,22 @@ void stage_kernel(StageArgs a) {
       }
     }
     const int nfe = nyT + (HASY ? nxT : 0);
-    int slot_e = 0;
+    int slot_e = 0, pc_e = 0, st_e = 1;  // (pc_e, st_e: the face's right cell in the plane, SB)
     bool ydir_e = false;
     if (tid < nfe) {
       if (tid < nyT) {
         slot_e = tid * (nxT + 1) + nxT;
+        pc_e = (tid + RO) * (TX + 4) + nxT + 2;
       } else {
         slot_e = nfx + nyT * nxT + (tid - nyT);
+        pc_e = (nyT + RO) * (TX + 4) + (tid - nyT) + 2;
+        st_e = TX + 4;
         ydir_e = true;
       }
     }
 
     // halo of plane k (prefetched) into LDS, then prefetch the halo of plane k+1
-    auto halo_to_lds = [&](int k) {
+    auto halo_to_lds = [&](int k, int pb) {
 #pragma unroll
       for (int s = 0; s < HMAX; ++s) {
         if (tid + s * TL < nhx + nhy) {
@@ -265,21 +272,21 @@ void stage_kernel(StageArgs a) {
           if (hflip[s] == 2) reflect_flip<NV>(Hn[s], 1);
           bad |= cons2prim<RT, NV>(Hn[s], C, q);
 #pragma unroll
-          for (int v = 0; v < NV; ++v) sP[buf][v][hrow[s] + RO][hcol[s] + 2] = q[v];
+          for (int v = 0; v < NV; ++v) sP[pb][v][hrow[s] + RO][hcol[s] + 2] = q[v];
           if (k + 1 < T.z1) load_halo(s, k + 1, Hn[s]);
         }
       }
     };
-    auto own_to_lds = [&](const RT qc[NV]) {
+    auto own_to_lds = [&](const RT qc[NV], int pb) {
       if (act) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sP[buf][v][cy + RO][cx + 2] = qc[v];
+        for (int v = 0; v < NV; ++v) sP[pb][v][cy + RO][cx + 2] = qc[v];
       }
     };
-    if constexpr (DB) {  // plane z0 into LDS ahead of the plane loop
-      halo_to_lds(T.z0);
+    if constexpr (SB) {  // plane z0 into LDS ahead of the plane loop
+      halo_to_lds(T.z0, T.z0 & 1);
       if (hasz) {
-        own_to_lds(qz);
+        own_to_lds(qz, T.z0 & 1);
       } else {
         double u[NV];
         RT qc[NV];
@@ -287,20 +294,20 @@ void stage_kernel(StageArgs a) {
         bad |= cons2prim<RT, NV>(u, C, qc);
 #pragma unroll
         for (int v = 0; v < NV; ++v) sV[T.z0 & 1][v][threadIdx.x] = u[v];
-        own_to_lds(qc);
+        own_to_lds(qc, T.z0 & 1);
       }
       tile_sync();
     }
 
     for (int k = T.z0; k < T.z1; ++k) {
-      const int fb = DB ? (k & 1) : buf;  // face-state buffer of this plane
+      const int fb = SB ? (k & 1) : buf;  // LDS buffer of this plane
       // this step's HBM read first: plane k+2 of the column in 3D (consumed by the z
       // flux after the x-y work), plane k itself in 1D/2D.  Issued by every lane
       // without a branch, so that nothing between here and the use waits for it.
       double Vn2[NV];
       const bool fz2 = load_col_raw(hasz ? k + 2 : k, Vn2);
-      if constexpr (!DB) {
-        halo_to_lds(k);
+      if constexpr (!SB) {
+        halo_to_lds(k, buf);
         // (every lane computes; inactive lanes of ragged tiles hold a copy of an active
         // column and only skip the shared and global writes: a branch around loads or
         // their uses would leave loads pending on one path, and the next iteration would
@@ -321,38 +328,9 @@ void stage_kernel(StageArgs a) {
             for (int v = 0; v < NV; ++v) sV[k & 1][v][threadIdx.x] = Vn2[v];
           }
         }
-        own_to_lds(qc);
+        own_to_lds(qc, buf);
         tile_sync();  // (A) plane primitives ready; previous plane's fluxes consumed
       }
-
-      // (1) slopes, once per cell, as face states
-      if (act) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          const RT* pl = &sP[buf][v][0][0];
-          const RT q0 = pl[pc_own];
-          const RT sx = plm_slope_t<RT, TH1>(pl[pc_own - 1], q0, pl[pc_own + 1], theta);
-          sFR[fb][v][xs_own] = madd(RT(-0.5), sx, q0);     // right state of its low x face
-          sFL[fb][v][xs_own + 1] = madd(RT(0.5), sx, q0);  // left state of its high x face
-          if constexpr (HASY) {
-            const RT sy = plm_slope_t<RT, TH1>(pl[pc_own - (TX + 4)], q0, pl[pc_own + (TX + 4)], theta);
-            sFR[fb][v][ys_own] = madd(RT(-0.5), sy, q0);
-            sFL[fb][v][ys_own + nxT] = madd(RT(0.5), sy, q0);
-          }
-        }
-      }
-      if (tid < nhs) {
-        RT* dst = left_h ? &sFL[fb][0][slot_h] : &sFR[fb][0][slot_h];
-        const RT hs = left_h ? RT(0.5) : RT(-0.5);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          const RT* pl = &sP[buf][v][0][0];
-          const RT q0 = pl[pc_h];
-          const RT sg = plm_slope_t<RT, TH1>(pl[pc_h - st_h], q0, pl[pc_h + st_h], theta);
-          dst[v * NSLOT] = madd(hs, sg, q0);
-        }
-      }
-      tile_sync();  // (B) face states ready
 
       // the stage input of this cell (from the lane's LDS ring, else re-read) and, in
       // stage 2, U^n: the global loads are issued before the face pass so that it
@@ -374,41 +352,107 @@ void stage_kernel(StageArgs a) {
           for (int v = 0; v < NV; ++v) Vc[v] = a.V[ecell + v * P.S];
         }
       };
+      if constexpr (!SB) {
+        // (1) slopes, once per cell, as face states
+        if (act) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const RT* pl = &sP[fb][v][0][0];
+            const RT q0 = pl[pc_own];
+            const RT sx = plm_slope_t<RT, TH1>(pl[pc_own - 1], q0, pl[pc_own + 1], theta);
+            sFR[fb][v][xs_own] = madd(RT(-0.5), sx, q0);     // right state of its low x face
+            sFL[fb][v][xs_own + 1] = madd(RT(0.5), sx, q0);  // left state of its high x face
+            if constexpr (HASY) {
+              const RT sy = plm_slope_t<RT, TH1>(pl[pc_own - (TX + 4)], q0, pl[pc_own + (TX + 4)], theta);
+              sFR[fb][v][ys_own] = madd(RT(-0.5), sy, q0);
+              sFL[fb][v][ys_own + nxT] = madd(RT(0.5), sy, q0);
+            }
+          }
+        }
+        if (tid < nhs) {
+          RT* dst = left_h ? &sFL[fb][0][slot_h] : &sFR[fb][0][slot_h];
+          const RT hs = left_h ? RT(0.5) : RT(-0.5);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const RT* pl = &sP[fb][v][0][0];
+            const RT q0 = pl[pc_h];
+            const RT sg = plm_slope_t<RT, TH1>(pl[pc_h - st_h], q0, pl[pc_h + st_h], theta);
+            dst[v * NSLOT] = madd(hs, sg, q0);
+          }
+        }
+        tile_sync();  // (B) face states ready
+      }
+
       if constexpr (WPB == 1) {
         load_u0();
         if constexpr (!RING) load_vc();
       }
 
-      // (2) every x- and y-face flux of the block, once, written over its left state
-      auto face_at = [&](int slot, RT qL[NV], RT qR[NV]) {
+      if constexpr (SB) {
+        // (1+2) each lane's low x and low y face, and one face of the tile's high x or y
+        // edge: both states from the cells on either side (the same limited slopes of
+        // the same primitives as the slope pass of the other tilings), then the flux
+        auto face_states = [&](int pc, int st, RT qL[NV], RT qR[NV]) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          qL[v] = sFL[fb][v][slot];
-          qR[v] = sFR[fb][v][slot];
+          for (int v = 0; v < NV; ++v) {
+            const RT* pl = &sP[fb][v][0][0];
+            const RT a0 = pl[pc - 2 * st], a1 = pl[pc - st], a2 = pl[pc], a3 = pl[pc + st];
+            qL[v] = madd(RT(0.5), plm_slope_t<RT, TH1>(a0, a1, a2, theta), a1);
+            qR[v] = madd(RT(-0.5), plm_slope_t<RT, TH1>(a1, a2, a3, theta), a2);
+          }
+        };
+        if (act) {
+          RT qL[NV], qR[NV], F[NV];
+          face_states(pc_own, 1, qL, qR);
+          riemann_flux<RT, 0, NV>(qL, qR, K, kind, F);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) sFL[fb][v][xs_own] = F[v];
+          if constexpr (HASY) {
+            face_states(pc_own, TX + 4, qL, qR);
+            riemann_flux_xy<RT, NV>(qL, qR, true, K, kind, F);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) sFL[fb][v][ys_own] = F[v];
+          }
         }
-      };
-      if (act) {
-        RT qL[NV], qR[NV], F[NV];
-        face_at(xs_own, qL, qR);
-        riemann_flux<RT, 0, NV>(qL, qR, K, kind, F);
+        if (tid < nfe) {
+          RT qL[NV], qR[NV], F[NV];
+          face_states(pc_e, st_e, qL, qR);
+          riemann_flux_xy<RT, NV>(qL, qR, ydir_e, K, kind, F);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sFL[fb][v][xs_own] = F[v];
-        if constexpr (HASY) {
-          face_at(ys_own, qL, qR);
-          // (the x-frame evaluation, as for every y face: riemann_flux<RT, 1> sums the
-          // kinetic energy in another order, and in the mixed path its FP32 rounding
-          // would differ from the coarse level's recomputed flux in refluxing)
-          riemann_flux_xy<RT, NV>(qL, qR, true, K, kind, F);
-#pragma unroll
-          for (int v = 0; v < NV; ++v) sFL[fb][v][ys_own] = F[v];
+          for (int v = 0; v < NV; ++v) sFL[fb][v][slot_e] = F[v];
         }
-      }
-      if (tid < nfe) {
-        RT qL[NV], qR[NV], F[NV];
-        face_at(slot_e, qL, qR);
-        riemann_flux_xy<RT, NV>(qL, qR, ydir_e, K, kind, F);
+      } else {
+        // (2) every x- and y-face flux of the block, once, written over its left state
+        auto face_at = [&](int slot, RT qL[NV], RT qR[NV]) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sFL[fb][v][slot_e] = F[v];
+          for (int v = 0; v < NV; ++v) {
+            qL[v] = sFL[fb][v][slot];
+            qR[v] = sFR[fb][v][slot];
+          }
+        };
+        if (act) {
+          RT qL[NV], qR[NV], F[NV];
+          face_at(xs_own, qL, qR);
+          riemann_flux<RT, 0, NV>(qL, qR, K, kind, F);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) sFL[fb][v][xs_own] = F[v];
+          if constexpr (HASY) {
+            face_at(ys_own, qL, qR);
+            // (the x-frame evaluation, as for every y face: riemann_flux<RT, 1> sums the
+            // kinetic energy in another order, and in the mixed path its FP32 rounding
+            // would differ from the coarse level's recomputed flux in refluxing)
+            riemann_flux_xy<RT, NV>(qL, qR, true, K, kind, F);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) sFL[fb][v][ys_own] = F[v];
+          }
+        }
+        if (tid < nfe) {
+          RT qL[NV], qR[NV], F[NV];
+          face_at(slot_e, qL, qR);
+          riemann_flux_xy<RT, NV>(qL, qR, ydir_e, K, kind, F);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) sFL[fb][v][slot_e] = F[v];
+        }
       }
       // z-face flux F_{k+1/2} of this column from the register queue
       RT Fzp[NV], qn2[NV], sg1[NV];
@@ -424,13 +468,13 @@ void stage_kernel(StageArgs a) {
         }
         riemann_flux<RT, 2, NV>(qL, qR, K, kind, Fzp);
       }
-      if constexpr (DB) {  // plane k+1 into LDS: plane k's slope pass is done with sP
+      if constexpr (SB) {  // plane k+1 into the other buffer (3D: 1D/2D tiles have one plane)
         if (k + 1 < T.z1) {
-          halo_to_lds(k + 1);
-          own_to_lds(qz1);  // (3D: plane loops of 1D/2D tiles have one plane)
+          halo_to_lds(k + 1, (k + 1) & 1);
+          own_to_lds(qz1, (k + 1) & 1);
         }
       }
-      tile_sync();  // (C) fluxes ready (DB: and the next plane's primitives)
+      tile_sync();  // (C) fluxes ready (SB: and the next plane's primitives)
       if constexpr (WPB > 1) {
         load_u0();
         load_vc();
