@@ -192,9 +192,9 @@ int default_shape(const amr_table* t) {
     return cols / lanes;
   };
   const double u1 = lane_use(1), us = lane_use(SHAPE_SMALL);
-  // (MHD: 32 x 8, whose two workgroups per CU beat one 512-thread workgroup of the
-  // eight-variable 32 x 16 tile)
-  if (t->ph.ndim == 3 && t->ph.nvar == NVAR && lane_use(5) >= 0.9) return 5;
+  // 32 x 16 where those tiles are nearly full (one barrier per plane; for MHD only in
+  // mixed precision, the FP64 eight-variable tile not fitting in LDS)
+  if (t->ph.ndim == 3 && (t->ph.nvar == NVAR || t->ph.precision == AMR_PREC_MIXED) && lane_use(5) >= 0.9) return 5;
   return (u1 < 0.5 && us > u1) ? SHAPE_SMALL : 1;
 }
 

@@ -18,7 +18,11 @@
 //     two x and two y fluxes.  The two cells sharing a face use the same bits,
 //     so the flux difference telescopes and totals are conserved to round-off
 //     in both precisions.  The z-face flux of each column is computed between
-//     (2) and (3), overlapping with the other waves' face work;
+//     (2) and (3), overlapping with the other waves' face work.  On 32 x 16
+//     tiles (one workgroup per CU, where every barrier drains the CU) (1) and (2)
+//     are one pass: the lane of a face forms both its states from the primitive
+//     plane (the same slopes, evaluated once per face side), and with the plane
+//     and the fluxes double-buffered one barrier per plane remains;
 //   * L(U) is accumulated in FP64 in the order x, y, z (MOL equation), and the
 //     TVD-RK2 stage combine is applied in FP64 before one store per variable.
 // Stage 2 writes U^{n+1} over U^n in place: U^n is only read at the cell being
@@ -66,12 +70,14 @@ void stage_kernel(StageArgs a) {
   constexpr int HMAX = HASY ? (4 * (TX + TY) + TL - 1) / TL : 1;  // halo cells per lane
   // face slots: x faces first, slot row*(nxT+1) + f, then y faces, slot nfx + f*nxT + col
   constexpr int NSLOT = TY * (TX + 1) + (HASY ? YR * TX : 0);
-  // SB (FP32 hydro on 512-lane tiles, one workgroup per CU): one workgroup barrier per
-  // plane instead of three.  Each lane forms both states of its low x and y faces from
-  // the primitive plane itself (the limited slopes of the cells on either side), so no
-  // face states pass through LDS; the primitive plane and the fluxes are double-buffered
-  // by plane parity, and plane k+1's primitives go to LDS during plane k's face pass.
-  constexpr bool SB = WPB == 1 && Fast<RT>::value && NV == NVAR && NTH == 512;
+  // SB (512-lane tiles, one workgroup per CU: FP32 reconstruction, and FP64 hydro in
+  // stage 1, its stage 2 being short of registers for it): one workgroup barrier per
+  // plane instead of three.
+  // Each lane forms both states of its low x and y faces from the primitive plane itself
+  // (the limited slopes of the cells on either side), so no face states pass through LDS;
+  // the primitive plane and the fluxes are double-buffered by plane parity, and plane
+  // k+1's primitives go to LDS during plane k's face pass.
+  constexpr bool SB = WPB == 1 && NTH == 512 && (Fast<RT>::value || (NV == NVAR && STAGE == 1));
   constexpr int PB = SB ? 2 : WPB;
   __shared__ RT sP[PB][NV][PR][TX + 4];  // primitives of the plane (+ face halo)
   // face states; sFL then holds the flux (SB: the flux only)
@@ -292,8 +298,10 @@ void stage_kernel(StageArgs a) {
         RT qc[NV];
         load_col(T.z0, u);
         bad |= cons2prim<RT, NV>(u, C, qc);
+        if constexpr (RING) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sV[T.z0 & 1][v][threadIdx.x] = u[v];
+          for (int v = 0; v < NV; ++v) sV[T.z0 & 1][v][threadIdx.x] = u[v];
+        }
         own_to_lds(qc, T.z0 & 1);
       }
       tile_sync();
