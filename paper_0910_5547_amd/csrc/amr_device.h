@@ -358,13 +358,12 @@ __device__ __forceinline__ double cell_speed(const double u[NV], const Consts& c
 // Three-argument minmod of Sec. 4:
 //   0.25 (sgn a + sgn b) |sgn a + sgn c| min(|a|,|b|,|c|)
 // = sgn(a) max(0, min(|a|, sgn(a) b, sgn(a) c)): equal to the printed form for
-// every input (up to the sign of a zero result), evaluated with sign-bit
-// arithmetic, one min3 and one max.
+// every input (up to the sign of a zero result).  FP32: the two-argument minmod is
+// the median of (a, b, 0) - the smaller magnitude when a and b share a sign, else
+// 0 - one v_med3_f32, and minmod(a, b, c) = minmod(minmod(a, b), c).  FP64 (no
+// median instruction): sign-bit arithmetic, one min3 and one max.
 __device__ __forceinline__ float minmod3(float a, float b, float c) {
-  const unsigned sa = __float_as_uint(a) & 0x80000000u;
-  const float bb = __uint_as_float(__float_as_uint(b) ^ sa), cc = __uint_as_float(__float_as_uint(c) ^ sa);
-  const float m = fmaxf(fminf(fabsf(a), fminf(bb, cc)), 0.0f);
-  return __uint_as_float(__float_as_uint(m) | sa);
+  return __builtin_amdgcn_fmed3f(__builtin_amdgcn_fmed3f(a, b, 0.0f), c, 0.0f);
 }
 __device__ __forceinline__ double minmod3(double a, double b, double c) {
   const unsigned long long sa = (unsigned long long)__double_as_longlong(a) & 0x8000000000000000ull;
@@ -389,12 +388,9 @@ __device__ __forceinline__ RT plm_slope(RT qm, RT q0, RT qp, RT theta) {
   return minmod3(theta * (q0 - qm), theta * (qp - q0), (qp - qm) * RT(0.5));
 }
 
-// Two-argument minmod in the same sign-bit form: sgn(a) max(0, min(|a|, sgn(a) b)).
-__device__ __forceinline__ float minmod_ab(float a, float b) {
-  const unsigned sa = __float_as_uint(a) & 0x80000000u;
-  const float m = fmaxf(fminf(fabsf(a), __uint_as_float(__float_as_uint(b) ^ sa)), 0.0f);
-  return __uint_as_float(__float_as_uint(m) | sa);
-}
+// Two-argument minmod: FP32 the median of (a, b, 0); FP64 in the sign-bit form
+// sgn(a) max(0, min(|a|, sgn(a) b)).
+__device__ __forceinline__ float minmod_ab(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
 __device__ __forceinline__ double minmod_ab(double a, double b) {
   const unsigned long long sa = (unsigned long long)__double_as_longlong(a) & 0x8000000000000000ull;
   const double bb = __longlong_as_double((long long)((unsigned long long)__double_as_longlong(b) ^ sa));
@@ -406,7 +402,7 @@ __device__ __forceinline__ double minmod_ab(double a, double b) {
 // theta are then exact, and when the one-sided differences a, b agree in sign the
 // centred argument fl(fl(a + b)/2) is never below min(|a|, |b|) (rounding is
 // monotone, halving exact), so the three-argument minmod returns the same value
-// as the two-argument one, which skips three operations per variable.
+// as the two-argument one, which skips the centred difference and a minmod per variable.
 template <typename RT, bool TH1>
 __device__ __forceinline__ RT plm_slope_t(RT qm, RT q0, RT qp, RT theta) {
   if constexpr (TH1) return minmod_ab(q0 - qm, qp - q0);
