@@ -687,7 +687,8 @@ def sedov_uniform(N=64, t0=0.01, E=1.0, gamma=5.0 / 3.0, rho1=1.0, p1=1e-5, nvar
     """Point explosion on a uniform N^3 grid of the cube [-1/2, 1/2]^3 (one patch, outflow faces),
     initialised with the self-similar profile at time t0 (blast energy E at the centre), each cell
     the mean of sub^3 samples.  nvar 8 makes an ideal-MHD set-up with the uniform field (B0, 0, 0)
-    (the uniform-grid MHD blast of the paper's MHD section); B0 = 0 keeps the hydro solution.
+    (the uniform-grid MHD blast of the paper's MHD section), nvar 9 the same with psi = 0; B0 = 0
+    keeps the hydro solution.
     Returns (PatchSet, U, SedovSolution)."""
     sol = SedovSolution(gamma)
     ps = make_patchset(3, [[N, N, N]], ng, [BC_OUTFLOW] * 6, gamma=gamma, dx0=(1.0 / N,) * 3, nvar=nvar)
@@ -712,9 +713,11 @@ def sedov_uniform(N=64, t0=0.01, E=1.0, gamma=5.0 / 3.0, rho1=1.0, p1=1e-5, nvar
     U = new_arena(ps)
     a = ps.active(U, 0)
     a[0], a[1], a[2], a[3], a[4] = rho, mom[0], mom[1], mom[2], En
-    if nvar == NVAR_MHD:
+    if nvar >= NVAR_MHD:
         a[4] += 0.5 * B0 * B0
         a[5], a[6], a[7] = B0, 0.0, 0.0
+    if nvar == NVAR_GLM:
+        a[8] = 0.0
     return ps, U, sol
 
 

@@ -63,3 +63,32 @@ def test_blast_with_a_dynamic_hierarchy(env):
     log(f"root shock radius {Rm:.4f} exact {R:.4f}")
     assert abs(Rm - R) <= 1.0 / N
     dh.close()
+
+
+@pytest.mark.parametrize("nvar,ch", [(8, 0.0), (9, 3.0)])
+def test_magnetised_blast_with_a_dynamic_hierarchy(env, nvar, ch):
+    """The MHD blast (weak uniform field, the paper's MHD Sedov set-up) on the same dynamic
+    hierarchy: refined around the shock, every conserved total (B and psi included) kept
+    through steps and rebuilds, the shock radius that of the hydro blast within a root cell."""
+    torch, A, D = env
+    N = 32
+    ps, U, sol = W.sedov_uniform(N, t0=0.01, nvar=nvar, B0=0.01)
+    tot0 = W.composite_totals(ps, U)
+    dh = D.DynamicHierarchy(ps, U, max_level=2, eps=0.3, every=2, t0=0.01, ch=ch, **W.SEDOV_FLOORS)
+    dh.advance(0.014)
+    ps2, U2 = dh.host_state()
+    levels = np.bincount(ps2.level)
+    log(f"nvar {nvar}: steps {dh.steps}, rebuilds {dh.rebuilds}, patches per level {levels.tolist()}")
+    assert dh.rebuilds >= 2 and len(levels) == 3 and levels[2] > 0
+    tot = W.composite_totals(ps2, U2)
+    scale = np.maximum(W.composite_totals(ps2, np.abs(U2)), W.composite_totals(ps, np.abs(U)))
+    for k in range(nvar):
+        assert abs(tot[k] - tot0[k]) <= 1e-12 * scale[k], (k, tot[k] - tot0[k])
+    root = W.make_patchset(3, [[N] * 3], 2, [W.BC_OUTFLOW] * 6, dx0=ps.dx0, nvar=nvar)
+    Ur = W.new_arena(root)
+    Ur[...] = 0.0
+    root.active(Ur, 0)[...] = ps2.active(U2, 0)
+    R, Rm = sol.radius(1.0, dh.t), W.shock_radius(root, Ur)
+    log(f"nvar {nvar}: root shock radius {Rm:.4f} exact (hydro) {R:.4f}")
+    assert abs(Rm - R) <= 1.0 / N
+    dh.close()
