@@ -205,10 +205,18 @@ def test_mixed_brio_wu(env):
     assert l1 <= 1e-5
 
 
-def test_every_mhd_tiling_gives_identical_bits(env):
-    """Face fluxes are computed once per face by the same code in every tile shape and z-slab."""
+@pytest.mark.parametrize("ndim", [3, 2])
+def test_every_mhd_tiling_gives_identical_bits(env, ndim):
+    """Face fluxes are computed once per face by the same code in every tile shape and z-slab
+    (2D included: the single-barrier pass of the 32 x 16 tiles has its own 2D branch)."""
     torch, A, O = env
-    ps, U = _random_mhd([[40, 21, 18], [16, 16, 16]], [W.BC_PERIODIC] * 6, seed=45)
+    if ndim == 3:
+        ps, U = _random_mhd([[40, 21, 18], [16, 16, 16]], [W.BC_PERIODIC] * 6, seed=45)
+    else:
+        ps = W.make_patchset(2, [[45, 29, 1], [33, 17, 1]], 2, [W.BC_PERIODIC, W.BC_PERIODIC, W.BC_REFLECT,
+                                                               W.BC_OUTFLOW, 0, 0], gamma=5 / 3,
+                             dx0=(0.02, 0.03, 1.0), nvar=8)
+        U = W.random_state(ps, 46, shocks=1.0)
     for prec in (0, 1):
         ref = None
         T = A.Table(ps, precision=prec, exec_form=1)

@@ -132,6 +132,32 @@ def test_two_dimensional(env):
     compare(ps, Ug, Uo, bitwise=True, what="2d")
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_two_dimensional_every_tiling(env, prec):
+    """2D tables on every tile shape (the 32 x 16 tiles take the single-barrier face pass,
+    whose 2D branch stages the plane ahead of its loop): FP64 bitwise against the oracle,
+    mixed identical across shapes."""
+    torch, A, O = env
+    ps = W.make_patchset(2, [[70, 45, 1], [33, 17, 1]], 2, [W.BC_PERIODIC] * 2 + [W.BC_REFLECT] * 2 + [0, 0],
+                         gamma=5 / 3, dx0=(1 / 70, 1 / 45, 1.0))
+    U = W.random_state(ps, 9, shocks=1.0)
+    T = A.Table(ps, precision=prec)
+    shapes = [sh for sh in range(1, A.amr_table_num_tilings(T.h)) if A.lib().amr_table_set_tiling(T.h, sh, 0) == 0]
+    T.close()
+    assert 5 in shapes
+    ref = None
+    for sh in shapes:
+        log(f"case 2d tiling prec={prec} shape={sh}")
+        Ug, Uo = run_pair(env, ps, U, 3, prec=prec, tiling=(sh, 0), check_dt=prec == 0)
+        if prec == 0:
+            compare(ps, Ug, Uo, bitwise=True, what=f"2d shape {sh}")
+        out = active_all(ps, Ug)
+        if ref is None:
+            ref = out
+        else:
+            assert np.array_equal(out, ref), sh
+
+
 @pytest.mark.parametrize("theta", [0.0, 0.5, 2.0])
 def test_limiter_theta(env, theta):
     """theta != 1: the three-argument minmod path of the stage kernel (theta = 1 compiles to
