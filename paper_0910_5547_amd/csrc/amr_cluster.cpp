@@ -36,7 +36,8 @@ extern "C" amr_status amr_cluster_flags(const amr_patch_desc* patches, int32_t n
     return AMR_EINVAL;
   int N[3], bd[3];
   for (int d = 0; d < 3; ++d) {
-    if (d < ndim && domain[d] < 1) return AMR_EINVAL;
+    // (level-l extents must fit an int32 index)
+    if (d < ndim && (domain[d] < 1 || level > 30 || ((int64_t)domain[d] << level) > INT32_MAX)) return AMR_EINVAL;
     N[d] = d < ndim ? domain[d] << level : 1;
     bd[d] = d < ndim ? brick : 1;
   }

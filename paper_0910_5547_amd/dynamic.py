@@ -83,8 +83,14 @@ class DynamicHierarchy:
             boxes.append(b)
             ps = self._patchset(boxes)
             T = A.Table(ps, **self.kw)
-            U = torch.zeros(int(A.amr_table_arena_elems(T.h)), dtype=torch.float64, device=cur_U.device)
-            A.amr_regrid_fill(old_T.h, old_U, T.h, U)
+            try:
+                U = torch.zeros(int(A.amr_table_arena_elems(T.h)), dtype=torch.float64, device=cur_U.device)
+                A.amr_regrid_fill(old_T.h, old_U, T.h, U)
+            except BaseException:
+                T.close()
+                if cur_T is not old_T:
+                    cur_T.close()
+                raise
             if cur_T is not old_T:
                 cur_T.close()
             cur_T, cur_U, cur_ps = T, U, ps
@@ -93,8 +99,12 @@ class DynamicHierarchy:
                 return
             ps = self._patchset([])
             T = A.Table(ps, **self.kw)
-            U = torch.zeros(int(A.amr_table_arena_elems(T.h)), dtype=torch.float64, device=old_U.device)
-            A.amr_regrid_fill(old_T.h, old_U, T.h, U)
+            try:
+                U = torch.zeros(int(A.amr_table_arena_elems(T.h)), dtype=torch.float64, device=old_U.device)
+                A.amr_regrid_fill(old_T.h, old_U, T.h, U)
+            except BaseException:
+                T.close()
+                raise
             cur_T, cur_U, cur_ps = T, U, ps
         old_T.close()
         self.T, self.U, self.ps = cur_T, cur_U, cur_ps

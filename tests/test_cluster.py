@@ -106,3 +106,18 @@ def test_bad_arguments(amr):
     st = amr.lib().amr_cluster_flags(descs, 1, 3, dom, 0, f.ctypes.data_as(C.POINTER(C.c_uint8)), 8, 32,
                                      out.ctypes.data_as(C.POINTER(C.c_int32)), 10, C.byref(n))
     assert st == amr.AMR_EINVAL
+
+
+def test_level_whose_extent_overflows_is_rejected(amr):
+    """A level whose index extent (domain << level) exceeds an int32 is an invalid argument."""
+    import ctypes as C
+    ps = W.make_patchset(3, [[16, 16, 16]], 2, [W.BC_OUTFLOW] * 6)
+    descs = amr.descriptors(ps)
+    out = np.zeros(60, np.int32)
+    n = C.c_int32(0)
+    dom = (C.c_int32 * 3)(16, 16, 16)
+    f = np.zeros(16 ** 3, np.uint8)
+    for level in (28, 31):
+        st = amr.lib().amr_cluster_flags(descs, 1, 3, dom, level, f.ctypes.data_as(C.POINTER(C.c_uint8)), 8, 32,
+                                         out.ctypes.data_as(C.POINTER(C.c_int32)), 10, C.byref(n))
+        assert st == amr.AMR_EINVAL, level
