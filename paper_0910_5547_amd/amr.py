@@ -123,6 +123,13 @@ def _ptr(t):
     return C.c_void_p(int(t))
 
 
+def _arena(h, U):
+    """_ptr of an arena tensor, checked to hold the table's arena (U indexes up to it)."""
+    if isinstance(U, torch.Tensor) and U.numel() < int(lib().amr_table_arena_elems(h)):
+        raise ValueError("the arena tensor is smaller than the table's arena (amr_table_arena_elems)")
+    return _ptr(U)
+
+
 def descriptors(ps):
     """amr_patch_desc array of a :class:`paper_0910_5547_amd.workloads.PatchSet`."""
     arr = (amr_patch_desc * ps.npatch)()
@@ -174,22 +181,22 @@ def amr_table_arena_elems(h):
 def amr_cfl_dt(h, U, cfl, level, dt_dev, host=False, stream=None):
     """dt into dt_dev; with host=True also returns it (synchronising)."""
     out = C.c_double(0.0)
-    _check(lib().amr_cfl_dt(h, _ptr(U), float(cfl), int(level), _ptr(dt_dev), C.byref(out) if host else None,
+    _check(lib().amr_cfl_dt(h, _arena(h, U), float(cfl), int(level), _ptr(dt_dev), C.byref(out) if host else None,
                             _stream(stream)), "amr_cfl_dt")
     return out.value if host else None
 
 
 def amr_hydro_rk2_step(h, U, dt_dev, level=-1, flags=0, stream=None):
-    return _check(lib().amr_hydro_rk2_step(h, _ptr(U), _ptr(dt_dev), int(level), int(flags), _stream(stream)),
+    return _check(lib().amr_hydro_rk2_step(h, _arena(h, U), _ptr(dt_dev), int(level), int(flags), _stream(stream)),
                   "amr_hydro_rk2_step")
 
 
 def amr_flux_correct(h, U, coarse_level, stream=None):
-    return _check(lib().amr_flux_correct(h, _ptr(U), int(coarse_level), _stream(stream)), "amr_flux_correct")
+    return _check(lib().amr_flux_correct(h, _arena(h, U), int(coarse_level), _stream(stream)), "amr_flux_correct")
 
 
 def amr_hydro_advance(h, U, dt0_dev, flags=0, stream=None):
-    return _check(lib().amr_hydro_advance(h, _ptr(U), _ptr(dt0_dev), int(flags), _stream(stream)),
+    return _check(lib().amr_hydro_advance(h, _arena(h, U), _ptr(dt0_dev), int(flags), _stream(stream)),
                   "amr_hydro_advance")
 
 
@@ -219,7 +226,7 @@ def amr_table_tiling_shape(h, tid):
 
 def amr_autotune(h, U, dt_dev, level=-1, reps=3, stream=None):
     ms = C.c_float(0.0)
-    _check(lib().amr_autotune(h, _ptr(U), _ptr(dt_dev), int(level), int(reps), _stream(stream), C.byref(ms)),
+    _check(lib().amr_autotune(h, _arena(h, U), _ptr(dt_dev), int(level), int(reps), _stream(stream), C.byref(ms)),
            "amr_autotune")
     return ms.value
 
@@ -233,17 +240,21 @@ def amr_flag_cells(h, U, level, eps, flags, stream=None):
     if not (flags.dtype == torch.uint8 and flags.is_cuda and flags.is_contiguous()
             and flags.numel() >= amr_table_cells(h, level)):
         raise ValueError("flags must be a contiguous uint8 GPU tensor of amr_table_cells(level) bytes")
-    _check(lib().amr_flag_cells(h, _ptr(U), level, float(eps), C.c_void_p(flags.data_ptr()), _stream(stream)),
+    _check(lib().amr_flag_cells(h, _arena(h, U), level, float(eps), C.c_void_p(flags.data_ptr()), _stream(stream)),
            "amr_flag_cells")
 
 
 def amr_regrid_fill(h_old, U_old, h_new, U_new, stream=None):
-    _check(lib().amr_regrid_fill(h_old, _ptr(U_old), h_new, _ptr(U_new), _stream(stream)), "amr_regrid_fill")
+    _check(lib().amr_regrid_fill(h_old, _arena(h_old, U_old), h_new, _arena(h_new, U_new), _stream(stream)),
+           "amr_regrid_fill")
 
 
 def amr_cluster_flags(descs, ndim, domain, level, flags, brick=8, block=32):
     """Boxes (lo[3], n[3]) of level+1 clustered from the host uint8 flags of `level` (host work)."""
     flags = np.ascontiguousarray(flags, np.uint8)
+    need = sum(int(d.n[0]) * int(d.n[1]) * int(d.n[2]) for d in descs if d.level == level)
+    if flags.size < need:
+        raise ValueError(f"flags hold {flags.size} cells, the level-{level} patches {need}")
     dom = (C.c_int32 * 3)(*[int(x) for x in domain])
     n = C.c_int32(0)
     cap = 1024

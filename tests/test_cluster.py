@@ -121,3 +121,10 @@ def test_level_whose_extent_overflows_is_rejected(amr):
         st = amr.lib().amr_cluster_flags(descs, 1, 3, dom, level, f.ctypes.data_as(C.POINTER(C.c_uint8)), 8, 32,
                                          out.ctypes.data_as(C.POINTER(C.c_int32)), 10, C.byref(n))
         assert st == amr.AMR_EINVAL, level
+
+
+def test_short_flags_are_rejected_by_the_binding(amr):
+    """The binding checks the host flags against the level's cell count before the library reads them."""
+    ps = W.make_patchset(3, [[16, 16, 16]], 2, [W.BC_OUTFLOW] * 6)
+    with pytest.raises(ValueError):
+        amr.amr_cluster_flags(amr.descriptors(ps), 3, (16, 16, 16), 0, np.zeros(16 ** 3 - 1, np.uint8))
