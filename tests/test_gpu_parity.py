@@ -158,6 +158,46 @@ def test_two_dimensional_every_tiling(env, prec):
             assert np.array_equal(out, ref), sh
 
 
+@pytest.mark.parametrize("prec,shape", [(0, None), (0, 5), (1, 5)])
+def test_patch_stored_beyond_2_31_elements(env, prec, shape):
+    """A patch whose storage starts past element 2^31 of the arena (17 GB of FP64): every index
+    of the stage, CFL and tile code is 64-bit.  FP64 bitwise against the oracle on a compact copy of
+    the same patches; mixed within 1e-5."""
+    import dataclasses
+    torch, A, O = env
+    ps = W.make_patchset(3, [[24, 20, 18], [20, 16, 12]], 2, [W.BC_PERIODIC] * 6, gamma=5 / 3,
+                         dx0=(0.04, 0.05, 0.055))
+    U = W.random_state(ps, 11, shocks=1.0)
+    far = (2 ** 31 + 4096) // 64 * 64
+    size1 = int(ps.arena - ps.offset[1])
+    big = dataclasses.replace(ps, offset=np.array([0, far], np.int64), arena=far + size1)
+    log(f"case far patch prec={prec} shape={shape} arena {big.arena}")
+    T = A.Table(big, precision=prec)
+    if shape is not None:
+        assert A.lib().amr_table_set_tiling(T.h, shape, 0) == A.AMR_OK
+    Ud = torch.empty(T.arena, dtype=torch.float64, device="cuda")
+    Ud[:int(ps.offset[1])] = torch.from_numpy(U[:int(ps.offset[1])]).cuda()
+    Ud[far:far + size1] = torch.from_numpy(U[int(ps.offset[1]):]).cuda()
+    o = O.Oracle(ps)
+    Uo = U.copy()
+    for s in range(3):
+        dt = T.cfl_dt(Ud, 0.8)
+        if prec == 0:
+            assert dt == o.cfl_dt(Uo, 0.8), s
+        T.step(Ud)
+        assert o.rk2_step(Uo, dt) == 0
+    torch.cuda.synchronize()
+    assert T.status() == A.AMR_OK
+    Ug = np.concatenate([Ud[:int(ps.offset[1])].cpu().numpy(), Ud[far:far + size1].cpu().numpy()])
+    T.close()
+    del Ud
+    torch.cuda.empty_cache()
+    if prec == 0:
+        compare(ps, Ug, Uo, bitwise=True, what=f"far patch shape {shape}")
+    else:
+        assert l1_rel(active_all(ps, Ug), active_all(ps, Uo)) <= 1e-5
+
+
 @pytest.mark.parametrize("theta", [0.0, 0.5, 2.0])
 def test_limiter_theta(env, theta):
     """theta != 1: the three-argument minmod path of the stage kernel (theta = 1 compiles to
