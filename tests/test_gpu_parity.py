@@ -158,6 +158,26 @@ def test_two_dimensional_every_tiling(env, prec):
             assert np.array_equal(out, ref), sh
 
 
+@pytest.mark.parametrize("shape", [None, 1, 4, 5])
+@pytest.mark.parametrize("bcs", [
+    [W.BC_OUTFLOW] * 6,
+    [W.BC_REFLECT, W.BC_OUTFLOW, W.BC_PERIODIC, W.BC_PERIODIC, W.BC_OUTFLOW, W.BC_REFLECT],
+])
+def test_smallest_patches(env, bcs, shape):
+    """The smallest patches validation admits (n = ng = 2 in an active dimension) and near-minimal
+    ragged ones, where almost every lane of a tile is idle: FP64 bitwise against the oracle in
+    each tiling, the mixed path within 1e-5."""
+    log(f"case smallest patches bcs={bcs} shape={shape}")
+    ps = W.make_patchset(3, [[2, 2, 2], [2, 3, 4], [5, 2, 2], [3, 7, 2]], 2, bcs, gamma=5 / 3,
+                         dx0=(0.05, 0.04, 0.06))
+    U = W.random_state(ps, 12, shocks=1.0)
+    tiling = None if shape is None else (shape, 0)
+    Ug, Uo = run_pair(env, ps, U, 4, tiling=tiling)
+    compare(ps, Ug, Uo, bitwise=True, what=f"smallest shape {shape}")
+    Ug, Uo = run_pair(env, ps, U, 4, prec=1, tiling=tiling, check_dt=False)
+    assert l1_rel(active_all(ps, Ug), active_all(ps, Uo)) <= 1e-5
+
+
 @pytest.mark.parametrize("prec,shape", [(0, None), (0, 5), (1, 5)])
 def test_patch_stored_beyond_2_31_elements(env, prec, shape):
     """A patch whose storage starts past element 2^31 of the arena (17 GB of FP64): every index
