@@ -341,8 +341,8 @@ def main():
         print(json.dumps(e, indent=1))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(multi-GPU sharding of the patch table is a design note, not built)", file=sys.stderr)
+        print(f"bench.py: the update runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding the patch table over several GPUs is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch

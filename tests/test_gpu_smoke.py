@@ -1,4 +1,4 @@
-"""The round-end smoke check (a tiny batched step in both precisions against the
+"""The smoke check of __graft_entry__ (a tiny batched step in both precisions against the
 oracle) run as a GPU test, so that the suite sees what the smoke entry point sees."""
 import pytest
 
