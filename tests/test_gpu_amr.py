@@ -172,3 +172,41 @@ def test_sedov_full_hierarchy_conserves_and_mixed_tracks_fp64(env):
     l1 = l1_rel(active_all(ps, out[1]), active_all(ps, out[0]))
     log(f"sedov mixed vs fp64 L1(rho) = {l1:.2e}")
     assert l1 <= 1e-5
+
+
+@pytest.mark.parametrize("exe,prec", [(1, 0), (0, 0), (1, 1)])
+@pytest.mark.parametrize("ndim,nlev", [(1, 3), (3, 2), (3, 3)])
+def test_subcycled_ramp_exact_on_gpu(env, ndim, nlev, exe, prec):
+    """The advected linear ramp on a subcycled hierarchy (the oracle's time-schedule pin):
+    the GPU's refined cells reproduce the exact solution, FP64 to 1e-13 and bitwise equal
+    to the oracle, mixed to FP32 rounding (the face fluxes are FP32), with the ghosts of
+    each stage taken at that stage's own fraction of the parent step."""
+    from tests.test_oracle_amr_schedule import CASES as RC, ramp_errors, ramp_hierarchy
+    torch, A, O = env
+    log(f"case amr ramp ndim={ndim} levels={nlev} exec={exe} prec={prec}")
+    Nc, boxes, grad, vel = RC[ndim]
+    ps, U = ramp_hierarchy(ndim, Nc, boxes[:nlev - 1], grad, vel)
+    T = A.Table(ps, precision=prec, exec_form=exe, recon=A.AMR_RECON_P)
+    Ud = T.upload(U)
+    o = O.AmrOracle(ps, recon=O.RECON_P)
+    Uo = U.copy()
+    t, steps = 0.0, 2
+    for s in range(steps):
+        dt = A.amr_cfl_dt(T.h, Ud, 0.8, -1, T.dt, host=True)
+        dto = o.cfl_dt0(Uo, 0.8)
+        if prec == 0:
+            assert dt == dto, s
+        T.dt.fill_(dto)  # both sides on the oracle's time step
+        A.amr_hydro_advance(T.h, Ud, T.dt)
+        o.advance(Uo, dto)
+        t += dto
+    torch.cuda.synchronize()
+    assert T.status() == A.AMR_OK
+    Ug = Ud.cpu().numpy()
+    T.close()
+    errs = ramp_errors(ps, Ug, t, steps)
+    log(f"ramp ndim={ndim} levels={nlev} exec={exe} prec={prec}: max |U - exact| per level {errs}")
+    tol = 1e-13 if prec == 0 else 1e-5
+    assert max(errs.values()) <= tol, errs
+    if prec == 0:
+        assert np.array_equal(active_all(ps, Ug), active_all(ps, Uo))
