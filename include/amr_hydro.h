@@ -42,8 +42,8 @@
  *     non-finite value in a cell the stencil reads) is latched in the table and
  *     returned as AMR_EUNPHYSICAL by the next synchronising call
  *     (amr_cfl_dt with dt_host, amr_table_status); the U it produced is not
- *     meaningful.  Recovery (restore U^n, retry with a smaller dt) is the
- *     caller's.
+ *     meaningful.  Recovery is the caller's: amr_table_status (which clears
+ *     the latch), restore U^n, then retry with a smaller dt.
  *   - A table is not thread-safe; calls on one table must be serialised.
  *
  * The U arena (layout of conserved state, caller-owned, FP64)
@@ -168,18 +168,26 @@ amr_status amr_patch_table_create(const amr_patch_desc* patches, int32_t npatch,
 /* Free everything the table owns (waits for the device to finish using it). */
 amr_status amr_patch_table_destroy(amr_table* table);
 
-/* Number of doubles the U arena must hold (max over patches of offset + 5 S). */
+/* Number of doubles the U arena must hold (max over patches of offset + nvar S). */
 int64_t amr_table_arena_elems(const amr_table* table);
 
-/* Global CFL time step (the rule the paper leaves unstated; see the design
- * notes): dt = cfl / max over active cells of sum_d (|v_d| + c_s) / dx_d, with
+/* Global CFL time step (a rule the paper leaves unstated; the unsplit sum form
+ * keeps 3D runs stable at cfl = 0.8): dt = cfl / max over active cells of
+ * sum_d (|v_d| + c_s) / dx_d, with
  * c_s = sqrt(gamma p / rho), over the patches of `level` (-1 = all levels).
  * With several levels and level = -1 the root step of a factor-2 subcycled
  * hierarchy is returned: dt0 = cfl * min_l 2^l / smax_l.  The result is written
  * to dt_dev[0] (device, caller-owned).  If dt_host is not NULL the call waits
  * for the stream, copies the value there, and returns AMR_EUNPHYSICAL if the
- * device flag is set.  The max is order-independent, so the value is
- * deterministic. */
+ * device flag is set (the latch stays set: every later call with dt_host returns
+ * AMR_EUNPHYSICAL until amr_table_status clears it).  The max is
+ * order-independent, so the value is deterministic.  After a step with
+ * AMR_STEP_FUSE_DT the first call on the same U and level reads the maxima that
+ * step reduced instead of scanning U, unless amr_table_status was called in
+ * between; any later call scans U again.
+ * Recovery (from AMR_EUNPHYSICAL, or any rejected step): amr_table_status (clears
+ * the latch and the fused maxima), restore U^n, amr_cfl_dt (a fresh scan of U^n),
+ * then retry with a smaller dt. */
 amr_status amr_cfl_dt(amr_table* table, const double* U, double cfl, int32_t level, double* dt_dev,
                       double* dt_host, hipStream_t stream);
 
@@ -225,7 +233,8 @@ amr_status amr_hydro_advance(amr_table* table, double* U, const double* dt0_dev,
 
 /* Wait for `stream`, then return AMR_EUNPHYSICAL if any kernel latched an
  * unphysical state since the table was created or last cleared, else AMR_OK.
- * Clears the latch. */
+ * Clears the latch, and drops the maxima fused into the last step (the next
+ * amr_cfl_dt scans U, which the caller may have rewritten since). */
 amr_status amr_table_status(amr_table* table, hipStream_t stream);
 
 /* Tile shape control (batched and plain forms share the kernels).
@@ -244,9 +253,16 @@ amr_status amr_table_get_tiling(amr_table* table, int32_t* id, int32_t* zslab);
 amr_status amr_table_tiling_shape(const amr_table* table, int32_t id, int32_t* tx, int32_t* ty);
 
 /* Autotuner: time every (shape, zslab) candidate on the caller's data with
- * HIP events (each candidate runs `reps` full RK2 steps on a copy of U held
- * in the table's scratch, so U is not modified), keep the fastest, and
- * return its time per step in *ms_best (nullable).  Synchronises the stream. */
+ * HIP events (each candidate runs `reps` full RK2 steps of `level` on a copy of
+ * U in a temporary device buffer of amr_table_arena_elems doubles that the call
+ * allocates and frees, so U is not modified), keep the fastest (it stays the
+ * table's tiling until amr_table_set_tiling), and return its time per step in
+ * *ms_best (nullable).  Synchronises the stream.  The unphysical latch is left as
+ * it was before the call.  Tables with several levels: `level` must name one
+ * level (AMR_EINVAL otherwise), and AMR_ESTATE is returned while a caller-driven
+ * recursion is open (a level with children has stepped and its amr_flux_correct
+ * is still due), because the candidates reuse the snapshot, U^(1) and the flux
+ * registers that recursion needs.  AMR_ENOMEM if the copy cannot be allocated. */
 amr_status amr_autotune(amr_table* table, const double* U, const double* dt_dev, int32_t level, int32_t reps,
                         hipStream_t stream, float* ms_best);
 

@@ -22,6 +22,69 @@
 
 using namespace amr;
 
+namespace amr {
+
+amr_status validate_patches(const amr_patch_desc* P, int32_t np, const amr_physics* ph) {
+  if (!P || !ph || np < 1) return AMR_EINVAL;
+  if ((ph->nvar != NVAR && ph->nvar != NVAR_MHD && ph->nvar != NVAR_GLM) || ph->ndim < 1 || ph->ndim > 3)
+    return AMR_EINVAL;
+  if (!(ph->ch >= 0.0 && ph->ch < 1e300)) return AMR_EINVAL;
+  if (!(ph->gamma > 1.0) || !(ph->theta >= 0.0 && ph->theta <= 2.0)) return AMR_EINVAL;
+  for (int d = 0; d < 3; ++d)
+    if (!(ph->dx0[d] > 0)) return AMR_EINVAL;
+  if (ph->flux != AMR_FLUX_PAPER && ph->flux != AMR_FLUX_HLL2) return AMR_EINVAL;
+  if (ph->precision != AMR_PREC_FP64 && ph->precision != AMR_PREC_MIXED) return AMR_EINVAL;
+  if (ph->exec != AMR_EXEC_PLAIN && ph->exec != AMR_EXEC_BATCHED) return AMR_EINVAL;
+  if ((ph->recon != AMR_RECON_E && ph->recon != AMR_RECON_P) || ph->periodic < 0 || ph->periodic > 7)
+    return AMR_EINVAL;
+  for (int d = 0; d < 3; ++d)
+    if (((ph->periodic >> d) & 1) && ph->domain[d] < 1) return AMR_EINVAL;
+  if (ph->rho_floor < 0 || ph->e_floor < 0) return AMR_EINVAL;
+  std::vector<std::pair<int64_t, int64_t>> spans;
+  for (int p = 0; p < np; ++p) {
+    const amr_patch_desc& D = P[p];
+    if (D.level < 0 || D.level >= MAX_LEVELS || D.offset < 0 || D.reserved[0] || D.reserved[1]) return AMR_EINVAL;
+    if (D.ng < 2 || D.ng > 8) return AMR_EINVAL;
+    int64_t S = 1;
+    for (int d = 0; d < 3; ++d) {
+      if (D.n[d] < 1) return AMR_EINVAL;
+      if (d >= ph->ndim && D.n[d] != 1) return AMR_EINVAL;
+      if (d < ph->ndim && D.n[d] < D.ng) return AMR_EINVAL;
+      if (D.n[d] > (1 << 24)) return AMR_EINVAL;
+      S *= D.n[d] + (d < ph->ndim ? 2 * D.ng : 0);
+      for (int s = 0; s < 2; ++s) {
+        const int b = D.bc[2 * d + s];
+        if (b < AMR_BC_OUTFLOW || b > AMR_BC_EXTERNAL) return AMR_EINVAL;
+      }
+      if (d < ph->ndim && ((D.bc[2 * d] == AMR_BC_PERIODIC) != (D.bc[2 * d + 1] == AMR_BC_PERIODIC)))
+        return AMR_EINVAL;
+    }
+    spans.emplace_back(D.offset, D.offset + ph->nvar * S);
+  }
+  std::sort(spans.begin(), spans.end());
+  for (size_t i = 1; i < spans.size(); ++i)
+    if (spans[i].first < spans[i - 1].second) return AMR_EINVAL;
+  return AMR_OK;
+}
+
+Consts consts_of_phys(const amr_physics& ph) {
+  Consts c{};
+  c.gamma = ph.gamma;
+  c.gm1 = ph.gamma - 1.0;
+  c.gg1 = ph.gamma * (ph.gamma - 1.0);
+  c.theta = ph.theta;
+  c.rho_floor = ph.rho_floor;
+  c.e_floor = ph.e_floor;
+  c.ndim = ph.ndim;
+  c.flux = ph.flux;
+  c.recon = ph.recon;
+  c.ch = ph.nvar == NVAR_GLM ? ph.ch : 0.0;
+  c.ch2 = c.ch * c.ch;
+  return c;
+}
+
+}  // namespace amr
+
 namespace {
 
 struct TileSet {
@@ -75,9 +138,13 @@ struct amr_table {
   std::map<std::tuple<int, int, int>, TileSet> tiles;  // (level scope, shape, zslab)
   GraphCache gc;
   hipStream_t cap_stream = nullptr;
-  // fused dt bookkeeping
+  // fused dt bookkeeping: the U and level whose maxima stage 2 reduced into fused_d,
+  // valid until amr_cfl_dt reads them or the unphysical latch is found set
   const double* fused_U = nullptr;
   int fused_level = -2;
+  // caller-driven recursion: bit l is set by a step of level l that has children and
+  // cleared by amr_flux_correct(l) (the snapshot, U^(1) and registers are in use)
+  uint32_t open_mask = 0;
   int occ[3][2][NSHAPES][2][2] = {};  // resident stage workgroups per CU: [5/8/9 variables][mixed][shape][stage][recording]
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // AMR_STEP_TIMED: around each stage kernel
   bool timed_valid = false;
@@ -158,19 +225,7 @@ int auto_zslab(amr_table* t, int level, int shape) {
   // three of 86 although three fill every resident slot)
   const int64_t G = (int64_t)std::min(occupancy_grid(t, 2, 1 << 30, rec), 2 * t->ncu) * shape_tiles_per_wg(shape);
   t->shape = keep;
-  if (txy >= 4 * G) return nz;
-  int64_t best = -1;
-  int bz = nz;
-  for (int ns = 1; ns <= std::max(1, nz / 8); ++ns) {
-    const int zs = (nz + ns - 1) / ns;
-    const int64_t rounds = (txy * ((nz + zs - 1) / zs) + G - 1) / G;
-    const int64_t c = rounds * (zs + 4);
-    if (best < 0 || c < best) {
-      best = c;
-      bz = zs;
-    }
-  }
-  return bz;
+  return balanced_zslab(txy, nz, G);
 }
 
 int default_zslab(const amr_table* t) { return t->ph.ndim == 3 ? 0 : 1; }  // 0 = auto_zslab
@@ -274,21 +329,7 @@ amr_status get_tiles(amr_table* t, int level, int shape, int zslab, TileSet** ou
   return AMR_OK;
 }
 
-Consts consts_of(const amr_table* t) {
-  Consts c{};
-  c.gamma = t->ph.gamma;
-  c.gm1 = t->ph.gamma - 1.0;
-  c.gg1 = t->ph.gamma * (t->ph.gamma - 1.0);
-  c.theta = t->ph.theta;
-  c.rho_floor = t->ph.rho_floor;
-  c.e_floor = t->ph.e_floor;
-  c.ndim = t->ph.ndim;
-  c.flux = t->ph.flux;
-  c.recon = t->ph.recon;
-  c.ch = t->ph.nvar == NVAR_GLM ? t->ph.ch : 0.0;
-  c.ch2 = c.ch * c.ch;
-  return c;
-}
+Consts consts_of(const amr_table* t) { return consts_of_phys(t->ph); }
 
 // Resident workgroups per CU of the stage kernel in use (queried once per
 // (precision, shape, stage, recording), outside any graph capture); the grid of a
@@ -454,48 +495,6 @@ void drop_graph(amr_table* t) {
   t->gadv = GraphCache{};
 }
 
-amr_status validate(const amr_patch_desc* P, int32_t np, const amr_physics* ph) {
-  if (!P || !ph || np < 1) return AMR_EINVAL;
-  if ((ph->nvar != NVAR && ph->nvar != NVAR_MHD && ph->nvar != NVAR_GLM) || ph->ndim < 1 || ph->ndim > 3)
-    return AMR_EINVAL;
-  if (!(ph->ch >= 0.0 && ph->ch < 1e300)) return AMR_EINVAL;
-  if (!(ph->gamma > 1.0) || !(ph->theta >= 0.0 && ph->theta <= 2.0)) return AMR_EINVAL;
-  for (int d = 0; d < 3; ++d)
-    if (!(ph->dx0[d] > 0)) return AMR_EINVAL;
-  if (ph->flux != AMR_FLUX_PAPER && ph->flux != AMR_FLUX_HLL2) return AMR_EINVAL;
-  if (ph->precision != AMR_PREC_FP64 && ph->precision != AMR_PREC_MIXED) return AMR_EINVAL;
-  if (ph->exec != AMR_EXEC_PLAIN && ph->exec != AMR_EXEC_BATCHED) return AMR_EINVAL;
-  if ((ph->recon != AMR_RECON_E && ph->recon != AMR_RECON_P) || ph->periodic < 0 || ph->periodic > 7)
-    return AMR_EINVAL;
-  for (int d = 0; d < 3; ++d)
-    if (((ph->periodic >> d) & 1) && ph->domain[d] < 1) return AMR_EINVAL;
-  if (ph->rho_floor < 0 || ph->e_floor < 0) return AMR_EINVAL;
-  std::vector<std::pair<int64_t, int64_t>> spans;
-  for (int p = 0; p < np; ++p) {
-    const amr_patch_desc& D = P[p];
-    if (D.level < 0 || D.level >= MAX_LEVELS || D.offset < 0 || D.reserved[0] || D.reserved[1]) return AMR_EINVAL;
-    if (D.ng < 2 || D.ng > 8) return AMR_EINVAL;
-    int64_t S = 1;
-    for (int d = 0; d < 3; ++d) {
-      if (D.n[d] < 1) return AMR_EINVAL;
-      if (d >= ph->ndim && D.n[d] != 1) return AMR_EINVAL;
-      if (d < ph->ndim && D.n[d] < D.ng) return AMR_EINVAL;
-      if (D.n[d] > (1 << 24)) return AMR_EINVAL;
-      S *= D.n[d] + (d < ph->ndim ? 2 * D.ng : 0);
-      for (int s = 0; s < 2; ++s) {
-        const int b = D.bc[2 * d + s];
-        if (b < AMR_BC_OUTFLOW || b > AMR_BC_EXTERNAL) return AMR_EINVAL;
-      }
-      if (d < ph->ndim && ((D.bc[2 * d] == AMR_BC_PERIODIC) != (D.bc[2 * d + 1] == AMR_BC_PERIODIC)))
-        return AMR_EINVAL;
-    }
-    spans.emplace_back(D.offset, D.offset + ph->nvar * S);
-  }
-  std::sort(spans.begin(), spans.end());
-  for (size_t i = 1; i < spans.size(); ++i)
-    if (spans[i].first < spans[i - 1].second) return AMR_EINVAL;
-  return AMR_OK;
-}
 
 // EXTERNAL ghost plan: each ghost cell (two layers, the cross region) is copied
 // from the same-level patch that holds it as an active cell (periodic root domain
@@ -944,7 +943,7 @@ amr_status amr_patch_table_create(const amr_patch_desc* patches, int32_t npatch,
                                   hipStream_t stream, amr_table** out) {
   if (!out) return AMR_EINVAL;
   *out = nullptr;
-  amr_status st = validate(patches, npatch, phys);
+  amr_status st = validate_patches(patches, npatch, phys);
   if (st != AMR_OK) return st;
   amr_table* t = new (std::nothrow) amr_table();
   if (!t) return AMR_ENOMEM;
@@ -1147,6 +1146,7 @@ amr_status amr_hydro_rk2_step(amr_table* t, double* U, const double* dt_dev, int
     t->fused_U = nullptr;
     t->fused_level = -2;
   }
+  if (level >= 0 && t->has_kids[level]) t->open_mask |= 1u << level;
   return AMR_OK;
 }
 
@@ -1157,6 +1157,10 @@ amr_status amr_cfl_dt(amr_table* t, const double* U, double cfl, int32_t level, 
   const unsigned long long* src;
   if (t->fused_U == U && t->fused_level == level) {
     src = t->fused_d;  // maxima of this U were reduced by the last fused stage 2
+    // read once: a caller that restores U^n into the same memory (the recovery
+    // recipe) gets a fresh scan from the next call
+    t->fused_U = nullptr;
+    t->fused_level = -2;
   } else {
     TileSet* ts = nullptr;
     amr_status st = get_tiles(t, level, t->shape, t->zslab, &ts);
@@ -1186,7 +1190,11 @@ amr_status amr_cfl_dt(amr_table* t, const double* U, double cfl, int32_t level, 
     int flag = 0;
     HIPCHECK(hipMemcpyAsync(&flag, t->flag_d, sizeof(int), hipMemcpyDeviceToHost, stream));
     HIPCHECK(hipStreamSynchronize(stream));
-    if (flag) return AMR_EUNPHYSICAL;
+    if (flag) {
+      t->fused_U = nullptr;
+      t->fused_level = -2;
+      return AMR_EUNPHYSICAL;
+    }
   }
   return AMR_OK;
 }
@@ -1194,7 +1202,9 @@ amr_status amr_cfl_dt(amr_table* t, const double* U, double cfl, int32_t level, 
 amr_status amr_flux_correct(amr_table* t, double* U, int32_t coarse_level, hipStream_t stream) {
   if (!t || !U || coarse_level < 0 || coarse_level > t->max_level) return AMR_EINVAL;
   if (!t->has_kids[coarse_level] || !t->last_dt[coarse_level]) return AMR_ESTATE;
-  return enqueue_correct(t, U, coarse_level, stream);
+  amr_status st = enqueue_correct(t, U, coarse_level, stream);
+  if (st == AMR_OK) t->open_mask &= ~(1u << coarse_level);
+  return st;
 }
 
 amr_status amr_hydro_advance(amr_table* t, double* U, const double* dt0_dev, uint32_t flags, hipStream_t stream) {
@@ -1206,6 +1216,7 @@ amr_status amr_hydro_advance(amr_table* t, double* U, const double* dt0_dev, uin
   if (t->max_level == 0) {  // no hierarchy: one step of the root level with dt0
     return amr_hydro_rk2_step(t, U, dt0_dev, -1, 0, stream);
   }
+  t->open_mask = 0;  // a whole root step closes every level's recursion
   for (int l = 0; l <= t->max_level; ++l) {  // tile lists and occupancy before any capture
     TileSet* ts = nullptr;
     amr_status st = get_tiles(t, l, t->shape, t->zslab, &ts);
@@ -1253,6 +1264,10 @@ amr_status amr_table_status(amr_table* t, hipStream_t stream) {
   int flag = 0;
   HIPCHECK(hipMemcpyAsync(&flag, t->flag_d, sizeof(int), hipMemcpyDeviceToHost, stream));
   HIPCHECK(hipStreamSynchronize(stream));
+  // the caller may now rewrite U (the recovery recipe restores U^n): the next
+  // amr_cfl_dt scans U instead of reading maxima fused into the last step
+  t->fused_U = nullptr;
+  t->fused_level = -2;
   if (flag) {
     HIPCHECK(launch_fill_i32(stream, t->flag_d, 1, 0));
     HIPCHECK(hipStreamSynchronize(stream));
@@ -1297,11 +1312,22 @@ amr_status amr_table_tiling_shape(const amr_table* t, int32_t id, int32_t* tx, i
 amr_status amr_autotune(amr_table* t, const double* U, const double* dt_dev, int32_t level, int32_t reps,
                         hipStream_t stream, float* ms_best) {
   if (!t || !U || !dt_dev || reps < 1 || level < -1 || level > t->max_level) return AMR_EINVAL;
+  if (t->max_level > 0 && level < 0) return AMR_EINVAL;
+  // the candidates overwrite the snapshot, U^(1) and the flux registers that an open
+  // caller-driven recursion still needs
+  if (t->open_mask) return AMR_ESTATE;
+  // the latch as the caller left it: candidate runs on the copy must not change it
+  int flag_keep = 0;
+  HIPCHECK(hipMemcpyAsync(&flag_keep, t->flag_d, sizeof(int), hipMemcpyDeviceToHost, stream));
+  HIPCHECK(hipStreamSynchronize(stream));
   double* W = nullptr;
   if (hipMalloc(&W, sizeof(double) * (size_t)t->arena) != hipSuccess) return AMR_ENOMEM;
-  hipEvent_t e0, e1;
-  HIPCHECK(hipEventCreate(&e0));
-  HIPCHECK(hipEventCreate(&e1));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    (void)hipFree(W);
+    return AMR_EHIP;
+  }
   int maxnz = 1;
   for (auto& P : t->pdev)
     if (level < 0 || P.level == level) maxnz = std::max(maxnz, P.n[2]);
@@ -1315,6 +1341,7 @@ amr_status amr_autotune(amr_table* t, const double* U, const double* dt_dev, int
     zs.push_back(1);
   }
   const int keep_shape = t->shape, keep_z = t->zslab;
+  const std::vector<const double*> keep_dt = t->last_dt;
   float best = 1e30f;
   int bshape = keep_shape, bz = keep_z;
   amr_status st = AMR_OK;
@@ -1354,11 +1381,16 @@ amr_status amr_autotune(amr_table* t, const double* U, const double* dt_dev, int
   t->shape = st == AMR_OK ? bshape : keep_shape;
   t->zslab = st == AMR_OK ? bz : keep_z;
   drop_graph(t);
-  if (t->fused_U == W) t->fused_U = nullptr;
-  if (ms_best) *ms_best = best;
-  if (st == AMR_OK) {
-    // the candidate runs may have latched a flag on the copy; report through status as usual
+  if (t->fused_U == W) {
+    t->fused_U = nullptr;
+    t->fused_level = -2;
   }
+  // the candidates' steps leave no recursion open and no level stepped on the caller's U
+  t->open_mask = 0;
+  t->last_dt = keep_dt;
+  HIPCHECK(launch_fill_i32(stream, t->flag_d, 1, flag_keep));
+  HIPCHECK(hipStreamSynchronize(stream));
+  if (ms_best) *ms_best = best;
   return st;
 }
 

@@ -4,6 +4,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "../../include/amr_hydro.h"
 #include "amr_device.h"
 
 namespace amr {
@@ -109,6 +110,33 @@ constexpr int shape_tiles_per_wg(int shape) { return SHAPE_NT[shape] / (SHAPE_TX
 // that spills registers).
 constexpr bool mhd_shape_ok(int mixed, int shape) {
   return shape == 0 || shape == 1 || shape == 4 || ((shape == 5 || shape == 6) && mixed);
+}
+
+// Host helpers shared by the table (amr_api.hip) and the allocation-free step
+// (amr_noalloc.hip).
+// Descriptor and physics validation of amr_patch_table_create (AMR_EINVAL rules of
+// the public header).
+amr_status validate_patches(const amr_patch_desc* P, int32_t np, const amr_physics* ph);
+// Kernel constants of a physics block.
+Consts consts_of_phys(const amr_physics& ph);
+// z-slab length that balances a persistent launch: per-tile time taken as
+// proportional to its planes + 4 (the z prologue reads 4 planes); with txy column
+// blocks, nz planes and G tiles in flight, the slab count that minimises
+// rounds x (slab + 4).  Enough column blocks keep whole patches.
+inline int balanced_zslab(int64_t txy, int nz, int64_t G) {
+  if (txy >= 4 * G) return nz;
+  int64_t best = -1;
+  int bz = nz;
+  for (int ns = 1; ns <= (nz / 8 > 1 ? nz / 8 : 1); ++ns) {
+    const int zs = (nz + ns - 1) / ns;
+    const int64_t rounds = (txy * ((nz + zs - 1) / zs) + G - 1) / G;
+    const int64_t c = rounds * (zs + 4);
+    if (best < 0 || c < best) {
+      best = c;
+      bz = zs;
+    }
+  }
+  return bz;
 }
 
 }  // namespace amr
