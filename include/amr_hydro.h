@@ -315,6 +315,32 @@ amr_status amr_cluster_flags(const amr_patch_desc* patches, int32_t npatch, int3
                              int32_t level, const uint8_t* flags, int32_t brick, int32_t block, int32_t* boxes,
                              int32_t max_boxes, int32_t* nboxes);
 
+/* Allocation-free RK2 step of one patch, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same update and same bits as amr_hydro_rk2_step on a single-level table
+ * made of this one patch (any precision; the persistent launch of the batched form,
+ * enqueued eagerly), with no table: the patch descriptor, its tile list and the
+ * stage output U^(1) live in a device array of AMR_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each GPU it runs on until the process ends.  The call allocates
+ * nothing and copies nothing from the host; it enqueues three kernels on `stream`.
+ *   patch   host descriptor: level 0, bc OUTFLOW, PERIODIC or REFLECT on every face
+ *           (no EXTERNAL face: a lone patch has no source for it), other rules as in
+ *           amr_patch_table_create; phys as there (exec is ignored).
+ *   U       caller-owned device arena holding the patch at patch->offset; U^n in,
+ *           U^{n+1} out.
+ *   dt_dev  caller-owned device double, read when the step runs.
+ *   flag_dev caller-owned device int32, set nonzero (never cleared) if the step meets
+ *           an unphysical state (the table's latch).
+ * AMR_EINVAL (nothing enqueued) for a bad argument, an EXTERNAL face, a level other
+ * than 0, or a patch whose nvar * S doubles of U^(1) plus its tile list exceed the
+ * scratch (e.g. 5 variables of 144^3 stored cells fit, 8 variables of 136^3 do not);
+ * the last case also prints the bytes needed to stderr.  Every call on one GPU shares
+ * that GPU's scratch: calls that overlap on one GPU (other streams, other host
+ * threads) race and must be serialised by the caller. */
+#define AMR_NOALLOC_SCRATCH_BYTES (134217728ull) /* 128 MiB per GPU */
+amr_status amr_patch_rk2_step_noalloc(const amr_patch_desc* patch, const amr_physics* phys, double* U,
+                                      const double* dt_dev, int32_t* flag_dev, hipStream_t stream);
+
 const char* amr_status_string(amr_status status);
 
 #ifdef __cplusplus

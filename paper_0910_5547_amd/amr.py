@@ -32,7 +32,8 @@ EXPORTED = ("amr_patch_table_create", "amr_patch_table_destroy", "amr_table_aren
             "amr_hydro_rk2_step", "amr_flux_correct", "amr_table_status", "amr_table_num_tilings",
             "amr_table_set_tiling", "amr_table_get_tiling", "amr_table_tiling_shape", "amr_autotune",
             "amr_table_last_stage_ms", "amr_hydro_advance", "amr_status_string", "amr_table_cells",
-            "amr_flag_cells", "amr_cluster_flags", "amr_regrid_fill")
+            "amr_flag_cells", "amr_cluster_flags", "amr_regrid_fill", "amr_patch_rk2_step_noalloc")
+AMR_NOALLOC_SCRATCH_BYTES = 134217728
 
 
 class amr_patch_desc(C.Structure):
@@ -86,6 +87,7 @@ def lib():
         L.amr_table_cells.restype = i64
         L.amr_flag_cells.argtypes = [vp, vp, i32, C.c_double, vp, vp]
         L.amr_regrid_fill.argtypes = [vp, vp, vp, vp, vp]
+        L.amr_patch_rk2_step_noalloc.argtypes = [C.POINTER(amr_patch_desc), C.POINTER(amr_physics), vp, vp, vp, vp]
         L.amr_cluster_flags.argtypes = [C.POINTER(amr_patch_desc), i32, i32, C.POINTER(i32), i32,
                                          C.POINTER(C.c_uint8), i32, i32, C.POINTER(i32), i32, C.POINTER(i32)]
         for name in EXPORTED:
@@ -269,6 +271,16 @@ def amr_cluster_flags(descs, ndim, domain, level, flags, brick=8, block=32):
             cap = n.value
             continue
         _check(st, "amr_cluster_flags")
+
+
+def amr_patch_rk2_step_noalloc(desc, phys, U, dt_dev, flag_dev, stream=None):
+    """One RK2 step of the lone patch `desc` (an amr_patch_desc) with the library's static
+    scratch; flag_dev is an int32 device tensor the step sets nonzero on an unphysical state."""
+    if not (flag_dev.dtype == torch.int32 and flag_dev.is_cuda and flag_dev.numel() >= 1):
+        raise ValueError("flag_dev must be an int32 GPU tensor")
+    return _check(lib().amr_patch_rk2_step_noalloc(C.byref(desc), C.byref(phys), _ptr(U), _ptr(dt_dev),
+                                                   C.c_void_p(flag_dev.data_ptr()), _stream(stream)),
+                  "amr_patch_rk2_step_noalloc")
 
 
 def amr_table_last_stage_ms(h):
