@@ -32,6 +32,16 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Threads the parallel regions below use: 1 in the serial build (the checker); the
+ * OpenMP build of the same source, used only to time the oracle on all host cores,
+ * reports its team size. */
+#ifdef _OPENMP
+#include <omp.h>
+int or_threads(void) { return omp_get_max_threads(); }
+#else
+int or_threads(void) { return 1; }
+#endif
+
 /* ---------------------------------------------------------------- geometry */
 typedef struct {
   int level, n[3], g[3], s[3], bc[6];
@@ -246,7 +256,11 @@ static int prolong_cell(int32_t np, const int32_t* meta, const int64_t* off, con
                         const double* Cnew, double alpha, int level, const int L[3], double* out) {
   int Cc[3] = {0, 0, 0};
   for (int e = 0; e < ph->ndim; ++e) Cc[e] = L[e] >> 1; /* L >= 0 after the periodic wrap */
-  for (int q = 0; q < np; ++q) {
+  /* the patches of a level are disjoint, so at most one holds C; the search starts at the
+   * patch that held the previous cell (neighbouring ghost cells share it) */
+  static _Thread_local int last = 0;
+  for (int i = 0; i < np; ++i) {
+    const int q = (last + i) % np;
     const int32_t* mq = meta + (size_t)q * OR_META;
     if (mq[0] != level - 1) continue;
     int inside = 1;
@@ -271,15 +285,51 @@ static int prolong_cell(int32_t np, const int32_t* meta, const int64_t* off, con
       }
       out[k] = v;
     }
+    last = q;
     return 1;
   }
   return 0;
+}
+
+/* Does the cell interval [a, b) of an axis meet [c, e)?  On a periodic axis of length D
+ * (D > 0) the interval is taken modulo D. */
+static int axis_meets(int a, int b, int c, int e, int D) {
+  if (D <= 0) return a < e && c < b;
+  if (b - a >= D) return 1;
+  int a0 = ((a % D) + D) % D, b0 = a0 + (b - a);
+  if (b0 <= D) return a0 < e && c < b0;
+  return (a0 < e && c < D) || (0 < e && c < b0 - D);
 }
 
 static void fill_external(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph, double* V, int p,
                           const geom* G, int d, int side, const double* Cold, const double* Cnew, double alpha) {
   const int32_t* m = meta + (size_t)p * OR_META;
   int a = (d + 1) % 3, b = (d + 2) % 3;
+  /* The same-level patches whose box meets this face's ghost slab: only these can hold a
+   * ghost cell (a pure lookup; the patches of a level are disjoint, so the holder of a
+   * cell is unique and the search order does not matter). */
+  int* cand = malloc(sizeof(int) * (size_t)np);
+  int nc = 0;
+  {
+    int slo[3], shi[3];
+    for (int e = 0; e < 3; ++e) {
+      slo[e] = m[1 + e];
+      shi[e] = m[1 + e] + G->n[e];
+    }
+    slo[d] = side == 0 ? m[1 + d] - G->g[d] : m[1 + d] + G->n[d];
+    shi[d] = slo[d] + G->g[d];
+    for (int q = 0; q < np; ++q) {
+      const int32_t* mq = meta + (size_t)q * OR_META;
+      if (mq[0] != m[0]) continue; /* p itself can hold them across a periodic wrap */
+      int meets = 1;
+      for (int e = 0; e < ph->ndim && meets; ++e) {
+        int D = ((ph->periodic >> e) & 1) ? (ph->domain[e] << m[0]) : 0;
+        meets = axis_meets(slo[e], shi[e], mq[1 + e], mq[1 + e] + mq[4 + e], D);
+      }
+      if (meets) cand[nc++] = q;
+    }
+  }
+  int last = 0;
   for (int layer = 1; layer <= G->g[d]; ++layer) {
     int gi = side == 0 ? -layer : G->n[d] - 1 + layer;
     for (int ib = 0; ib < G->n[b]; ++ib)
@@ -294,9 +344,9 @@ static void fill_external(int32_t np, const int32_t* meta, const int64_t* off, c
           }
         }
         int found = 0;
-        for (int q = 0; q < np; ++q) {
+        for (int i = 0; i < nc; ++i) { /* start at the last hit: neighbouring cells share it */
+          const int q = cand[(last + i) % nc];
           const int32_t* mq = meta + (size_t)q * OR_META;
-          if (mq[0] != m[0]) continue;
           int inside = 1;
           for (int e = 0; e < ph->ndim; ++e)
             if (L[e] < mq[1 + e] || L[e] >= mq[1 + e] + mq[4 + e]) inside = 0;
@@ -306,6 +356,7 @@ static void fill_external(int32_t np, const int32_t* meta, const int64_t* off, c
           for (int e = 0; e < ph->ndim; ++e) cs[e] = L[e] - mq[1 + e];
           for (int k = 0; k < ph->nvar; ++k) V[at(G, k, cg)] = V[at(&Q, k, cs)];
           found = 1;
+          last = (last + i) % nc;
           break;
         }
         if (!found && m[0] > 0 && Cold && Cnew) {
@@ -315,6 +366,7 @@ static void fill_external(int32_t np, const int32_t* meta, const int64_t* off, c
         }
       }
   }
+  free(cand);
 }
 
 
@@ -325,6 +377,8 @@ int or_fill_ghosts(int32_t np, const int32_t* meta, const int64_t* off, const or
 
 int or_fill_ghosts_amr(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph, double* V,
                        int32_t level, const double* Cold, const double* Cnew, double alpha) {
+  /* each patch writes only its own ghost cells and reads active cells */
+#pragma omp parallel for schedule(dynamic)
   for (int p = 0; p < np; ++p) {
     const int32_t* m = meta + (size_t)p * OR_META;
     if (!is_level(m, level)) continue;
@@ -462,6 +516,9 @@ int or_stage_rec(int32_t np, const int32_t* meta, const int64_t* off, const or_p
                  const double* U0, double* out, double dt, int32_t stage, int32_t level, const int64_t* rec_off,
                  double* Frec) {
   int bad = 0;
+  /* patches are independent within a stage: the OpenMP build (timing only) runs them on
+   * several cores; the serial build ignores the pragma */
+#pragma omp parallel for schedule(dynamic) reduction(| : bad)
   for (int p = 0; p < np; ++p) {
     const int32_t* m = meta + (size_t)p * OR_META;
     if (!is_level(m, level)) continue;
@@ -501,6 +558,7 @@ double or_max_speed(int32_t np, const int32_t* meta, const int64_t* off, const o
                     const double* U, int32_t level, int* flag) {
   double smax = 0.0;
   int bad = 0;
+#pragma omp parallel for schedule(dynamic) reduction(max : smax) reduction(| : bad)
   for (int p = 0; p < np; ++p) {
     const int32_t* m = meta + (size_t)p * OR_META;
     if (!is_level(m, level)) continue;

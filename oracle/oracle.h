@@ -107,6 +107,9 @@ int64_t or_flag_cells(int32_t np, const int32_t* meta, const int64_t* off, const
 double or_cfl_dt(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph,
                  const double* U, double cfl, int32_t level);
 
+/* Threads of the oracle's parallel patch loops: 1 in the serial build. */
+int or_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,6 +17,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
+_LIB_OMP = None
 
 FLUX_PAPER, FLUX_HLL2 = 0, 1
 RECON_E, RECON_P = 0, 1
@@ -29,10 +30,11 @@ class Phys(C.Structure):
                 ("rho_floor", C.c_double), ("e_floor", C.c_double), ("ch", C.c_double)]
 
 
-def lib():
-    global _LIB
-    if _LIB is None:
-        path = os.path.join(HERE, "liboracle.so")
+def lib(parallel: bool = False):
+    """The serial oracle (the checker), or with parallel=True its OpenMP build (timing only)."""
+    global _LIB, _LIB_OMP
+    if (_LIB_OMP if parallel else _LIB) is None:
+        path = os.path.join(HERE, "liboracle_omp.so" if parallel else "liboracle.so")
         if not os.path.exists(path):
             from . import build as _b  # noqa: F401  (plain build of the C source)
             _b.build()
@@ -64,8 +66,13 @@ def lib():
         L.or_flag_cells.argtypes = [C.c_int32, ip, lp, pp, dp, C.c_int32, C.c_double, C.POINTER(C.c_uint8)]
         L.or_cfl_dt.restype = C.c_double
         L.or_cfl_dt.argtypes = [C.c_int32, ip, lp, pp, dp, C.c_double, C.c_int32]
-        _LIB = L
-    return _LIB
+        L.or_threads.restype = C.c_int
+        L.or_threads.argtypes = []
+        if parallel:
+            _LIB_OMP = L
+        else:
+            _LIB = L
+    return _LIB_OMP if parallel else _LIB
 
 
 def _dp(a):
@@ -132,8 +139,11 @@ class Oracle:
     """Oracle bound to one patch table.  All arrays are FP64 arenas laid out as ``ps``."""
 
     def __init__(self, ps, flux=FLUX_PAPER, rho_floor=0.0, e_floor=0.0, theta=None, periodic=0, domain=(0, 0, 0),
-                 recon=RECON_E, ch=0.0):
+                 recon=RECON_E, ch=0.0, parallel=False):
+        """parallel=True binds the OpenMP build of the same source (same results; used to
+        time the oracle on all host cores)."""
         self.ps = ps
+        self.L = lib(parallel)
         self.ph = phys(ps.gamma, ps.theta if theta is None else theta, ps.ndim, ps.dx0, flux, rho_floor, e_floor,
                        periodic, domain, ps.nvar, recon, ch)
         self.meta = np.ascontiguousarray(ps.meta(), np.int32)
@@ -145,31 +155,31 @@ class Oracle:
                 self.off.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(self.ph))
 
     def fill_ghosts(self, U, level=-1):
-        lib().or_fill_ghosts(*self._args(), _dp(U), level)
+        self.L.or_fill_ghosts(*self._args(), _dp(U), level)
 
     def stage(self, V, U0, out, dt, stage, level=-1):
-        return lib().or_stage(*self._args(), _dp(V), _dp(U0) if U0 is not None else None, _dp(out), dt, stage,
+        return self.L.or_stage(*self._args(), _dp(V), _dp(U0) if U0 is not None else None, _dp(out), dt, stage,
                               level)
 
     def rk2_step(self, U, dt, level=-1):
         if self._W is None or self._W.shape != U.shape:
             self._W = np.full_like(U, np.nan)
-        return lib().or_rk2_step(*self._args(), _dp(U), _dp(self._W), dt, level)
+        return self.L.or_rk2_step(*self._args(), _dp(U), _dp(self._W), dt, level)
 
     def max_speed(self, U, level=-1):
         flag = C.c_int(0)
-        s = lib().or_max_speed(*self._args(), _dp(U), level, C.byref(flag))
+        s = self.L.or_max_speed(*self._args(), _dp(U), level, C.byref(flag))
         return s, flag.value
 
     def cfl_dt(self, U, cfl, level=-1):
-        return lib().or_cfl_dt(*self._args(), _dp(U), cfl, level)
+        return self.L.or_cfl_dt(*self._args(), _dp(U), cfl, level)
 
     def flag_cells(self, U, eps, level=-1):
         """Refinement flags (uint8, one per active cell of `level`, patch order): ghosts of U are
         filled first, so U's ghost storage is overwritten."""
         self.fill_ghosts(U, level)
         out = np.zeros(self.ps.active_cells(level), np.uint8)
-        n = lib().or_flag_cells(*self._args(), _dp(U), level, eps, out.ctypes.data_as(C.POINTER(C.c_uint8)))
+        n = self.L.or_flag_cells(*self._args(), _dp(U), level, eps, out.ctypes.data_as(C.POINTER(C.c_uint8)))
         assert n == out.size
         return out
 
@@ -222,6 +232,7 @@ class AmrOracle:
         self.snap = None
         self.W = None
         self.reg = {}
+        self._boxes = {}
         self.dt = [0.0] * self.nlev
 
     # -------------------------------------------------------------- pieces
@@ -284,14 +295,41 @@ class AmrOracle:
         inside = (ps.level == level + 1) & np.all((ps.lo[:, :nd] <= c) & (c < ps.lo[:, :nd] + ps.n[:, :nd]), axis=1)
         return bool(inside.any())
 
+    def _level_boxes(self, level):
+        """(patch ids, lo, hi) of the patches of one level (active boxes, level index space)."""
+        if level not in self._boxes:
+            ps, nd = self.ps, self.ps.ndim
+            ids = np.nonzero(ps.level == level)[0]
+            lo = ps.lo[ids, :nd].astype(np.int64)
+            self._boxes[level] = (ids, lo, lo + ps.n[ids, :nd])
+        return self._boxes[level]
+
+    def _owner(self, level, cells):
+        """For an (m, ndim) array of level cells: the patch of `level` holding each (-1 if
+        none).  The patches of a level are disjoint, so the owner is unique."""
+        ids, lo, hi = self._level_boxes(level)
+        own = np.full(len(cells), -1, np.int64)
+        if len(cells) == 0:
+            return own
+        # only the patches whose box meets the cells' bounding box can hold one of them
+        near = np.all((lo <= cells.max(axis=0)) & (hi > cells.min(axis=0)), axis=1)
+        for q, l0, h0 in zip(ids[near], lo[near], hi[near]):
+            inside = np.all((cells >= l0) & (cells < h0), axis=1)
+            own[inside] = q
+        return own
+
     def correct(self, U, l):
-        """Berger-Colella refluxing of level l against its children."""
+        """Berger-Colella refluxing of level l against its children.  Fine patches, their
+        faces and sides are taken in order; along one face every uncovered coarse cell gets
+        U_c += s (R_c - <R_f>) / dx_c with <R_f> the mean of the 2^(ndim-1) fine register
+        entries under its face (summed in the order y, x of the face's two other axes)."""
         ps = self.ps
+        nd = ps.ndim
         dtc = self.dt[l]
         for p in range(ps.npatch):
             if ps.level[p] != l + 1:
                 continue
-            for d in range(ps.ndim):
+            for d in range(nd):
                 a, b = (d + 1) % 3, (d + 2) % 3
                 for side in (0, 1):
                     if ps.bc[p, 2 * d + side] != 3:
@@ -302,38 +340,42 @@ class AmrOracle:
                     Cd = self._wrap(l, d, cf - 1 if side == 0 else cf)
                     na, nb = int(ps.n[p, a]), int(ps.n[p, b])
                     ca_lo, cb_lo = int(ps.lo[p, a]) >> 1, int(ps.lo[p, b]) >> 1
-                    ca_n, cb_n = max(1, na // 2) if a < ps.ndim else 1, max(1, nb // 2) if b < ps.ndim else 1
-                    for jb in range(cb_n):
-                        for ja in range(ca_n):
-                            C3 = [0, 0, 0]
-                            C3[d], C3[a], C3[b] = Cd, ca_lo + ja, cb_lo + jb
-                            if self._covered(l, C3):
-                                continue
-                            q = self._patch_at(l, C3)
-                            if q < 0:
-                                continue
-                            # fine average over the 2^(ndim-1) fine faces under this coarse face
-                            ia = [2 * ja, 2 * ja + 1] if a < ps.ndim else [0]
-                            ib = [2 * jb, 2 * jb + 1] if b < ps.ndim else [0]
-                            Rf = np.zeros(ps.nvar)
-                            for y in ib:
-                                for x in ia:
-                                    Rf = Rf + R[:, y, x]
-                            Rf = Rf / float(len(ia) * len(ib))
-                            qa, qb = C3[a] - int(ps.lo[q, a]), C3[b] - int(ps.lo[q, b])
-                            fl = C3[d] - int(ps.lo[q, d]) + (1 if side == 0 else 0)
-                            F1 = self._face_block(self.F1, q, d)[:, qb, qa, fl]
-                            F2 = self._face_block(self.F2, q, d)[:, qb, qa, fl]
-                            Rc = 0.5 * dtc * F1
-                            Rc = Rc + 0.5 * dtc * F2
-                            sgn = 1.0 if side == 0 else -1.0
-                            dxc = self.ps.dx0[d] / 2 ** l
-                            cell = [C3[e] - int(ps.lo[q, e]) for e in range(3)]
-                            act = ps.active(U, q)
-                            act[:, cell[2], cell[1], cell[0]] += sgn * (Rc - Rf) / dxc
+                    ca_n = max(1, na // 2) if a < nd else 1
+                    cb_n = max(1, nb // 2) if b < nd else 1
+                    JB, JA = np.meshgrid(np.arange(cb_n), np.arange(ca_n), indexing="ij")
+                    C3 = np.zeros((cb_n * ca_n, 3), np.int64)
+                    C3[:, d] = Cd
+                    C3[:, a] = ca_lo + JA.ravel()
+                    C3[:, b] = cb_lo + JB.ravel()
+                    covered = self._owner(l + 1, 2 * C3[:, :nd]) >= 0
+                    owner = self._owner(l, C3[:, :nd])
+                    # fine average over the 2^(ndim-1) fine faces under each coarse face
+                    ia = [0, 1] if a < nd else [0]
+                    ib = [0, 1] if b < nd else [0]
+                    Rf = np.zeros((ps.nvar, cb_n, ca_n))
+                    for y in ib:
+                        for x in ia:
+                            Rf = Rf + R[:, y::len(ib), x::len(ia)][:, :cb_n, :ca_n]
+                    Rf = (Rf / float(len(ia) * len(ib))).reshape(ps.nvar, -1)
+                    sgn = 1.0 if side == 0 else -1.0
+                    dxc = self.ps.dx0[d] / 2 ** l
+                    for q in np.unique(owner[(owner >= 0) & ~covered]):
+                        sel = np.nonzero((owner == q) & ~covered)[0]
+                        qa = C3[sel, a] - int(ps.lo[q, a])
+                        qb = C3[sel, b] - int(ps.lo[q, b])
+                        fl = C3[sel, d] - int(ps.lo[q, d]) + (1 if side == 0 else 0)
+                        F1 = self._face_block(self.F1, q, d)[:, qb, qa, fl]
+                        F2 = self._face_block(self.F2, q, d)[:, qb, qa, fl]
+                        Rc = 0.5 * dtc * F1
+                        Rc = Rc + 0.5 * dtc * F2
+                        act = ps.active(U, q)
+                        cz, cy, cx = (C3[sel, 2] - int(ps.lo[q, 2]), C3[sel, 1] - int(ps.lo[q, 1]),
+                                      C3[sel, 0] - int(ps.lo[q, 0]))
+                        act[:, cz, cy, cx] = act[:, cz, cy, cx] + sgn * (Rc - Rf[:, sel]) / dxc
 
     def restrict(self, U, l):
-        """Covered coarse cells of level l become the mean of their 2^ndim children."""
+        """Covered coarse cells of level l become the mean of their 2^ndim children (summed
+        in the order z, y, x of the child offsets)."""
         ps = self.ps
         nd = ps.ndim
         for p in range(ps.npatch):
@@ -342,19 +384,26 @@ class AmrOracle:
             fine = ps.active(U, p)
             lo, n = ps.lo[p], ps.n[p]
             cn = [int(n[e]) // 2 if e < nd else 1 for e in range(3)]
-            for kz in range(cn[2]):
-                for jy in range(cn[1]):
-                    for ix in range(cn[0]):
-                        C3 = [(int(lo[0]) >> 1) + ix, (int(lo[1]) >> 1) + jy, (int(lo[2]) >> 1) + kz]
-                        q = self._patch_at(l, C3)
-                        acc = np.zeros(ps.nvar)
-                        for dz in (range(2) if nd > 2 else [0]):
-                            for dy in (range(2) if nd > 1 else [0]):
-                                for dx in range(2):
-                                    acc = acc + fine[:, 2 * kz + dz if nd > 2 else 0, 2 * jy + dy if nd > 1 else 0,
-                                                     2 * ix + dx]
-                        cell = [C3[e] - int(ps.lo[q, e]) for e in range(3)]
-                        ps.active(U, q)[:, cell[2], cell[1], cell[0]] = acc / float(2 ** nd)
+            acc = np.zeros((ps.nvar, cn[2], cn[1], cn[0]))
+            for dz in (range(2) if nd > 2 else [0]):
+                for dy in (range(2) if nd > 1 else [0]):
+                    for dx in range(2):
+                        acc = acc + fine[:, dz::2 if nd > 2 else 1, dy::2 if nd > 1 else 1, dx::2][
+                            :, :cn[2], :cn[1], :cn[0]]
+            mean = acc / float(2 ** nd)
+            # scatter into the level-l patches that hold the coarse footprint
+            clo = [int(lo[e]) >> 1 if e < nd else 0 for e in range(3)]
+            ids, qlo, qhi = self._level_boxes(l)
+            for q, l0, h0 in zip(ids, qlo, qhi):
+                blo = [max(clo[e], int(l0[e])) if e < nd else 0 for e in range(3)]
+                bhi = [min(clo[e] + cn[e], int(h0[e])) if e < nd else 1 for e in range(3)]
+                if any(bhi[e] <= blo[e] for e in range(3)):
+                    continue
+                dst = ps.active(U, q)
+                qo = [int(ps.lo[q, e]) if e < nd else 0 for e in range(3)]
+                dst[:, blo[2] - qo[2]:bhi[2] - qo[2], blo[1] - qo[1]:bhi[1] - qo[1], blo[0] - qo[0]:bhi[0] - qo[0]] = \
+                    mean[:, blo[2] - clo[2]:bhi[2] - clo[2], blo[1] - clo[1]:bhi[1] - clo[1],
+                         blo[0] - clo[0]:bhi[0] - clo[0]]
 
     # -------------------------------------------------------------- driver
     def cfl_dt0(self, U, cfl):
