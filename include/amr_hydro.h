@@ -341,6 +341,18 @@ amr_status amr_cluster_flags(const amr_patch_desc* patches, int32_t npatch, int3
 amr_status amr_patch_rk2_step_noalloc(const amr_patch_desc* patch, const amr_physics* phys, double* U,
                                       const double* dt_dev, int32_t* flag_dev, hipStream_t stream);
 
+/* Streaming ceiling, a measurement aid beside the update (not a step of it): out[i] =
+ * (a[i] + b[i]) / 2 for i < n, the HBM access pattern of the second RK stage (Sec. 4,
+ * RK2 combine: two arrays read, one written, each element once) with no other work, in
+ * one launch on `stream` (plus one for an odd last element).  Its bandwidth, 24 n bytes
+ * over its duration, is the practical ceiling the stage kernels' bandwidth is compared
+ * with.  a, b, out: caller-owned device arrays of n doubles, 16-byte aligned, out not
+ * overlapping a or b.  wg_per_cu: 0 = one workgroup per 2048 elements (a single pass),
+ * else a persistent grid of that many 256-lane workgroups per CU (at most 64).
+ * AMR_EINVAL for null or misaligned pointers, n < 1 or wg_per_cu out of range. */
+amr_status amr_stream_ceiling(const double* a, const double* b, double* out, int64_t n, int32_t wg_per_cu,
+                              hipStream_t stream);
+
 const char* amr_status_string(amr_status status);
 
 #ifdef __cplusplus

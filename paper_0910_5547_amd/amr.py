@@ -32,7 +32,8 @@ EXPORTED = ("amr_patch_table_create", "amr_patch_table_destroy", "amr_table_aren
             "amr_hydro_rk2_step", "amr_flux_correct", "amr_table_status", "amr_table_num_tilings",
             "amr_table_set_tiling", "amr_table_get_tiling", "amr_table_tiling_shape", "amr_autotune",
             "amr_table_last_stage_ms", "amr_hydro_advance", "amr_status_string", "amr_table_cells",
-            "amr_flag_cells", "amr_cluster_flags", "amr_regrid_fill", "amr_patch_rk2_step_noalloc")
+            "amr_flag_cells", "amr_cluster_flags", "amr_regrid_fill", "amr_patch_rk2_step_noalloc",
+            "amr_stream_ceiling")
 AMR_NOALLOC_SCRATCH_BYTES = 134217728
 
 
@@ -87,6 +88,7 @@ def lib():
         L.amr_table_cells.restype = i64
         L.amr_flag_cells.argtypes = [vp, vp, i32, C.c_double, vp, vp]
         L.amr_regrid_fill.argtypes = [vp, vp, vp, vp, vp]
+        L.amr_stream_ceiling.argtypes = [vp, vp, vp, i64, i32, vp]
         L.amr_patch_rk2_step_noalloc.argtypes = [C.POINTER(amr_patch_desc), C.POINTER(amr_physics), vp, vp, vp, vp]
         L.amr_cluster_flags.argtypes = [C.POINTER(amr_patch_desc), i32, i32, C.POINTER(i32), i32,
                                          C.POINTER(C.c_uint8), i32, i32, C.POINTER(i32), i32, C.POINTER(i32)]
@@ -281,6 +283,15 @@ def amr_patch_rk2_step_noalloc(desc, phys, U, dt_dev, flag_dev, stream=None):
     return _check(lib().amr_patch_rk2_step_noalloc(C.byref(desc), C.byref(phys), _ptr(U), _ptr(dt_dev),
                                                    C.c_void_p(flag_dev.data_ptr()), _stream(stream)),
                   "amr_patch_rk2_step_noalloc")
+
+
+def amr_stream_ceiling(a, b, out, n, wg_per_cu=0, stream=None):
+    """out[:n] = (a[:n] + b[:n]) / 2 on the device (the streaming ceiling's kernel)."""
+    for t in (a, b, out):
+        if t.numel() < n:
+            raise ValueError("arrays shorter than n")
+    return _check(lib().amr_stream_ceiling(_ptr(a), _ptr(b), _ptr(out), int(n), int(wg_per_cu), _stream(stream)),
+                  "amr_stream_ceiling")
 
 
 def amr_table_last_stage_ms(h):

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libamrhydro.so")
 OBJDIR = os.path.join(HERE, "_build")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in (
     "amr_stage_hydro_f32.hip", "amr_stage_hydro_f64.hip", "amr_stage_mhd.hip", "amr_stage_glm.hip",
-    "amr_kernels.hip", "amr_refine.hip", "amr_regrid.hip", "amr_api.hip", "amr_noalloc.hip", "amr_cluster.cpp")]
+    "amr_kernels.hip", "amr_refine.hip", "amr_regrid.hip", "amr_api.hip", "amr_noalloc.hip", "amr_stream.hip", "amr_cluster.cpp")]
 ARCH = os.environ.get("AMR_OFFLOAD_ARCH", "gfx950")
 
 
