@@ -421,6 +421,62 @@ int or_fill_ghosts_amr(int32_t np, const int32_t* meta, const int64_t* off, cons
   return 0;
 }
 
+/* ---------------------------------------------------------------- regrid */
+/* Fill the active cells of a new hierarchy (np patches, arena U) from an old one (npo
+ * patches, arena Uo) when the hierarchy is rebuilt (Sec. 3: the host rebuilds the grid
+ * hierarchy, and new fine grids take their data from the grids they replace, else from the
+ * coarser level).  Level by level from the root: a cell that an old patch of the same level
+ * holds is copied from it; any other cell is prolonged (the conservative minmod-linear
+ * interpolation of the ghost cells) from the new level below, whose ghost layers are filled
+ * first (siblings, physical boundaries, and coarser data for its own coarse/fine faces).
+ * Returns the number of cells that had no source (0 for a properly nested new root level
+ * covered by the old root). */
+int64_t or_regrid_fill(int32_t npo, const int32_t* meta_o, const int64_t* off_o, const double* Uo, int32_t np,
+                       const int32_t* meta, const int64_t* off, const or_phys* ph, double* U) {
+  int nlev = 0;
+  for (int p = 0; p < np; ++p)
+    if (meta[(size_t)p * OR_META] + 1 > nlev) nlev = meta[(size_t)p * OR_META] + 1;
+  int64_t missing = 0;
+  for (int l = 0; l < nlev; ++l) {
+    for (int p = 0; p < np; ++p) {
+      const int32_t* m = meta + (size_t)p * OR_META;
+      if (m[0] != l) continue;
+      geom G = get_geom(m, off[p], ph->ndim);
+      for (int k3 = 0; k3 < G.n[2]; ++k3)
+        for (int j = 0; j < G.n[1]; ++j)
+          for (int i = 0; i < G.n[0]; ++i) {
+            int c[3] = {i, j, k3}, L[3] = {0, 0, 0};
+            for (int e = 0; e < ph->ndim; ++e) L[e] = m[1 + e] + c[e];
+            int done = 0;
+            for (int q = 0; q < npo && !done; ++q) { /* an old patch of this level holding L */
+              const int32_t* mq = meta_o + (size_t)q * OR_META;
+              if (mq[0] != l) continue;
+              int inside = 1;
+              for (int e = 0; e < ph->ndim; ++e)
+                if (L[e] < mq[1 + e] || L[e] >= mq[1 + e] + mq[4 + e]) inside = 0;
+              if (!inside) continue;
+              geom Q = get_geom(mq, off_o[q], ph->ndim);
+              int cs[3] = {0, 0, 0};
+              for (int e = 0; e < ph->ndim; ++e) cs[e] = L[e] - mq[1 + e];
+              for (int k = 0; k < ph->nvar; ++k) U[at(&G, k, c)] = Uo[at(&Q, k, cs)];
+              done = 1;
+            }
+            if (!done && l > 0) {
+              double u[OR_NVMAX];
+              if (prolong_cell(np, meta, off, ph, U, U, 0.0, l, L, u)) {
+                for (int k = 0; k < ph->nvar; ++k) U[at(&G, k, c)] = u[k];
+                done = 1;
+              }
+            }
+            if (!done) ++missing;
+          }
+    }
+    /* this level's ghost layers, read by the next level's prolongation stencils */
+    or_fill_ghosts_amr(np, meta, off, ph, U, l, U, U, 0.0);
+  }
+  return missing;
+}
+
 /* ---------------------------------------------------------------- O2-O6 L(U) */
 int or_patch_L(const int32_t* m, int64_t off, const or_phys* ph, const double* V, double* L) {
   return or_patch_L_rec(m, off, ph, V, L, NULL);

@@ -107,6 +107,11 @@ int64_t or_flag_cells(int32_t np, const int32_t* meta, const int64_t* off, const
 double or_cfl_dt(int32_t np, const int32_t* meta, const int64_t* off, const or_phys* ph,
                  const double* U, double cfl, int32_t level);
 
+/* New hierarchy (np patches, arena U) filled from an old one (npo patches, arena Uo): per
+ * level from the root, copy from an old same-level patch, else prolong from the new level
+ * below (its ghosts filled first).  Returns the number of cells left without a source. */
+int64_t or_regrid_fill(int32_t npo, const int32_t* meta_o, const int64_t* off_o, const double* Uo, int32_t np,
+                       const int32_t* meta, const int64_t* off, const or_phys* ph, double* U);
 /* Threads of the oracle's parallel patch loops: 1 in the serial build. */
 int or_threads(void);
 

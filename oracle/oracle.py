@@ -66,6 +66,8 @@ def lib(parallel: bool = False):
         L.or_flag_cells.argtypes = [C.c_int32, ip, lp, pp, dp, C.c_int32, C.c_double, C.POINTER(C.c_uint8)]
         L.or_cfl_dt.restype = C.c_double
         L.or_cfl_dt.argtypes = [C.c_int32, ip, lp, pp, dp, C.c_double, C.c_int32]
+        L.or_regrid_fill.restype = C.c_int64
+        L.or_regrid_fill.argtypes = [C.c_int32, ip, lp, dp, C.c_int32, ip, lp, pp, dp]
         L.or_threads.restype = C.c_int
         L.or_threads.argtypes = []
         if parallel:
@@ -404,6 +406,16 @@ class AmrOracle:
                 dst[:, blo[2] - qo[2]:bhi[2] - qo[2], blo[1] - qo[1]:bhi[1] - qo[1], blo[0] - qo[0]:bhi[0] - qo[0]] = \
                     mean[:, blo[2] - clo[2]:bhi[2] - clo[2], blo[1] - clo[1]:bhi[1] - clo[1],
                          blo[0] - clo[0]:bhi[0] - clo[0]]
+
+    def regrid_fill(self, ps_old, U_old, U):
+        """Fill U (this hierarchy's arena) from U_old (arena of the hierarchy ps_old it replaces):
+        per level from the root, copy where an old patch of the level holds the cell, else
+        prolong from this hierarchy's level below.  Returns the number of cells without a source."""
+        mo = np.ascontiguousarray(ps_old.meta(), np.int32)
+        oo = np.ascontiguousarray(ps_old.offset, np.int64)
+        return int(lib().or_regrid_fill(ps_old.npatch, mo.ctypes.data_as(C.POINTER(C.c_int32)),
+                                         oo.ctypes.data_as(C.POINTER(C.c_int64)), _dp(U_old), *self._args(),
+                                         _dp(U)))
 
     # -------------------------------------------------------------- driver
     def cfl_dt0(self, U, cfl):
