@@ -208,11 +208,12 @@ int occupancy_grid(amr_table* t, int stage, int ntiles, bool rec);
 // minimises rounds x (slab + 4).  Levels with enough tiles keep whole patches.
 int auto_zslab(amr_table* t, int level, int shape) {
   if (t->ph.ndim != 3) return 1;
-  const int TX = SHAPE_TX[shape], TY = SHAPE_TY[shape];
   int64_t txy = 0;
   int nz = 1;
   for (const PatchDev& P : t->pdev) {
     if (level >= 0 && P.level != level) continue;
+    int TX, TY;
+    tile_dims(shape, P.n[0], TX, TY);
     txy += (int64_t)((P.n[0] + TX - 1) / TX) * ((P.n[1] + TY - 1) / TY);
     nz = std::max(nz, P.n[2]);
   }
@@ -238,9 +239,10 @@ int default_zslab(const amr_table* t) { return t->ph.ndim == 3 ? 0 : 1; }  // 0 
 int default_shape(const amr_table* t) {
   if (t->ph.ndim == 1) return 0;
   auto lane_use = [&](int shape) {
-    const int TX = SHAPE_TX[shape], TY = SHAPE_TY[shape];
     double cols = 0, lanes = 0;
     for (const PatchDev& P : t->pdev) {
+      int TX, TY;
+      tile_dims(shape, P.n[0], TX, TY);
       cols += (double)P.n[0] * P.n[1] * P.n[2];
       lanes += (double)((P.n[0] + TX - 1) / TX) * ((P.n[1] + TY - 1) / TY) * TX * TY * P.n[2];
     }
@@ -262,7 +264,6 @@ amr_status get_tiles(amr_table* t, int level, int shape, int zslab, TileSet** ou
     *out = &it->second;
     return AMR_OK;
   }
-  const int TX = SHAPE_TX[shape], TY = SHAPE_TY[shape];
   std::vector<Tile> list;
   TileSet ts;
   ts.first.assign(t->pdev.size(), 0);
@@ -271,6 +272,8 @@ amr_status get_tiles(amr_table* t, int level, int shape, int zslab, TileSet** ou
     const PatchDev& P = t->pdev[p];
     ts.first[p] = (int)list.size();
     if (level >= 0 && P.level != level) continue;
+    int TX, TY;
+    tile_dims(shape, P.n[0], TX, TY);
     const int zs = std::min(zslab, P.n[2]);
     for (int z0 = 0; z0 < P.n[2]; z0 += zs)
       for (int y0 = 0; y0 < P.n[1]; y0 += TY)
@@ -281,6 +284,7 @@ amr_status get_tiles(amr_table* t, int level, int shape, int zslab, TileSet** ou
           T.y0 = y0;
           T.z0 = z0;
           T.z1 = std::min(z0 + zs, P.n[2]);
+          T.tx = TX;
           list.push_back(T);
         }
     ts.count[p] = (int)list.size() - ts.first[p];

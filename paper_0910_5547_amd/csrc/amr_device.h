@@ -55,7 +55,7 @@ struct PatchDev {
 // One unit of stage-kernel work: a TX x TY column block of one patch, marched
 // over planes z0 <= z < z1.
 struct Tile {
-  int patch, x0, y0, z0, z1, pad0, pad1, pad2;
+  int patch, x0, y0, z0, z1, tx, pad1, pad2;  // tx: the tile's width (TX of its shape)
 };
 
 // Same-level ghost copy: dst ghost cells in box [lo, lo+sz) (dst active-relative

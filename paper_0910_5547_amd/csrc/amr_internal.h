@@ -28,7 +28,7 @@ struct CflArgs {
   const double* U;
   const PatchDev* patches;
   const Tile* tiles;
-  int ntiles, tx, ty, fast;         // fast: the mixed path's evaluation of the CFL rule
+  int ntiles, tx, ty, fast;         // tx 0: each tile carries its width (Tile::tx); fast: the mixed CFL rule
   int nv;                           // conserved variables (5 hydro, 8 MHD)
   int* flag;
   unsigned long long* smax;      // per-level maxima
@@ -98,18 +98,34 @@ hipError_t launch_flag_cells(hipStream_t s, const int* plist, const int64_t* cof
 // shape 6, which cut the y-halo share of a tile); 8 x 8 (shape 4, small patches):
 // one tile per wavefront, four per workgroup.  Every shape has at most one halo
 // cell and one edge face per lane.
-constexpr int NSHAPES = 7;
-constexpr int SHAPE_TX[NSHAPES] = {256, 32, 64, 16, 8, 32, 32};
-constexpr int SHAPE_TY[NSHAPES] = {1, 8, 4, 16, 8, 16, 12};
-constexpr int SHAPE_NT[NSHAPES] = {256, 256, 256, 256, 256, 512, 384};
+// Shape 7 (patch-fit, SHAPE_TX = SHAPE_TY = 0): 256-lane tiles whose width follows the
+// patch, tx = 8, 16 or 32 for n_x up to 8, 16 or more, height 256 / tx, so that patches
+// 8 or 16 cells wide fill the lanes that 32-wide tiles leave idle.
+constexpr int NSHAPES = 8;
+constexpr int SHAPE_TX[NSHAPES] = {256, 32, 64, 16, 8, 32, 32, 0};
+constexpr int SHAPE_TY[NSHAPES] = {1, 8, 4, 16, 8, 16, 12, 0};
+constexpr int SHAPE_NT[NSHAPES] = {256, 256, 256, 256, 256, 512, 384, 256};
 constexpr int SHAPE_SMALL = 4;
-constexpr int shape_tiles_per_wg(int shape) { return SHAPE_NT[shape] / (SHAPE_TX[shape] * SHAPE_TY[shape]); }
-// Shapes compiled for MHD (8 variables): 1D, 32 x 8 and 8 x 8 in both precisions;
+constexpr int SHAPE_FIT = 7;
+constexpr int shape_tiles_per_wg(int shape) {
+  return shape == SHAPE_FIT ? 1 : SHAPE_NT[shape] / (SHAPE_TX[shape] * SHAPE_TY[shape]);
+}
+// Tile width and height of a shape on a patch n_x cells wide.
+inline void tile_dims(int shape, int nx, int& tx, int& ty) {
+  if (shape == SHAPE_FIT) {
+    tx = nx <= 8 ? 8 : nx <= 16 ? 16 : 32;
+    ty = NT / tx;
+  } else {
+    tx = SHAPE_TX[shape];
+    ty = SHAPE_TY[shape];
+  }
+}
+// Shapes compiled for MHD (8 variables): 1D, 32 x 8, 8 x 8 and patch-fit in both precisions;
 // 32 x 16 and 32 x 12 in FP32 only (in FP64 the primitive plane and face states of
 // eight variables exceed the LDS of a workgroup, or leave one workgroup per CU
 // that spills registers).
 constexpr bool mhd_shape_ok(int mixed, int shape) {
-  return shape == 0 || shape == 1 || shape == 4 || ((shape == 5 || shape == 6) && mixed);
+  return shape == 0 || shape == 1 || shape == 4 || shape == SHAPE_FIT || ((shape == 5 || shape == 6) && mixed);
 }
 
 // Host helpers shared by the table (amr_api.hip) and the allocation-free step

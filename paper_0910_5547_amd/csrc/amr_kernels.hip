@@ -17,7 +17,8 @@ __global__ __launch_bounds__(NT) void cfl_kernel(CflArgs a) {
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const Tile T = a.tiles[t];
     const PatchDev P = a.patches[T.patch];
-    const int nxT = min(a.tx, P.n[0] - T.x0), nyT = min(a.ty, P.n[1] - T.y0);
+    const int tx = a.tx > 0 ? a.tx : T.tx, ty = a.tx > 0 ? a.ty : NT / tx;  // tx 0: the tile's own width
+    const int nxT = min(tx, P.n[0] - T.x0), nyT = min(ty, P.n[1] - T.y0);
     const int per_plane = nxT * nyT;
     const int ncell = per_plane * (T.z1 - T.z0);
     double smax = 0.0;

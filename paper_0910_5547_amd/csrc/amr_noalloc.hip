@@ -66,6 +66,7 @@ __global__ void noalloc_tiles(PatchDev P, PatchDev* pd, Tile* tiles, int L, int 
   T.y0 = yb * TY;
   T.z0 = zb * zs;
   T.z1 = min(T.z0 + zs, P.n[2]);
+  T.tx = TX;
   tiles[i] = T;
 }
 

@@ -59,17 +59,21 @@ template <typename RT, int NV, int TX, int TY, int NTH, int STAGE, bool REC, boo
 __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(
     NV >= NVAR_MHD ? (Fast<RT>::value ? 2 : 1) : (Fast<RT>::value && !REC && NTH != 512 ? 3 : 2))))
 void stage_kernel(StageArgs a) {
-  constexpr int TL = TX * TY;  // lanes (columns) per tile
+  // TX = TY = 0: patch-fit tiles of 256 columns whose width tx (8, 16 or 32) each tile
+  // carries (Tile::tx), its height 256 / tx; the LDS is sized for the largest plane
+  constexpr bool VARW = TX == 0;
+  static_assert(!VARW || NTH == NT, "patch-fit tiles are whole 256-lane workgroups");
+  constexpr int TL = VARW ? NTH : TX * TY;  // lanes (columns) per tile
   static_assert(TL == NTH || TL == 64, "a tile is the workgroup or one wavefront");
   constexpr int WPB = NTH / TL;  // tiles in flight per workgroup
   constexpr bool FAST = Fast<RT>::value;
-  constexpr bool HASY = TY > 1;          // 1D tiles carry no y rows
-  constexpr int PR = HASY ? TY + 4 : 1;  // LDS rows of the primitive plane
+  constexpr bool HASY = VARW || TY > 1;  // 1D tiles carry no y rows
   constexpr int RO = HASY ? 2 : 0;       // row offset of tile row 0
-  constexpr int YR = HASY ? TY + 1 : 1;  // y-face rows
-  constexpr int HMAX = HASY ? (4 * (TX + TY) + TL - 1) / TL : 1;  // halo cells per lane
+  // LDS plane: (ty + 4) rows of tx + 4 cells (tx x ty = 8 x 32, 16 x 16 or 32 x 8 when VARW)
+  constexpr int PLANE = VARW ? 36 * 12 : (HASY ? TY + 4 : 1) * (TX + 4);
+  constexpr int HMAX = VARW ? (4 * 40 + TL - 1) / TL : HASY ? (4 * (TX + TY) + TL - 1) / TL : 1;  // halo cells per lane
   // face slots: x faces first, slot row*(nxT+1) + f, then y faces, slot nfx + f*nxT + col
-  constexpr int NSLOT = TY * (TX + 1) + (HASY ? YR * TX : 0);
+  constexpr int NSLOT = VARW ? 32 * 9 + 33 * 8 : TY * (TX + 1) + (HASY ? (TY + 1) * TX : 0);
   // SB (512-lane tiles, one workgroup per CU: FP32 reconstruction, and FP64 hydro in
   // stage 1, its stage 2 being short of registers for it): one workgroup barrier per
   // plane instead of three.
@@ -79,7 +83,7 @@ void stage_kernel(StageArgs a) {
   // k+1's primitives go to LDS during plane k's face pass.
   constexpr bool SB = WPB == 1 && NTH == 512 && (Fast<RT>::value || (NV == NVAR && STAGE == 1));
   constexpr int PB = SB ? 2 : WPB;
-  __shared__ RT sP[PB][NV][PR][TX + 4];  // primitives of the plane (+ face halo)
+  __shared__ RT sP[PB][NV][PLANE];  // primitives of the plane (+ face halo), rows of tx + 4
   // face states; sFL then holds the flux (SB: the flux only)
   __shared__ RT sFL[PB][NV][NSLOT], sFR[SB ? 1 : WPB][NV][SB ? 1 : NSLOT];
   // conserved state of this lane's cell in planes k and k+1 (3D), for the update:
@@ -96,7 +100,7 @@ void stage_kernel(StageArgs a) {
   const int kind = C.flux;
   const int sub = WPB == 1 ? 0 : (int)threadIdx.x / TL;  // this lane's tile slot in the workgroup
   const int tid = WPB == 1 ? (int)threadIdx.x : (int)threadIdx.x % TL;  // lane in the tile
-  const int cx = tid % TX, cy = tid / TX;
+  int cx = VARW ? 0 : tid % TX, cy = VARW ? 0 : tid / TX;
   auto tile_sync = [] {
     if constexpr (WPB == 1) {
       __syncthreads();
@@ -114,8 +118,16 @@ void stage_kernel(StageArgs a) {
   for (int t = blockIdx.x * WPB + sub; t < a.ntiles; t += gridDim.x * WPB) {
     const Tile T = a.tiles[t];
     const PatchDev P = a.patches[T.patch];
-    const int nxT = min(TX, P.n[0] - T.x0);
-    const int nyT = HASY ? min(TY, P.n[1] - T.y0) : 1;
+    const int tx = VARW ? T.tx : TX;        // tile width (a power of two when VARW)
+    const int ty = VARW ? TL / tx : TY;
+    const int pitch = tx + 4;                 // LDS row length of the plane
+    if constexpr (VARW) {
+      const int lg = __builtin_ctz(tx);
+      cx = tid & (tx - 1);
+      cy = tid >> lg;
+    }
+    const int nxT = min(tx, P.n[0] - T.x0);
+    const int nyT = HASY ? min(ty, P.n[1] - T.y0) : 1;
     const bool act = cx < nxT && cy < nyT;
     const int i = T.x0 + cx, j = T.y0 + cy;
     const bool hasz = C.ndim == 3;
@@ -234,7 +246,7 @@ void stage_kernel(StageArgs a) {
     //  * one face on the tile's high x or high y edge (lanes < nfe).
     // Face slots: x faces row * (nxT + 1) + f, then y faces nfx + f * nxT + col.
     const int nfx = (nxT + 1) * nyT;
-    const int pc_own = (cy + RO) * (TX + 4) + cx + 2;
+    const int pc_own = (cy + RO) * pitch + cx + 2;
     const int xs_own = cy * (nxT + 1) + cx, ys_own = nfx + cy * nxT + cx;
     const int nhs = 2 * nyT + (HASY ? 2 * nxT : 0);
     int pc_h = 0, st_h = 1, slot_h = 0;
@@ -242,13 +254,13 @@ void stage_kernel(StageArgs a) {
     if (tid < nhs) {
       if (tid < 2 * nyT) {  // columns -1 and nxT
         const int row = tid >> 1, hi = tid & 1;
-        pc_h = (row + RO) * (TX + 4) + (hi ? nxT : -1) + 2;
+        pc_h = (row + RO) * pitch + (hi ? nxT : -1) + 2;
         slot_h = row * (nxT + 1) + (hi ? nxT : 0);
         left_h = !hi;
       } else {  // rows -1 and nyT
         const int q = tid - 2 * nyT, col = q >> 1, hi = q & 1;
-        pc_h = ((hi ? nyT : -1) + RO) * (TX + 4) + col + 2;
-        st_h = TX + 4;
+        pc_h = ((hi ? nyT : -1) + RO) * pitch + col + 2;
+        st_h = pitch;
         slot_h = nfx + (hi ? nyT : 0) * nxT + col;
         left_h = !hi;
       }
@@ -259,11 +271,11 @@ void stage_kernel(StageArgs a) {
     if (tid < nfe) {
       if (tid < nyT) {
         slot_e = tid * (nxT + 1) + nxT;
-        pc_e = (tid + RO) * (TX + 4) + nxT + 2;
+        pc_e = (tid + RO) * pitch + nxT + 2;
       } else {
         slot_e = nfx + nyT * nxT + (tid - nyT);
-        pc_e = (nyT + RO) * (TX + 4) + (tid - nyT) + 2;
-        st_e = TX + 4;
+        pc_e = (nyT + RO) * pitch + (tid - nyT) + 2;
+        st_e = pitch;
         ydir_e = true;
       }
     }
@@ -278,7 +290,7 @@ void stage_kernel(StageArgs a) {
           if (hflip[s] == 2) reflect_flip<NV>(Hn[s], 1);
           bad |= cons2prim<RT, NV>(Hn[s], C, q);
 #pragma unroll
-          for (int v = 0; v < NV; ++v) sP[pb][v][hrow[s] + RO][hcol[s] + 2] = q[v];
+          for (int v = 0; v < NV; ++v) sP[pb][v][(hrow[s] + RO) * pitch + hcol[s] + 2] = q[v];
           if (k + 1 < T.z1) load_halo(s, k + 1, Hn[s]);
         }
       }
@@ -286,7 +298,7 @@ void stage_kernel(StageArgs a) {
     auto own_to_lds = [&](const RT qc[NV], int pb) {
       if (act) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sP[pb][v][cy + RO][cx + 2] = qc[v];
+        for (int v = 0; v < NV; ++v) sP[pb][v][(cy + RO) * pitch + cx + 2] = qc[v];
       }
     };
     if constexpr (SB) {  // plane z0 into LDS ahead of the plane loop
@@ -365,13 +377,13 @@ void stage_kernel(StageArgs a) {
         if (act) {
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
-            const RT* pl = &sP[fb][v][0][0];
+            const RT* pl = &sP[fb][v][0];
             const RT q0 = pl[pc_own];
             const RT sx = plm_slope_t<RT, TH1>(pl[pc_own - 1], q0, pl[pc_own + 1], theta);
             sFR[fb][v][xs_own] = madd(RT(-0.5), sx, q0);     // right state of its low x face
             sFL[fb][v][xs_own + 1] = madd(RT(0.5), sx, q0);  // left state of its high x face
             if constexpr (HASY) {
-              const RT sy = plm_slope_t<RT, TH1>(pl[pc_own - (TX + 4)], q0, pl[pc_own + (TX + 4)], theta);
+              const RT sy = plm_slope_t<RT, TH1>(pl[pc_own - pitch], q0, pl[pc_own + pitch], theta);
               sFR[fb][v][ys_own] = madd(RT(-0.5), sy, q0);
               sFL[fb][v][ys_own + nxT] = madd(RT(0.5), sy, q0);
             }
@@ -382,7 +394,7 @@ void stage_kernel(StageArgs a) {
           const RT hs = left_h ? RT(0.5) : RT(-0.5);
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
-            const RT* pl = &sP[fb][v][0][0];
+            const RT* pl = &sP[fb][v][0];
             const RT q0 = pl[pc_h];
             const RT sg = plm_slope_t<RT, TH1>(pl[pc_h - st_h], q0, pl[pc_h + st_h], theta);
             dst[v * NSLOT] = madd(hs, sg, q0);
@@ -403,7 +415,7 @@ void stage_kernel(StageArgs a) {
         auto face_states = [&](int pc, int st, RT qL[NV], RT qR[NV]) {
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
-            const RT* pl = &sP[fb][v][0][0];
+            const RT* pl = &sP[fb][v][0];
             const RT a0 = pl[pc - 2 * st], a1 = pl[pc - st], a2 = pl[pc], a3 = pl[pc + st];
             qL[v] = madd(RT(0.5), plm_slope_t<RT, TH1>(a0, a1, a2, theta), a1);
             qR[v] = madd(RT(-0.5), plm_slope_t<RT, TH1>(a1, a2, a3, theta), a2);
@@ -416,7 +428,7 @@ void stage_kernel(StageArgs a) {
 #pragma unroll
           for (int v = 0; v < NV; ++v) sFL[fb][v][xs_own] = F[v];
           if constexpr (HASY) {
-            face_states(pc_own, TX + 4, qL, qR);
+            face_states(pc_own, pitch, qL, qR);
             riemann_flux_xy<RT, NV>(qL, qR, true, K, kind, F);
 #pragma unroll
             for (int v = 0; v < NV; ++v) sFL[fb][v][ys_own] = F[v];
@@ -610,6 +622,7 @@ inline hipError_t launch_stage_mhd_rt(int shape, int stage, dim3 grid, hipStream
     case 0: return launch_stage_s<RT, NV, 256, 1>(stage, grid, s, a);
     case 1: return launch_stage_s<RT, NV, 32, 8>(stage, grid, s, a);
     case 4: return launch_stage_s<RT, NV, 8, 8>(stage, grid, s, a);
+    case SHAPE_FIT: return launch_stage_s<RT, NV, 0, 0>(stage, grid, s, a);
     case 5:
       if constexpr (Fast<RT>::value) return launch_stage_s<RT, NV, 32, 16, 512>(stage, grid, s, a);
       else return hipErrorInvalidValue;
@@ -635,6 +648,7 @@ inline const void* stage_kernel_ptr_mhd_t(int mixed, int shape, int stage, bool 
       case 0: return stage_kernel_ptr_s<float, NV, 256, 1>(stage, rec);
       case 1: return stage_kernel_ptr_s<float, NV, 32, 8>(stage, rec);
       case 4: return stage_kernel_ptr_s<float, NV, 8, 8>(stage, rec);
+      case SHAPE_FIT: return stage_kernel_ptr_s<float, NV, 0, 0>(stage, rec);
       case 5: return stage_kernel_ptr_s<float, NV, 32, 16, 512>(stage, rec);
       case 6: return stage_kernel_ptr_s<float, NV, 32, 12, 384>(stage, rec);
     }
@@ -643,6 +657,7 @@ inline const void* stage_kernel_ptr_mhd_t(int mixed, int shape, int stage, bool 
       case 0: return stage_kernel_ptr_s<double, NV, 256, 1>(stage, rec);
       case 1: return stage_kernel_ptr_s<double, NV, 32, 8>(stage, rec);
       case 4: return stage_kernel_ptr_s<double, NV, 8, 8>(stage, rec);
+      case SHAPE_FIT: return stage_kernel_ptr_s<double, NV, 0, 0>(stage, rec);
     }
   }
   return nullptr;
@@ -659,6 +674,7 @@ inline hipError_t launch_stage_hydro_t(int shape, int stage, int grid, hipStream
     case 4: return launch_stage_s<RT, NVAR, 8, 8>(stage, dim3(grid), s, a);
     case 5: return launch_stage_s<RT, NVAR, 32, 16, 512>(stage, dim3(grid), s, a);
     case 6: return launch_stage_s<RT, NVAR, 32, 12, 384>(stage, dim3(grid), s, a);
+    case SHAPE_FIT: return launch_stage_s<RT, NVAR, 0, 0>(stage, dim3(grid), s, a);
     default: return hipErrorInvalidValue;
   }
 }
@@ -673,6 +689,7 @@ inline const void* stage_kernel_ptr_hydro_t(int shape, int stage, bool rec) {
     case 4: return stage_kernel_ptr_s<RT, NVAR, 8, 8>(stage, rec);
     case 5: return stage_kernel_ptr_s<RT, NVAR, 32, 16, 512>(stage, rec);
     case 6: return stage_kernel_ptr_s<RT, NVAR, 32, 12, 384>(stage, rec);
+    case SHAPE_FIT: return stage_kernel_ptr_s<RT, NVAR, 0, 0>(stage, rec);
     default: return nullptr;
   }
 }

@@ -99,7 +99,7 @@ def test_brio_wu_to_t01_fp64(env, exe):
     compare(ps, Ug, Uo, bitwise=True, what=f"brio-wu exec={exe} steps={n}")
 
 
-@pytest.mark.parametrize("shape", [1, 4])
+@pytest.mark.parametrize("shape", [1, 4, 7])
 @pytest.mark.parametrize("bcs", [
     [W.BC_PERIODIC] * 6,
     [W.BC_REFLECT, W.BC_OUTFLOW, W.BC_PERIODIC, W.BC_PERIODIC, W.BC_OUTFLOW, W.BC_REFLECT],
@@ -113,7 +113,7 @@ def test_ragged_3d_boundaries_fp64(env, bcs, shape):
     compare(ps, Ug, Uo, bitwise=True, what=f"mhd ragged shape={shape}")
 
 
-@pytest.mark.parametrize("shape", [1, 4])
+@pytest.mark.parametrize("shape", [1, 4, 7])
 def test_two_dimensional_fp64(env, shape):
     log(f"case mhd 2d shape={shape}")
     ps, U = _random_mhd([[45, 29, 1]], [W.BC_PERIODIC, W.BC_PERIODIC, W.BC_REFLECT, W.BC_OUTFLOW, 0, 0],
@@ -176,7 +176,7 @@ def test_zero_field_equals_hydro_library(env):
 
 
 # ------------------------------------------------------------------ mixed precision
-@pytest.mark.parametrize("shape", [1, 4, 5, 6])
+@pytest.mark.parametrize("shape", [1, 4, 5, 6, 7])
 def test_mixed_l1_and_conservation(env, shape):
     torch, A, O = env
     log(f"case mhd mixed shape={shape}")

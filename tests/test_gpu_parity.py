@@ -123,6 +123,26 @@ def test_boundary_mix_ragged_3d(env, bcs):
     compare(ps, Ug, Uo, bitwise=True, what="bcmix")
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_patch_fit_tiles_on_ragged_widths(env, prec):
+    """Patch-fit tiles (shape 7: width 8, 16 or 32 chosen per patch, height 256 / width) on
+    widths below, at and between those sizes, with every on-the-fly boundary condition:
+    FP64 bitwise against the oracle, mixed bitwise equal to the default tiling's."""
+    torch, A, O = env
+    bcs = [W.BC_REFLECT, W.BC_OUTFLOW, W.BC_PERIODIC, W.BC_PERIODIC, W.BC_OUTFLOW, W.BC_REFLECT]
+    n = [[5, 40, 9], [8, 8, 8], [11, 33, 6], [16, 17, 12], [23, 9, 7], [32, 24, 10], [37, 70, 5]]
+    ps = W.make_patchset(3, n, 3, bcs, gamma=5 / 3, dx0=(0.03, 0.05, 0.04))
+    U = W.random_state(ps, 17, shocks=0.5)
+    log(f"case patch-fit ragged prec={prec}")
+    if prec == 0:
+        Ug, Uo = run_pair(env, ps, U, 3, tiling=(7, 0))
+        compare(ps, Ug, Uo, bitwise=True, what="patch-fit ragged")
+    else:
+        Ug, _ = run_pair(env, ps, U, 3, prec=1, tiling=(7, 0), check_dt=False)
+        Ud, _ = run_pair(env, ps, U, 3, prec=1, check_dt=False)
+        assert np.array_equal(active_all(ps, Ug), active_all(ps, Ud))
+
+
 def test_two_dimensional(env):
     log("case 2d")
     ps = W.make_patchset(2, [[70, 45, 1]], 2, [W.BC_PERIODIC] * 2 + [W.BC_REFLECT] * 2 + [0, 0], gamma=5 / 3,
@@ -158,7 +178,7 @@ def test_two_dimensional_every_tiling(env, prec):
             assert np.array_equal(out, ref), sh
 
 
-@pytest.mark.parametrize("shape", [None, 1, 4, 5])
+@pytest.mark.parametrize("shape", [None, 1, 4, 5, 7])
 @pytest.mark.parametrize("bcs", [
     [W.BC_OUTFLOW] * 6,
     [W.BC_REFLECT, W.BC_OUTFLOW, W.BC_PERIODIC, W.BC_PERIODIC, W.BC_OUTFLOW, W.BC_REFLECT],

@@ -90,3 +90,31 @@ def test_regrid_copies_old_fine_cells_and_conserves(env, nvar):
     tA, tB = W.composite_totals(psA, UA), W.composite_totals(psB, UB)
     scale = W.composite_totals(psA, np.abs(UA))
     assert np.all(np.abs(tB - tA) <= 1e-13 * scale), (tB - tA) / scale
+
+
+@pytest.mark.parametrize("nvar", [5, 8, 9])
+def test_regrid_matches_the_oracle_cell_by_cell(env, nvar):
+    """A three-level hierarchy on a nonlinear periodic field rebuilt with moved level-1 and
+    level-2 patches: every new active cell (copied where an old patch of its level holds
+    it, else prolonged from the new level below, itself partly prolonged) equals the
+    oracle's regrid of the same hierarchies."""
+    from oracle import oracle as O
+    from tests.gpu_util import active_all, rel_err
+    torch, A = env
+    log(f"case regrid vs oracle nvar={nvar}")
+    psA, UA, per, dom = W.nested_box(Nc=16, boxes=((4, 12), (14, 20)), seed=55, nvar=nvar)
+    # new level 1 over root cells [6, 14), new level 2 over its cells [15, 23): overlapping the
+    # old patches of their levels and sticking out of them
+    n = [list(psA.n[0]), [16, 16, 16], [16, 16, 16]]
+    lo = [list(psA.lo[0]), [12, 12, 12], [30, 30, 30]]
+    psB = W.make_patchset(3, n, int(psA.ng[0]), [W.BC_EXTERNAL] * 6, level=[0, 1, 2], lo=lo, gamma=psA.gamma,
+                          dx0=psA.dx0, nvar=nvar)
+    ch = 1.0 if nvar == 9 else 0.0
+    UB = _fill(env, psA, UA, psB, dict(periodic=per, domain=dom, ch=ch))
+    Uo = W.new_arena(psB)
+    missing = O.AmrOracle(psB, periodic=per, domain=dom, ch=ch).regrid_fill(psA, UA, Uo)
+    assert missing == 0
+    g, r = active_all(psB, UB), active_all(psB, Uo)
+    e = rel_err(g, r)
+    log(f"regrid nvar={nvar}: max rel err {max(e):.1e}, bitwise={np.array_equal(g, r)}")
+    assert max(e) <= 1e-14
