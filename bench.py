@@ -13,6 +13,8 @@ Workloads (seeded, synthetic; see paper_0910_5547_amd.workloads):
   box256       256^3 periodic box, gamma 5/3, GRF density (k^-2, 1<=|k|<=16),
                Mach 0.5 GRF velocities, p = 1 (one patch; timed by default as an
                extra key of the same line)
+  patches4000-g0  the same 4000 patches stored without ghost layers (ng = 0, their
+               faces applied by index maps): timed by default as an extra key
   sedov        deep-AMR octant Sedov hierarchy (7 levels, subcycled root steps)
   glm192       the mhd192 box with the GLM cleaning field (9 variables, c_h = 3)
   sedovN       centred blast on a uniform N^3 grid (one patch); mhdsedovN: the same
@@ -155,14 +157,29 @@ def summarize_pmc(fetch_csv, write_csv, workload, form, cells, nvar=5):
 
 
 def make_workload(name):
-    """(PatchSet, U, description, extra Table arguments) of a named workload."""
+    """(PatchSet, U, description, extra Table arguments) of a named workload.  A name ending
+    in "-g0" stores the same patches without ghost layers (ng = 0: faces applied by index
+    maps or read from same-shaped siblings; boxes and independent patches only)."""
+    from paper_0910_5547_amd import workloads as W
+    if name.endswith("-g0"):
+        ps, U, desc, kw = make_workload_ng(name[:-3], 0)
+        return ps, U, desc.replace("ng=3", "ng=0").replace("ng=2", "ng=0") + "; no ghost layers stored", kw
+    return make_workload_ng(name, None)
+
+
+def make_workload_ng(name, ng):
     from paper_0910_5547_amd import workloads as W
     kw = {}
+    g = {} if ng is None else {"ng": ng}
+    if name in ("box256", "patches4000", "mhd192", "glm192") or name.startswith("box"):
+        pass
+    elif ng is not None:
+        raise SystemExit(f"workload {name} has no ghost-free form")
     if name == "box256":
-        ps, U = W.periodic_turbulent_box(N=256, seed=20)
+        ps, U = W.periodic_turbulent_box(N=256, seed=20, **g)
         desc = "periodic box 256^3, gamma=5/3, rho=1+0.1 GRF(k^-2, 1<=|k|<=16, seed 20), Mach 0.5 GRF velocities, p=1"
     elif name == "patches4000":
-        ps, U = W.uneven_patches(npatch=4000, seed=30)
+        ps, U = W.uneven_patches(npatch=4000, seed=30, **g)
         desc = "4000 patches, n_d in {8,16,24,32} (seed 30), ng=3, outflow, smooth states + 20% planar shocks"
     elif name == "sedov":
         ps, U, _, _ = W.sedov_hierarchy()
@@ -172,13 +189,13 @@ def make_workload(name):
                 f"{ps.npatch} patches of 8..32 cells per dimension, subcycled with refluxing, "
                 f"floors rho {kw['rho_floor']:g} e {kw['e_floor']:g}")
     elif name == "mhd192":
-        ps, U = W.mhd_vortex_box(N=192, patch=32, seed=50)
+        ps, U = W.mhd_vortex_box(N=192, patch=32, seed=50, **g)
         kw = dict(periodic=7, domain=(192, 192, 192))
         desc = ("ideal MHD (8 variables), 192^3 periodic as 216 patches of 32^3 (EXTERNAL faces, ng=3), "
                 "gamma=5/3, rho=25/(36 pi), p=5/(12 pi), v=(-sin 2 pi y, sin 2 pi x, 0), B=curl A with "
                 "A=GRF(k^-2, 1<=|k|<=4, seeds 50-52), beta=1.7")
     elif name == "glm192":
-        ps8, U8 = W.mhd_vortex_box(N=192, patch=32, seed=50)
+        ps8, U8 = W.mhd_vortex_box(N=192, patch=32, seed=50, **g)
         ps = W.make_patchset(3, ps8.n, ps8.ng, ps8.bc, lo=ps8.lo, gamma=ps8.gamma, dx0=ps8.dx0, nvar=W.NVAR_GLM)
         U = W.new_arena(ps)
         for p in range(ps.npatch):
@@ -200,25 +217,25 @@ def make_workload(name):
     elif name.startswith("box") and "p" in name[3:]:
         # boxNpP: the N^3 periodic box as (N/P)^3 patches of P^3 with EXTERNAL faces
         N, P = (int(x) for x in name[3:].split("p"))
-        ps, U = W.periodic_turbulent_box(N=N, seed=20, kmax=min(16.0, N / 4), patch=P, ng=3)
+        ps, U = W.periodic_turbulent_box(N=N, seed=20, kmax=min(16.0, N / 4), patch=P, ng=g.get("ng", 3))
         kw = dict(periodic=7, domain=(N, N, N))
         desc = f"periodic box {N}^3 as {(N // P) ** 3} patches of {P}^3 (EXTERNAL faces, ng=3)"
     elif name.startswith("box"):
         N = int(name[3:])
-        ps, U = W.periodic_turbulent_box(N=N, seed=20, kmax=min(16.0, N / 4))
+        ps, U = W.periodic_turbulent_box(N=N, seed=20, kmax=min(16.0, N / 4), **g)
         desc = f"periodic box {N}^3"
     else:
         raise SystemExit(f"unknown workload {name}")
     return ps, U, desc, kw
 
 
-def time_hierarchy(A, torch, ps, U, precision, exec_form, steps, warmup, kw, shape=None):
+def time_hierarchy(A, torch, ps, U, precision, exec_form, steps, warmup, kw, shape=None, zslab=0):
     """Root steps of a subcycled hierarchy: CFL reduction (all levels) + amr_hydro_advance.
     The stage split is not measured here (a root step launches every level's stages);
     stage_ms halves the whole step."""
     T = A.Table(ps, precision=precision, exec_form=exec_form, **kw)
     if shape is not None:
-        A.amr_table_set_tiling(T.h, shape, 0)
+        A.amr_table_set_tiling(T.h, shape, zslab)
     Ud = T.upload(U)
     for _ in range(warmup):
         A.amr_cfl_dt(T.h, Ud, 0.8, -1, T.dt)
@@ -245,12 +262,12 @@ def time_hierarchy(A, torch, ps, U, precision, exec_form, steps, warmup, kw, sha
             "tiling": list(tiling), "tile": tile}
 
 
-def time_form(A, torch, ps, U, precision, exec_form, steps, warmup, kw, tune=True, shape=None):
+def time_form(A, torch, ps, U, precision, exec_form, steps, warmup, kw, tune=True, shape=None, zslab=0):
     if int(ps.level.max()) > 0:
-        return time_hierarchy(A, torch, ps, U, precision, exec_form, steps, warmup, kw, shape)
+        return time_hierarchy(A, torch, ps, U, precision, exec_form, steps, warmup, kw, shape, zslab)
     T = A.Table(ps, precision=precision, exec_form=exec_form, **kw)
     if shape is not None:
-        A.amr_table_set_tiling(T.h, shape, 0)
+        A.amr_table_set_tiling(T.h, shape, zslab)
     Ud = T.upload(U)
     T.cfl_dt(Ud, 0.8)
     if tune and shape is None and exec_form == A.AMR_EXEC_BATCHED:
@@ -332,8 +349,9 @@ def check_patches(A, torch, O, ps, U, precision, exec_form, kw, steps=10, nsampl
     from paper_0910_5547_amd import workloads as W
     Ug, dts = _gpu_steps(A, torch, ps, U, precision, exec_form, kw, steps)
     sel = sorted(set(np.linspace(0, ps.npatch - 1, min(nsample, ps.npatch)).astype(int).tolist()))
-    sub = W.make_patchset(ps.ndim, ps.n[sel], ps.ng[sel], ps.bc[sel], gamma=ps.gamma, theta=ps.theta,
-                          dx0=ps.dx0, nvar=ps.nvar)
+    # (the oracle stores its ghost layers: at least two)
+    sub = W.make_patchset(ps.ndim, ps.n[sel], np.maximum(ps.ng[sel], 2), ps.bc[sel], gamma=ps.gamma,
+                          theta=ps.theta, dx0=ps.dx0, nvar=ps.nvar)
     Us = W.new_arena(sub)
     for i, p in enumerate(sel):
         sub.active(Us, i)[...] = ps.active(U, p)
@@ -474,6 +492,8 @@ def _oracle_rate(O, ps, U, kw, parallel, budget_s):
 def cpu_baseline(ps_full, U_full, kw, budget_s=8.0):
     """The FP64 oracle on a bounded sample of the same workload: the serial build pinned to
     one core, and its OpenMP build (same results) on every core this process may use."""
+    import numpy as np
+
     from oracle import oracle as O
     from paper_0910_5547_amd import workloads as W
     nv = ps_full.nvar
@@ -488,8 +508,8 @@ def cpu_baseline(ps_full, U_full, kw, budget_s=8.0):
     else:
         k = 64 if nv == W.NVAR else 8
         sel = list(range(k))
-        ps = W.make_patchset(3, ps_full.n[sel], ps_full.ng[sel], [W.BC_OUTFLOW] * 6, gamma=ps_full.gamma,
-                             dx0=ps_full.dx0, nvar=nv)
+        ps = W.make_patchset(3, ps_full.n[sel], np.maximum(ps_full.ng[sel], 2), [W.BC_OUTFLOW] * 6,
+                             gamma=ps_full.gamma, dx0=ps_full.dx0, nvar=nv)
         U = W.new_arena(ps)
         for i, p in enumerate(sel):
             ps.active(U, i)[...] = ps_full.active(U_full, p)
@@ -542,7 +562,8 @@ def run_workload(A, torch, name, forms, args):
             # one launch per patch and stage: thousands of launches per step
             steps, warmup = min(steps, 5), min(warmup, 2)
         log(f"form {form} ({steps} steps)")
-        r = time_form(A, torch, ps, U, prec, exe, steps, warmup, kw, tune=args.tune, shape=args.shape)
+        r = time_form(A, torch, ps, U, prec, exe, steps, warmup, kw, tune=args.tune, shape=args.shape,
+                      zslab=args.zslab)
         r["steps"] = steps
         r["value"] = cells / (r["ms_per_step"] * 1e-3)
         r["hbm_frac_step"] = bpc * cells / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBPS
@@ -586,7 +607,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="patches4000")
-    ap.add_argument("--extra", default="box256",
+    ap.add_argument("--extra", default="box256,patches4000-g0",
                     help="comma-separated workloads timed as extra keys of the same line ('' = none)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-check", dest="check", action="store_false",
@@ -598,6 +619,7 @@ def main():
     ap.add_argument("--forms", default=",".join(FORMS))
     ap.add_argument("--shape", type=int, default=None,
                     help="tile shape id (default: the library's choice for the workload; --tune overrides)")
+    ap.add_argument("--zslab", type=int, default=0, help="z-slab length with --shape (0 = automatic)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration for --summarize-pmc)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),

@@ -57,8 +57,10 @@
  *   must not overlap.  Ghost storage is only read on faces whose boundary
  *   condition is AMR_BC_EXTERNAL (filled by the library from other patches);
  *   the other conditions are applied by index mapping, so those ghost cells
- *   may hold anything.  The library never writes ghost cells of non-EXTERNAL
- *   faces and writes only active cells of U otherwise.
+ *   may hold anything, and a patch may store none (ng = 0, g = 0: s = n).
+ *   The library writes the active cells of U, the ghost cells of EXTERNAL
+ *   faces, and, on a level with children in a hierarchy, the two ghost layers of
+ *   the other faces (the children's prolongation stencils read them).
  */
 #ifndef AMR_HYDRO_H
 #define AMR_HYDRO_H
@@ -124,7 +126,11 @@ typedef struct {
   int32_t level;    /* refinement level, 0 = root; cell width dx0[d] / 2^level          */
   int32_t lo[3];    /* index of the first active cell in level index space             */
   int32_t n[3];     /* active cells per dimension, >= 1; 1 in dimensions >= ndim       */
-  int32_t ng;       /* ghost layers per side in active dimensions, 2 <= ng <= 8, ng <= n */
+  int32_t ng;       /* ghost layers stored per side in active dimensions, 2 <= ng <= 8, ng <= n;
+                       or 0: no ghost storage (s = n), for a patch of a single-level table
+                       whose faces are OUTFLOW, PERIODIC, REFLECT or EXTERNAL faces read
+                       directly from one sibling of the same shape (see AMR_BC_EXTERNAL);
+                       the stencil's two ghost layers per side are then never stored */
   int64_t offset;   /* element offset of variable 0 of this patch in the U arena       */
   int32_t bc[6];    /* AMR_BC_* of faces -x, +x, -y, +y, -z, +z                         */
   int32_t reserved[2]; /* must be 0                                                    */
@@ -153,7 +159,9 @@ typedef struct amr_table amr_table; /* opaque, library-owned */
 
 /* Create a table for `npatch` patches (Sec. 3 hierarchy as a flat list).
  * Copies the descriptors, validates them (AMR_EINVAL on: npatch < 1, n < 1,
- * ng out of range in an active dimension, n > 1 in an absent dimension,
+ * ng out of range in an active dimension, ng = 0 on a patch of a table with
+ * several levels or with an EXTERNAL face that is not read from one same-shaped
+ * sibling, n > 1 in an absent dimension,
  * overlapping storage, unknown bc/flux/precision/exec/recon, nvar not 5, 8 or 9,
  * ch negative or not finite,
  * gamma <= 1, theta outside [0,2], dx0 <= 0, a PERIODIC face whose opposite

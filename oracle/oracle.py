@@ -143,7 +143,10 @@ class Oracle:
     def __init__(self, ps, flux=FLUX_PAPER, rho_floor=0.0, e_floor=0.0, theta=None, periodic=0, domain=(0, 0, 0),
                  recon=RECON_E, ch=0.0, parallel=False):
         """parallel=True binds the OpenMP build of the same source (same results; used to
-        time the oracle on all host cores)."""
+        time the oracle on all host cores).  The oracle fills ghost layers in storage: every
+        patch must store at least two per side (ng >= 2)."""
+        if int(ps.ng.min()) < 2:
+            raise ValueError("the oracle stores its ghost layers: patches need ng >= 2")
         self.ps = ps
         self.L = lib(parallel)
         self.ph = phys(ps.gamma, ps.theta if theta is None else theta, ps.ndim, ps.dx0, flux, rho_floor, e_floor,

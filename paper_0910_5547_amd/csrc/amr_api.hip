@@ -44,7 +44,9 @@ amr_status validate_patches(const amr_patch_desc* P, int32_t np, const amr_physi
   for (int p = 0; p < np; ++p) {
     const amr_patch_desc& D = P[p];
     if (D.level < 0 || D.level >= MAX_LEVELS || D.offset < 0 || D.reserved[0] || D.reserved[1]) return AMR_EINVAL;
-    if (D.ng < 2 || D.ng > 8) return AMR_EINVAL;
+    // ng 0: no ghost storage (faces applied by index maps or read from direct siblings;
+    // the table checks that no face needs stored ghosts)
+    if (D.ng != 0 && (D.ng < 2 || D.ng > 8)) return AMR_EINVAL;
     int64_t S = 1;
     for (int d = 0; d < 3; ++d) {
       if (D.n[d] < 1) return AMR_EINVAL;
@@ -642,6 +644,8 @@ amr_status build_ghost_plan(amr_table* t, std::vector<CopyOp>& ops, std::vector<
             ops.pop_back();
           }
         }
+        // a patch without ghost storage takes every EXTERNAL face from a direct sibling
+        if (D.ng == 0 && (ops.size() != first_op || D.level > 0)) return AMR_EINVAL;
         if (D.level > 0) {
           for (int q = 0; q < np; ++q) {
             const amr_patch_desc& Q = t->desc[q];
@@ -976,6 +980,12 @@ amr_status amr_patch_table_create(const amr_patch_desc* patches, int32_t npatch,
     t->arena = std::max(t->arena, D.offset + phys->nvar * S);
     t->max_level = std::max(t->max_level, D.level);
   }
+  // hierarchies store ghosts (prolongation, physical ghosts for the children's stencils)
+  for (int p = 0; p < npatch && t->max_level > 0; ++p)
+    if (patches[p].ng == 0) {
+      delete t;
+      return AMR_EINVAL;
+    }
   std::vector<CopyOp> ops;
   std::vector<ProlongOp> pops;
   HierPlan H;

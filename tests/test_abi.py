@@ -176,3 +176,45 @@ def test_mhd_hierarchies_pass_validation(amr, nvar):
         assert not h.value
     else:
         amr.lib().amr_patch_table_destroy(h)
+
+
+def _try(amr, ps, **kw):
+    descs = amr.descriptors(ps)
+    ph = amr.physics(ps, **kw)
+    h = C.c_void_p()
+    r = amr.lib().amr_patch_table_create(descs, len(descs), C.byref(ph), None, C.byref(h))
+    if r == amr.AMR_OK:
+        amr.lib().amr_patch_table_destroy(h)
+    return r
+
+
+def test_ghost_free_storage_rules(amr):
+    """ng = 0 (no ghost storage): accepted for physical faces and for EXTERNAL faces read
+    directly from one same-shaped sibling of a single-level table; rejected where a face
+    would need stored ghosts (a slab over two siblings, a sibling of another shape) and on
+    tables with several levels.  Without a GPU an accepted table stops at the device
+    allocation, so acceptance shows as any status but AMR_EINVAL."""
+    ok = W.make_patchset(3, [[8, 16, 24], [32, 8, 8]], 0, [W.BC_OUTFLOW, W.BC_REFLECT, W.BC_PERIODIC,
+                                                          W.BC_PERIODIC, W.BC_REFLECT, W.BC_OUTFLOW])
+    assert _try(amr, ok) != amr.AMR_EINVAL
+    box, _ = W.periodic_turbulent_box(N=32, seed=20, kmax=8.0, patch=16, ng=0)
+    assert _try(amr, box, periodic=7, domain=(32, 32, 32)) != amr.AMR_EINVAL
+    # the -x ghost slab of patch 2 spans the two patches below it in y
+    split = W.make_patchset(3, [[8, 8, 8], [8, 8, 8], [8, 16, 8]], 0, [W.BC_EXTERNAL] * 6,
+                            lo=[[0, 0, 0], [0, 8, 0], [8, 0, 0]])
+    assert _try(amr, split, periodic=7, domain=(16, 16, 8)) == amr.AMR_EINVAL
+    # a sibling of another shape
+    shape = W.make_patchset(3, [[8, 8, 8], [16, 8, 8]], 0, [W.BC_EXTERNAL] * 6, lo=[[0, 0, 0], [8, 0, 0]])
+    assert _try(amr, shape, periodic=7, domain=(24, 8, 8)) == amr.AMR_EINVAL
+    # the same with stored ghosts is a valid table
+    shape3 = W.make_patchset(3, [[8, 8, 8], [16, 8, 8]], 3, [W.BC_EXTERNAL] * 6, lo=[[0, 0, 0], [8, 0, 0]])
+    assert _try(amr, shape3, periodic=7, domain=(24, 8, 8)) != amr.AMR_EINVAL
+    # several levels
+    two = W.make_patchset(3, [[8, 8, 8], [8, 8, 8]], 0, [W.BC_OUTFLOW] * 6, level=[0, 1], lo=[[0, 0, 0], [4, 4, 4]])
+    assert _try(amr, two) == amr.AMR_EINVAL
+
+
+def test_oracle_refuses_ghost_free_storage(oracle_lib):
+    ps = W.make_patchset(3, [[8, 8, 8]], 0, [W.BC_OUTFLOW] * 6)
+    with pytest.raises(ValueError):
+        oracle_lib.Oracle(ps)
