@@ -340,8 +340,9 @@ amr_status amr_cluster_flags(const amr_patch_desc* patches, int32_t npatch, int3
  *   flag_dev caller-owned device int32, set nonzero (never cleared) if the step meets
  *           an unphysical state (the table's latch).
  * AMR_EINVAL (nothing enqueued) for a bad argument, an EXTERNAL face, a level other
- * than 0, or a patch whose nvar * S doubles of U^(1) plus its tile list exceed the
- * scratch (e.g. 5 variables of 144^3 stored cells fit, 8 variables of 136^3 do not);
+ * than 0, or a patch whose U^(1) (nvar doubles per active cell) plus its tile list
+ * exceed the scratch (e.g. 5 variables of 144^3 active cells fit, 8 variables of
+ * 128^3 do not);
  * the last case also prints the bytes needed to stderr.  Every call on one GPU shares
  * that GPU's scratch: calls that overlap on one GPU (other streams, other host
  * threads) race and must be serialised by the caller. */

@@ -127,7 +127,11 @@ struct amr_table {
   std::vector<PatchDev> pdev;
   PatchDev* pdev_d = nullptr;
   int64_t arena = 0;
+  int64_t arena1 = 0;  // doubles of the stage scratch U^(1) (its own layout, PatchDev::off1)
   int max_level = 0;
+  // direct sibling faces found by the ghost plan: source patch and shift per face
+  std::vector<int> dsrc;
+  std::vector<int> dsh;
   double* U1 = nullptr;
   int* flag_d = nullptr;
   unsigned long long* smax_d = nullptr;  // [MAX_LEVELS + 1] scan maxima
@@ -565,6 +569,8 @@ WorkList add_work(std::vector<Seg>& segs, std::vector<int>& blk, const Op* ops, 
 amr_status build_ghost_plan(amr_table* t, std::vector<CopyOp>& ops, std::vector<ProlongOp>& pops) {
   const int nd = t->ph.ndim;
   const int np = (int)t->desc.size();
+  t->dsrc.assign(6 * (size_t)np, -1);
+  t->dsh.assign(18 * (size_t)np, 0);
   const int layers = 2;  // the PLM stencil reads two ghost layers
   for (int p = 0; p < np; ++p) {
     const amr_patch_desc& D = t->desc[p];
@@ -641,6 +647,8 @@ amr_status build_ghost_plan(amr_table* t, std::vector<CopyOp>& ops, std::vector<
             const int f = 2 * d + side;
             P.dmask |= 1 << f;
             P.nbo[f] = (t->pdev[op.src].off - P.off) + ((int64_t)op.sh[2] * P.s[1] + op.sh[1]) * P.s[0] + op.sh[0];
+            t->dsrc[6 * p + f] = op.src;
+            for (int e = 0; e < 3; ++e) t->dsh[3 * (6 * p + f) + e] = op.sh[e];
             ops.pop_back();
           }
         }
@@ -933,6 +941,56 @@ amr_status build_hierarchy(amr_table* t, HierPlan& H) {
 
 }  // namespace
 
+namespace {
+// Layout of the stage scratch U^(1).  Where no patch needs stored ghosts (a single
+// level, every EXTERNAL face read directly from a same-shaped sibling), U^(1) holds the
+// active cells alone, patch after patch (the stage kernels write and read whole 128-byte
+// lines instead of rows framed by ghost cells); otherwise it mirrors U's layout, whose
+// ghost storage the ghost fill and refluxing use.
+void set_scratch_layout(amr_table* t, bool dense) {
+  dense = dense && t->max_level == 0;
+  const int np = (int)t->pdev.size();
+  int64_t cur = 0;
+  for (int p = 0; p < np; ++p) {
+    PatchDev& P = t->pdev[p];
+    if (!dense) {
+      P.off1 = P.off;
+      P.S1 = P.S;
+      for (int d = 0; d < 3; ++d) {
+        P.s1[d] = P.s[d];
+        P.g1[d] = P.g[d];
+      }
+      for (int f = 0; f < 6; ++f) P.nbo1[f] = P.nbo[f];
+      continue;
+    }
+    cur = (cur + 63) / 64 * 64;  // 512-byte aligned patches
+    P.off1 = cur;
+    P.S1 = (int64_t)P.n[0] * P.n[1] * P.n[2];
+    for (int d = 0; d < 3; ++d) {
+      P.s1[d] = P.n[d];
+      P.g1[d] = 0;
+    }
+    cur += t->ph.nvar * P.S1;
+  }
+  if (dense) {
+    for (int p = 0; p < np; ++p) {
+      PatchDev& P = t->pdev[p];
+      for (int f = 0; f < 6; ++f) {
+        const int q = t->dsrc[6 * p + f];
+        if (q < 0) {
+          P.nbo1[f] = 0;
+          continue;
+        }
+        const int* sh = &t->dsh[3 * (6 * p + f)];
+        P.nbo1[f] = (t->pdev[q].off1 - P.off1) + ((int64_t)sh[2] * P.s1[1] + sh[1]) * P.s1[0] + sh[0];
+      }
+    }
+  }
+  t->arena1 = dense ? std::max<int64_t>(cur, 1) : t->arena;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* amr_status_string(amr_status s) {
@@ -995,6 +1053,7 @@ amr_status amr_patch_table_create(const amr_patch_desc* patches, int32_t npatch,
     delete t;
     return st;
   }
+  set_scratch_layout(t, ops.empty() && pops.empty());
   t->last_dt.assign(MAX_LEVELS, nullptr);
   auto fail = [&](amr_status s) {
     amr_patch_table_destroy(t);
@@ -1004,7 +1063,7 @@ amr_status amr_patch_table_create(const amr_patch_desc* patches, int32_t npatch,
   if (hipDeviceGetAttribute(&t->ncu, hipDeviceAttributeMultiprocessorCount, t->device) != hipSuccess)
     return fail(AMR_EHIP);
   if (hipMalloc(&t->pdev_d, sizeof(PatchDev) * t->pdev.size()) != hipSuccess) return fail(AMR_ENOMEM);
-  if (hipMalloc(&t->U1, sizeof(double) * (size_t)t->arena) != hipSuccess) return fail(AMR_ENOMEM);
+  if (hipMalloc(&t->U1, sizeof(double) * (size_t)t->arena1) != hipSuccess) return fail(AMR_ENOMEM);
   if (hipMalloc(&t->flag_d, sizeof(int)) != hipSuccess) return fail(AMR_ENOMEM);
   if (hipMalloc(&t->smax_d, sizeof(unsigned long long) * (MAX_LEVELS + 1)) != hipSuccess) return fail(AMR_ENOMEM);
   if (hipMalloc(&t->fused_d, sizeof(unsigned long long) * (MAX_LEVELS + 1)) != hipSuccess) return fail(AMR_ENOMEM);

@@ -50,6 +50,12 @@ struct PatchDev {
   // shape, so the element of a ghost cell of face f in the sibling's storage is the
   // element of the same cell in this patch's ghost storage plus nbo[f].
   int64_t nbo[6];
+  // Layout of the patch in the table's stage scratch U^(1): the caller's layout above,
+  // or (tables whose patches need no stored ghosts) the active cells alone, s1 = n,
+  // g1 = 0, at off1; nbo1 as nbo for that layout.
+  int64_t off1, S1;
+  int s1[3], g1[3];
+  int64_t nbo1[6];
 };
 
 // One unit of stage-kernel work: a TX x TY column block of one patch, marched

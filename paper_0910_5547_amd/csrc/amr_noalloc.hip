@@ -25,7 +25,7 @@ using namespace amr;
 namespace {
 
 constexpr size_t SCRATCH_BYTES = AMR_NOALLOC_SCRATCH_BYTES;
-constexpr size_t HDR_BYTES = 256;  // descriptor slot; the tile list follows
+constexpr size_t HDR_BYTES = 512;  // descriptor slot; the tile list follows
 static_assert(sizeof(PatchDev) <= HDR_BYTES, "descriptor slot too small");
 static_assert(sizeof(Tile) == 32, "tile layout");
 
@@ -124,6 +124,13 @@ extern "C" amr_status amr_patch_rk2_step_noalloc(const amr_patch_desc* patch, co
     P.bc[f] = patch->bc[f];
     P.reg[f] = -1;
   }
+  // U^(1) in the scratch: the active cells alone, from its start
+  P.off1 = 0;
+  P.S1 = (int64_t)P.n[0] * P.n[1] * P.n[2];
+  for (int d = 0; d < 3; ++d) {
+    P.s1[d] = P.n[d];
+    P.g1[d] = 0;
+  }
 
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return AMR_EHIP;
@@ -157,7 +164,7 @@ extern "C" amr_status amr_patch_rk2_step_noalloc(const amr_patch_desc* patch, co
   const int64_t nzs = (P.n[2] + zs - 1) / zs;
   const int64_t L64 = (int64_t)ntx * nty * nzs;
   const size_t tile_bytes = (size_t)((L64 * (int64_t)sizeof(Tile) + 255) / 256 * 256);
-  const size_t need = HDR_BYTES + tile_bytes + sizeof(double) * (size_t)phys->nvar * (size_t)S;
+  const size_t need = HDR_BYTES + tile_bytes + sizeof(double) * (size_t)phys->nvar * (size_t)P.S1;
   if (L64 > (1 << 30) || need > SCRATCH_BYTES) {
     fprintf(stderr,
             "amr_patch_rk2_step_noalloc: the patch needs %zu bytes of scratch, more than the %zu the library "
@@ -169,9 +176,6 @@ extern "C" amr_status amr_patch_rk2_step_noalloc(const amr_patch_desc* patch, co
   PatchDev* pd = reinterpret_cast<PatchDev*>(base);
   Tile* tiles = reinterpret_cast<Tile*>(base + HDR_BYTES);
   double* U1 = reinterpret_cast<double*>(base + HDR_BYTES + tile_bytes);
-  // U^(1) is addressed like U (element offset P.off of the patch): shift the base so
-  // that the patch's first element lands at the start of the scratch region
-  double* U1base = U1 - P.off;
 
   hipLaunchKernelGGL(noalloc_tiles, dim3((L + 255) / 256), dim3(256), 0, stream, P, pd, tiles, L, W, ntx, nty, TX,
                      TY, zs);
@@ -184,7 +188,7 @@ extern "C" amr_status amr_patch_rk2_step_noalloc(const amr_patch_desc* patch, co
   StageArgs a{};
   a.V = U;
   a.U0 = nullptr;
-  a.out = U1base;
+  a.out = U1;
   a.dt = dt_dev;
   a.patches = pd;
   a.tiles = tiles;
@@ -194,7 +198,7 @@ extern "C" amr_status amr_patch_rk2_step_noalloc(const amr_patch_desc* patch, co
   a.reg = nullptr;
   a.c = consts_of_phys(*phys);
   if (launch_stage(phys->nvar, mixed, shape, 1, grid_of(occ1), stream, a) != hipSuccess) return AMR_EHIP;
-  a.V = U1base;
+  a.V = U1;
   a.U0 = U;
   a.out = U;
   if (launch_stage(phys->nvar, mixed, shape, 2, grid_of(occ2), stream, a) != hipSuccess) return AMR_EHIP;

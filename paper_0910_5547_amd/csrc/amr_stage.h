@@ -132,14 +132,29 @@ void stage_kernel(StageArgs a) {
     const int i = T.x0 + cx, j = T.y0 + cy;
     const bool hasz = C.ndim == 3;
     const bool hasy = HASY && C.ndim >= 2;
+    // Layouts: the stage input V (stage 1: the caller's U; stage 2: the scratch U^(1))
+    // and the cell's own U^n and output (stage 1: U^(1); stage 2: U), each an element
+    // offset, variable stride, row length, plane stride and ghost offsets.
+    constexpr bool in_caller = STAGE == 1;
+    const int64_t offV = in_caller ? P.off : P.off1, SV = in_caller ? P.S : P.S1;
+    const int64_t offO = in_caller ? P.off1 : P.off, SO = in_caller ? P.S1 : P.S;
+    const int rowV = in_caller ? P.s[0] : P.s1[0], rowO = in_caller ? P.s1[0] : P.s[0];
+    const int gV0 = in_caller ? P.g[0] : P.g1[0], gV1 = in_caller ? P.g[1] : P.g1[1];
+    const int gV2 = in_caller ? P.g[2] : P.g1[2];
+    const int gO0 = in_caller ? P.g1[0] : P.g[0], gO1 = in_caller ? P.g1[1] : P.g[1];
+    const int gO2 = in_caller ? P.g1[2] : P.g[2];
+    // (constant indices only: a runtime index into P would move it to scratch memory)
+#define NBO_V(f) (in_caller ? P.nbo[f] : P.nbo1[f])
     // element of this lane's column in plane 0 (the column is inside the patch) and
     // the stride between planes; plane k of the column is at col0 + kk * pstride,
     // kk being k after the z boundary map (uniform across the workgroup)
-    const int64_t pstride = (int64_t)P.s[0] * P.s[1];
+    const int64_t pstride = (int64_t)rowV * (in_caller ? P.s[1] : P.s1[1]);
+    const int64_t pstrideO = (int64_t)rowO * (in_caller ? P.s1[1] : P.s[1]);
     // (inactive lanes of a ragged tile point at the tile's last active column, so that
     // every lane can issue the plane prefetch below unconditionally)
     const int ic = min(i, P.n[0] - 1), jc = min(j, P.n[1] - 1);
-    const int64_t col0 = P.off + (int64_t)P.g[2] * pstride + (int64_t)(jc + P.g[1]) * P.s[0] + (ic + P.g[0]);
+    const int64_t col0 = offV + (int64_t)gV2 * pstride + (int64_t)(jc + gV1) * rowV + (ic + gV0);
+    const int64_t colO = offO + (int64_t)gO2 * pstrideO + (int64_t)(jc + gO1) * rowO + (ic + gO0);
     // The REFLECT sign flip of the normal momentum is applied where loaded values
     // are used, not at the load: a flip right after the load would make the load
     // wait for its data, and the prefetches below would stop hiding latency.
@@ -148,10 +163,10 @@ void stage_kernel(StageArgs a) {
       bool fz = false;
       const int kk = map_index(kz, P.n[2], P.bc[4], P.bc[5], fz);
       int64_t e = col0 + (int64_t)kk * pstride;
-      if (kz < 0 && (P.dmask & 16)) e += P.nbo[4];
-      if (kz >= P.n[2] && (P.dmask & 32)) e += P.nbo[5];
+      if (kz < 0 && (P.dmask & 16)) e += NBO_V(4);
+      if (kz >= P.n[2] && (P.dmask & 32)) e += NBO_V(5);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) u[v] = a.V[e + v * P.S];
+      for (int v = 0; v < NV; ++v) u[v] = a.V[e + v * SV];
       return fz;
     };
     auto load_col = [&](int kz, double u[NV]) {
@@ -207,7 +222,7 @@ void stage_kernel(StageArgs a) {
     auto load_halo = [&](int s, int kz, double u[NV]) {  // raw: hflip applied at use
       const int64_t e = hbase[s] + (int64_t)kz * pstride;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) u[v] = a.V[e + v * P.S];
+      for (int v = 0; v < NV; ++v) u[v] = a.V[e + v * SV];
     };
 #pragma unroll
     for (int s = 0; s < HMAX; ++s) {
@@ -227,13 +242,13 @@ void stage_kernel(StageArgs a) {
       const int ii = map_index(iraw, P.n[0], P.bc[0], P.bc[1], fx);
       const int jj = map_index(jraw, P.n[1], P.bc[2], P.bc[3], fy);
       hflip[s] = fx ? 1 : (fy ? 2 : 0);
-      hbase[s] = P.off + (int64_t)P.g[2] * pstride + (int64_t)(jj + P.g[1]) * P.s[0] + (ii + P.g[0]);
+      hbase[s] = offV + (int64_t)gV2 * pstride + (int64_t)(jj + gV1) * rowV + (ii + gV0);
       // a halo cell has at most one coordinate outside the patch (cross stencil)
       const int hf = iraw < 0 ? 0 : iraw >= P.n[0] ? 1 : jraw < 0 ? 2 : jraw >= P.n[1] ? 3 : -1;
-      if (hf == 0 && (P.dmask & 1)) hbase[s] += P.nbo[0];
-      if (hf == 1 && (P.dmask & 2)) hbase[s] += P.nbo[1];
-      if (hf == 2 && (P.dmask & 4)) hbase[s] += P.nbo[2];
-      if (hf == 3 && (P.dmask & 8)) hbase[s] += P.nbo[3];
+      if (hf == 0 && (P.dmask & 1)) hbase[s] += NBO_V(0);
+      if (hf == 1 && (P.dmask & 2)) hbase[s] += NBO_V(1);
+      if (hf == 2 && (P.dmask & 4)) hbase[s] += NBO_V(2);
+      if (hf == 3 && (P.dmask & 8)) hbase[s] += NBO_V(3);
       if (h < nhx + nhy) load_halo(s, T.z0, Hn[s]);
     }
     // Per-lane work of the slope and face passes, fixed for the tile:
@@ -356,11 +371,12 @@ void stage_kernel(StageArgs a) {
       // stage 2, U^n: the global loads are issued before the face pass so that it
       // hides their latency (wavefront tiles, short of VGPRs, issue them after it)
       double Vc[NV], U0c[NV];
-      const int64_t ecell = col0 + (int64_t)k * pstride;
+      const int64_t ecell = col0 + (int64_t)k * pstride;    // the cell in V
+      const int64_t ecellO = colO + (int64_t)k * pstrideO;  // the cell in U^n and the output
       auto load_u0 = [&] {
         if (STAGE == 2) {
 #pragma unroll
-          for (int v = 0; v < NV; ++v) U0c[v] = a.U0[ecell + v * P.S];
+          for (int v = 0; v < NV; ++v) U0c[v] = a.U0[ecellO + v * SO];
         }
       };
       auto load_vc = [&] {
@@ -369,7 +385,7 @@ void stage_kernel(StageArgs a) {
           for (int v = 0; v < NV; ++v) Vc[v] = sV[k & 1][v][threadIdx.x];
         } else {
 #pragma unroll
-          for (int v = 0; v < NV; ++v) Vc[v] = a.V[ecell + v * P.S];
+          for (int v = 0; v < NV; ++v) Vc[v] = a.V[ecell + v * SV];
         }
       };
       if constexpr (!SB) {
@@ -555,7 +571,7 @@ void stage_kernel(StageArgs a) {
           }
         }
         // TVD-RK2 (Sec. 4): stage 1 U1 = U + dt L(U); stage 2 U^{n+1} = U^n/2 + (U1 + dt L(U1))/2
-        const int64_t e = ecell;
+        const int64_t e = ecellO;
         double un[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -566,7 +582,7 @@ void stage_kernel(StageArgs a) {
         }
         if (act) {
 #pragma unroll
-          for (int v = 0; v < NV; ++v) a.out[e + v * P.S] = un[v];
+          for (int v = 0; v < NV; ++v) a.out[e + v * SO] = un[v];
           if (STAGE == 2 && a.smax != nullptr) smax = fmax(smax, cell_speed<FAST, NV>(un, C, P, bad));
         }
       }
@@ -578,6 +594,7 @@ void stage_kernel(StageArgs a) {
     }
   }
   if (bad) atomicOr(a.flag, 1);
+#undef NBO_V
 }
 
 // ------------------------------------------------------------------ launchers
