@@ -161,6 +161,7 @@ struct amr_table {
   double* dtl = nullptr;                        // per-level dt of the subcycled root step
   std::vector<int64_t> reg_first, reg_len;      // per level, for clearing
   ProlongOp* prol_d = nullptr;
+  CopyOp* pcp_d = nullptr;                      // the prolongation boxes as same-cell copies (U^(1) -> U)
   std::vector<int> prol_first, prol_count;      // per destination level
   PhysOp* phys_d = nullptr;
   std::vector<int> phys_first, phys_count;      // per level with children
@@ -168,9 +169,9 @@ struct amr_table {
   std::vector<std::vector<std::pair<int, int>>> fix_colors;  // per coarse level: (first, count) per color
   RestrictOp* rst_d = nullptr;
   std::vector<int> rst_first, rst_count;        // per coarse level
-  int64_t* snap_d = nullptr;                    // (offset, length) pairs
+  CopyOp* snap_d = nullptr;                     // snapshot boxes (dst = src = the coarse patch)
   std::vector<int> snap_first, snap_count;      // per level
-  std::vector<int64_t> snap_maxlen;
+  std::vector<WorkList> w_snap;
   std::vector<const double*> last_dt;           // dt pointer of each level's last step
   GraphCache gadv;                              // captured root step (batched form)
   // cell-granular work lists of the box-op kernels (see Seg): per level, and for
@@ -367,16 +368,26 @@ int occupancy_grid(amr_table* t, int stage, int ntiles, bool rec) {
 // between its snapshot and its state in U at fraction alpha.
 Work work_of(const amr_table* t, const WorkList& w) { return Work{t->segs_d, t->blk_d + w.blk_base, w.nblk, 0}; }
 
+// The prolonged ghosts: computed (PROL_COMPUTE), copied from the same ghost cells of
+// U^(1), which hold them at this alpha already (PROL_FROM_U1), or left as they are
+// (PROL_KEEP: A holds them at this alpha).
+enum { PROL_COMPUTE = 0, PROL_FROM_U1 = 1, PROL_KEEP = 2 };
+
 amr_status enqueue_ghosts(amr_table* t, double* A, const double* U, int level, double alpha, hipStream_t s,
-                          const double* Cold = nullptr) {
+                          const double* Cold = nullptr, int prol = PROL_COMPUTE) {
   const int l0 = level < 0 ? 0 : level, l1 = level < 0 ? t->max_level : level;
   for (int l = l0; l <= l1; ++l)
     if (t->w_copy[l].nblk > 0)
       HIPCHECK(launch_copy_ghosts(s, t->ops_d + t->ops_level_first[l], work_of(t, t->w_copy[l]), t->pdev_d, A,
                                   t->ph.nvar));
-  if (level > 0 && t->w_prol[level].nblk > 0)
-    HIPCHECK(launch_prolong(s, t->prol_d + t->prol_first[level], work_of(t, t->w_prol[level]), t->pdev_d, A,
-                            Cold ? Cold : t->snap, U, alpha, t->ph.ndim, t->ph.nvar));
+  if (level > 0 && t->w_prol[level].nblk > 0) {
+    if (prol == PROL_COMPUTE)
+      HIPCHECK(launch_prolong(s, t->prol_d + t->prol_first[level], work_of(t, t->w_prol[level]), t->pdev_d, A,
+                              Cold ? Cold : t->snap, U, alpha, t->ph.ndim, t->ph.nvar));
+    else if (prol == PROL_FROM_U1)
+      HIPCHECK(launch_copy_cells_x(s, t->pcp_d + t->prol_first[level], work_of(t, t->w_prol[level]), t->pdev_d,
+                                   t->pdev_d, A, t->U1, t->ph.nvar));
+  }
   return AMR_OK;
 }
 
@@ -430,14 +441,19 @@ amr_status enqueue_step(amr_table* t, double* U, const double* dt, int level, ui
   const bool rec = level > 0 && t->reg != nullptr;
   const double a1 = 0.5 * substep, a2 = 0.5 * (substep + 1);
   if (fuse) HIPCHECK(launch_fill_u64(s, t->fused_d, MAX_LEVELS + 1, 0ull));
-  st = enqueue_ghosts(t, U, U, level, a1, s);
+  // The second substep's first stage takes its prolonged ghosts at time 1/2 of the parent
+  // step, as the first substep's second stage did into U^(1): a level with children
+  // copied them into U at the end of that step already; a level without copies them now.
+  const int prol1 = (level > 0 && substep == 1) ? (kids ? PROL_KEEP : PROL_FROM_U1) : PROL_COMPUTE;
+  st = enqueue_ghosts(t, U, U, level, a1, s, nullptr, prol1);
   if (st != AMR_OK) return st;
   if (kids) {
     if (t->w_phys[level].nblk > 0)
       HIPCHECK(launch_phys(s, t->phys_d + t->phys_first[level], work_of(t, t->w_phys[level]), t->pdev_d, U,
                                  t->ph.nvar));
-    HIPCHECK(launch_copy_ranges(s, t->snap_d + 2 * t->snap_first[level], t->snap_count[level],
-                                t->snap_maxlen[level], U, t->snap));
+    if (t->w_snap[level].nblk > 0)
+      HIPCHECK(launch_copy_cells_x(s, t->snap_d + t->snap_first[level], work_of(t, t->w_snap[level]), t->pdev_d,
+                                   t->pdev_d, t->snap, U, t->ph.nvar));
   }
   if (ev) HIPCHECK(hipEventRecord(ev[0], s));
   st = enqueue_stage(t, ts, 1, U, nullptr, t->U1, dt, fuse, rec, s);
@@ -450,7 +466,8 @@ amr_status enqueue_step(amr_table* t, double* U, const double* dt, int level, ui
   if (st != AMR_OK) return st;
   if (ev) HIPCHECK(hipEventRecord(ev[3], s));
   if (kids) {
-    st = enqueue_ghosts(t, U, U, level, a2, s);
+    // U^{n+1}'s ghosts for the children's stencils: the prolonged ones equal those of U^(1)
+    st = enqueue_ghosts(t, U, U, level, a2, s, nullptr, PROL_FROM_U1);
     if (st != AMR_OK) return st;
     if (t->w_phys[level].nblk > 0)
       HIPCHECK(launch_phys(s, t->phys_d + t->phys_first[level], work_of(t, t->w_phys[level]), t->pdev_d, U,
@@ -732,11 +749,11 @@ struct HierPlan {
   std::vector<FixOp> fix;
   std::vector<int> fix_color;
   std::vector<RestrictOp> rst;
-  std::vector<int64_t> snap;  // (offset, length) pairs
+  std::vector<CopyOp> snap;  // storage boxes of levels with children copied into the snapshot
   int64_t nreg = 0;
 };
 
-amr_status build_hierarchy(amr_table* t, HierPlan& H) {
+amr_status build_hierarchy(amr_table* t, HierPlan& H, const std::vector<ProlongOp>& pops) {
   const int nd = t->ph.ndim;
   const int np = (int)t->desc.size();
   const int L = t->max_level + 1;
@@ -768,23 +785,15 @@ amr_status build_hierarchy(amr_table* t, HierPlan& H) {
     }
     t->reg_len[l] = H.nreg - t->reg_first[l];
   }
-  // physical ghosts and snapshots of levels with children
+  // physical ghosts of levels with children
   t->phys_first.assign(MAX_LEVELS, 0);
   t->phys_count.assign(MAX_LEVELS, 0);
-  t->snap_first.assign(MAX_LEVELS, 0);
-  t->snap_count.assign(MAX_LEVELS, 0);
-  t->snap_maxlen.assign(MAX_LEVELS, 0);
   for (int l = 0; l < L; ++l) {
     if (!t->has_kids[l]) continue;
     t->phys_first[l] = (int)H.phys.size();
-    t->snap_first[l] = (int)H.snap.size() / 2;
     for (int p = 0; p < np; ++p) {
       const auto& D = t->desc[p];
       if (D.level != l) continue;
-      const PatchDev& P = t->pdev[p];
-      H.snap.push_back(P.off);
-      H.snap.push_back(t->ph.nvar * P.S);
-      t->snap_maxlen[l] = std::max<int64_t>(t->snap_maxlen[l], t->ph.nvar * P.S);
       for (int d = 0; d < nd; ++d)
         for (int side = 0; side < 2; ++side) {
           if (D.bc[2 * d + side] == AMR_BC_EXTERNAL) continue;
@@ -800,7 +809,6 @@ amr_status build_hierarchy(amr_table* t, HierPlan& H) {
         }
     }
     t->phys_count[l] = (int)H.phys.size() - t->phys_first[l];
-    t->snap_count[l] = (int)H.snap.size() / 2 - t->snap_first[l];
   }
   // coarse cells (level l coordinates) under a level l+1 patch
   auto key3 = [](int x, int y, int z) { return ((int64_t)z << 42) ^ ((int64_t)y << 21) ^ (int64_t)x; };
@@ -936,6 +944,78 @@ amr_status build_hierarchy(amr_table* t, HierPlan& H) {
     t->rst_count[l] = (int)H.rst.size() - t->rst_first[l];
   }
   H.fix = fixall;
+  // Snapshot boxes.  A level's U^n is read later by its children's prolongation (the
+  // coarse cell of each fine ghost cell and its face neighbours, from storage) and by
+  // refluxing (the coarse stage inputs two cells either side of each corrected face,
+  // through the boundary conditions' index maps): only those storage cells are copied,
+  // as boxes covering a per-patch mask of them.
+  t->snap_first.assign(MAX_LEVELS, 0);
+  t->snap_count.assign(MAX_LEVELS, 0);
+  std::vector<std::vector<char>> smask(np);
+  auto mark = [&](int q, int x, int y, int z) {
+    const PatchDev& Q = t->pdev[q];
+    const int c[3] = {x, y, z};
+    for (int e = 0; e < 3; ++e)
+      if (c[e] < -Q.g[e] || c[e] >= Q.n[e] + Q.g[e]) return;  // outside storage: nothing to read there
+    std::vector<char>& m = smask[q];
+    if (m.empty()) m.assign((size_t)Q.S, 0);
+    m[((size_t)(z + Q.g[2]) * Q.s[1] + (y + Q.g[1])) * Q.s[0] + (x + Q.g[0])] = 1;
+  };
+  for (const ProlongOp& op : pops) {
+    const int q = op.src;
+    int lo[3], hi[3];
+    for (int e = 0; e < 3; ++e) {
+      if (e >= nd) {
+        lo[e] = 0;
+        hi[e] = 1;
+        continue;
+      }
+      lo[e] = ((op.lo[e] + op.foff[e]) >> 1) - op.clo[e] - 1;
+      hi[e] = ((op.lo[e] + op.sz[e] - 1 + op.foff[e]) >> 1) - op.clo[e] + 2;
+    }
+    for (int z = lo[2]; z < hi[2]; ++z)
+      for (int y = lo[1]; y < hi[1]; ++y)
+        for (int x = lo[0]; x < hi[0]; ++x) mark(q, x, y, z);
+  }
+  for (const FixOp& op : fixall) {
+    const PatchDev& Q = t->pdev[op.coarse];
+    int lo[3], hi[3];
+    for (int e = 0; e < 3; ++e) {
+      lo[e] = op.lo[e];
+      hi[e] = op.lo[e] + op.sz[e];
+    }
+    lo[op.d] -= 2;
+    hi[op.d] += 2;
+    for (int z = lo[2]; z < hi[2]; ++z)
+      for (int y = lo[1]; y < hi[1]; ++y)
+        for (int x = lo[0]; x < hi[0]; ++x) {
+          int c[3] = {x, y, z};
+          bool flip = false;
+          const int dd = op.d;
+          c[dd] = map_index(c[dd], Q.n[dd], Q.bc[2 * dd], Q.bc[2 * dd + 1], flip);
+          mark(op.coarse, c[0], c[1], c[2]);
+        }
+  }
+  for (int l = 0; l < L; ++l) {
+    t->snap_first[l] = (int)H.snap.size();
+    if (!t->has_kids[l]) continue;
+    for (int q = 0; q < np; ++q) {
+      if (t->desc[q].level != l || smask[q].empty()) continue;
+      const PatchDev& Q = t->pdev[q];
+      cover_boxes(Q.s, smask[q], [&](const int blo[3], const int sz[3]) {
+        CopyOp op{};
+        op.dst = q;
+        op.src = q;
+        for (int e = 0; e < 3; ++e) {
+          op.lo[e] = blo[e] - Q.g[e];
+          op.sz[e] = sz[e];
+          op.sh[e] = 0;
+        }
+        H.snap.push_back(op);
+      });
+    }
+    t->snap_count[l] = (int)H.snap.size() - t->snap_first[l];
+  }
   return AMR_OK;
 }
 
@@ -1048,7 +1128,7 @@ amr_status amr_patch_table_create(const amr_patch_desc* patches, int32_t npatch,
   std::vector<ProlongOp> pops;
   HierPlan H;
   st = build_ghost_plan(t, ops, pops);
-  if (st == AMR_OK) st = build_hierarchy(t, H);
+  if (st == AMR_OK) st = build_hierarchy(t, H, pops);
   if (st != AMR_OK) {
     delete t;
     return st;
@@ -1082,7 +1162,16 @@ amr_status amr_patch_table_create(const amr_patch_desc* patches, int32_t npatch,
     if (hipMalloc(dst, sizeof(T) * v.size()) != hipSuccess) return false;
     return hipMemcpyAsync(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, stream) == hipSuccess;
   };
-  if (!upload(&t->prol_d, pops) || !upload(&t->phys_d, H.phys) || !upload(&t->fix_d, H.fix) ||
+  std::vector<CopyOp> pcp(pops.size());
+  for (size_t i = 0; i < pops.size(); ++i) {
+    pcp[i].dst = pcp[i].src = pops[i].dst;
+    for (int e = 0; e < 3; ++e) {
+      pcp[i].lo[e] = pops[i].lo[e];
+      pcp[i].sz[e] = pops[i].sz[e];
+      pcp[i].sh[e] = 0;
+    }
+  }
+  if (!upload(&t->prol_d, pops) || !upload(&t->pcp_d, pcp) || !upload(&t->phys_d, H.phys) || !upload(&t->fix_d, H.fix) ||
       !upload(&t->rst_d, H.rst) || !upload(&t->snap_d, H.snap))
     return fail(AMR_ENOMEM);
   // cell-granular work lists of every box-op launch
@@ -1093,12 +1182,14 @@ amr_status amr_patch_table_create(const amr_patch_desc* patches, int32_t npatch,
     t->w_prol.assign(MAX_LEVELS, {});
     t->w_phys.assign(MAX_LEVELS, {});
     t->w_rst.assign(MAX_LEVELS, {});
+    t->w_snap.assign(MAX_LEVELS, {});
     t->w_fix.assign(MAX_LEVELS, {});
     for (int l = 0; l <= t->max_level; ++l) {
       t->w_copy[l] = add_work(segs, blk, ops.data() + t->ops_level_first[l], t->ops_level_count[l]);
       t->w_prol[l] = add_work(segs, blk, pops.data() + t->prol_first[l], t->prol_count[l]);
       t->w_phys[l] = add_work(segs, blk, H.phys.data() + t->phys_first[l], t->phys_count[l]);
       t->w_rst[l] = add_work(segs, blk, H.rst.data() + t->rst_first[l], t->rst_count[l]);
+      t->w_snap[l] = add_work(segs, blk, H.snap.data() + t->snap_first[l], t->snap_count[l]);
       for (const auto& fc : t->fix_colors[l]) t->w_fix[l].push_back(add_work(segs, blk, H.fix.data() + fc.first, fc.second));
     }
     if (!upload(&t->segs_d, segs) || !upload(&t->blk_d, blk)) return fail(AMR_ENOMEM);
@@ -1144,7 +1235,7 @@ amr_status amr_patch_table_destroy(amr_table* t) {
   if (t->smax_d) (void)hipFree(t->smax_d);
   if (t->fused_d) (void)hipFree(t->fused_d);
   if (t->ops_d) (void)hipFree(t->ops_d);
-  for (void* q : {(void*)t->snap, (void*)t->reg, (void*)t->dtl, (void*)t->prol_d, (void*)t->phys_d, (void*)t->fix_d,
+  for (void* q : {(void*)t->snap, (void*)t->reg, (void*)t->dtl, (void*)t->prol_d, (void*)t->pcp_d, (void*)t->phys_d, (void*)t->fix_d,
                   (void*)t->rst_d, (void*)t->snap_d, (void*)t->segs_d, (void*)t->blk_d})
     if (q) (void)hipFree(q);
   if (t->cap_stream) (void)hipStreamDestroy(t->cap_stream);

@@ -181,7 +181,7 @@ __device__ __forceinline__ int64_t cell_elem(const PatchDev& P, int i, int j, in
 // Boundary condition as an index map (Sec. 3 ghost zones): a coordinate outside
 // [0, n) along one dimension is sent to the active cell whose value the ghost
 // holds; EXTERNAL keeps it (stored ghost, filled beforehand).
-__device__ __forceinline__ int map_index(int i, int n, int bclo, int bchi, bool& flip) {
+__host__ __device__ __forceinline__ int map_index(int i, int n, int bclo, int bchi, bool& flip) {
   if (i < 0) {
     if (bclo == BC_OUTFLOW) return 0;
     if (bclo == BC_PERIODIC) return i + n;

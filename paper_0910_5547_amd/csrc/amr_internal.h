@@ -80,8 +80,6 @@ hipError_t launch_fill_i32(hipStream_t s, int* p, int n, int v);
 hipError_t launch_prolong(hipStream_t s, const ProlongOp* ops, const Work& w, const PatchDev* p, double* A,
                           const double* Cold, const double* Cnew, double alpha, int ndim, int nv);
 hipError_t launch_phys(hipStream_t s, const PhysOp* ops, const Work& w, const PatchDev* p, double* A, int nv);
-hipError_t launch_copy_ranges(hipStream_t s, const int64_t* ranges, int nr, int64_t maxlen, const double* src,
-                              double* dst);
 hipError_t launch_flux_fix(int mixed, int nv, hipStream_t s, const FixOp* ops, const Work& w, const PatchDev* p,
                            double* U, const double* S1, const double* S2, const double* reg, const double* dtc,
                            const Consts& C, int* flag);

@@ -5,7 +5,6 @@
 //                    space, linear in time between the coarse old and new states;
 //   fill_phys_ghosts physical boundary ghosts of a coarse level written into
 //                    storage (the prolongation stencil reads one layer of them);
-//   copy_ranges      snapshot of a level's storage (its U^n for the children);
 //   flux_fix         refluxing: each uncovered coarse cell next to a fine patch
 //                    swaps its own interface flux (recomputed bit for bit from the
 //                    two saved stage inputs) for the fine registers' average;
@@ -86,16 +85,6 @@ __global__ __launch_bounds__(NT) void fill_phys_ghosts(const PhysOp* __restrict_
   const int64_t e = cell_elem(P, i, j, k);
 #pragma unroll
   for (int v = 0; v < NV; ++v) A[e + v * P.S] = u[v];
-}
-
-// ---------------------------------------------------------------- snapshot
-__global__ __launch_bounds__(NT) void copy_ranges(const int64_t* __restrict__ ranges, int nr,
-                                                  const double* __restrict__ src, double* __restrict__ dst) {
-  for (int r = blockIdx.y; r < nr; r += gridDim.y) {
-    const int64_t o = ranges[2 * r], len = ranges[2 * r + 1];
-    for (int64_t x = (int64_t)blockIdx.x * NT + threadIdx.x; x < len; x += (int64_t)gridDim.x * NT)
-      dst[o + x] = src[o + x];
-  }
 }
 
 // ---------------------------------------------------------------- refluxing
@@ -223,12 +212,6 @@ hipError_t launch_phys(hipStream_t s, const PhysOp* ops, const Work& w, const Pa
   if (nv == NVAR_MHD) hipLaunchKernelGGL(fill_phys_ghosts<NVAR_MHD>, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, A);
   else if (nv == NVAR_GLM) hipLaunchKernelGGL(fill_phys_ghosts<NVAR_GLM>, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, A);
   else hipLaunchKernelGGL(fill_phys_ghosts<NVAR>, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, A);
-  return hipGetLastError();
-}
-hipError_t launch_copy_ranges(hipStream_t s, const int64_t* ranges, int nr, int64_t maxlen, const double* src,
-                              double* dst) {
-  const int gx = (int)std::min<int64_t>((maxlen + NT - 1) / NT, 1024);
-  hipLaunchKernelGGL(copy_ranges, dim3(std::max(gx, 1), std::min(nr, 65535)), dim3(NT), 0, s, ranges, nr, src, dst);
   return hipGetLastError();
 }
 template <int NV>
