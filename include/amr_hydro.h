@@ -120,12 +120,18 @@ enum { AMR_RECON_E = 0, AMR_RECON_P = 1 };
 #define AMR_STEP_SUBSTEP1 0x4u /* hierarchies: this level step is the second of the two
                                  its parent level's step contains (its prolonged ghosts
                                  take the parent's state at times 1/2 and 1 of that step,
-                                 instead of 0 and 1/2) */
+                                 instead of 0 and 1/2).  It must follow the same level's
+                                 first substep of that parent step, with only the
+                                 recursion below this level in between: the ghosts of
+                                 its first stage (time 1/2) are the ones that first
+                                 substep's second stage prolonged, reused, not
+                                 interpolated again (without that first substep the
+                                 step returns AMR_ESTATE) */
 
 typedef struct {
   int32_t level;    /* refinement level, 0 = root; cell width dx0[d] / 2^level          */
   int32_t lo[3];    /* index of the first active cell in level index space             */
-  int32_t n[3];     /* active cells per dimension, >= 1; 1 in dimensions >= ndim       */
+  int32_t n[3];     /* active cells per dimension, >= max(2, ng); 1 in dims >= ndim    */
   int32_t ng;       /* ghost layers stored per side in active dimensions, 2 <= ng <= 8, ng <= n;
                        or 0: no ghost storage (s = n), for a patch of a single-level table
                        whose faces are OUTFLOW, PERIODIC, REFLECT or EXTERNAL faces read

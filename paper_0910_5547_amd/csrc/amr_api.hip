@@ -51,7 +51,8 @@ amr_status validate_patches(const amr_patch_desc* P, int32_t np, const amr_physi
     for (int d = 0; d < 3; ++d) {
       if (D.n[d] < 1) return AMR_EINVAL;
       if (d >= ph->ndim && D.n[d] != 1) return AMR_EINVAL;
-      if (d < ph->ndim && D.n[d] < D.ng) return AMR_EINVAL;
+      // (two cells at least: the boundary maps of the two-cell stencil stay in the patch)
+      if (d < ph->ndim && D.n[d] < std::max(2, D.ng)) return AMR_EINVAL;
       if (D.n[d] > (1 << 24)) return AMR_EINVAL;
       S *= D.n[d] + (d < ph->ndim ? 2 * D.ng : 0);
       for (int s = 0; s < 2; ++s) {
@@ -151,6 +152,9 @@ struct amr_table {
   // caller-driven recursion: bit l is set by a step of level l that has children and
   // cleared by amr_flux_correct(l) (the snapshot, U^(1) and registers are in use)
   uint32_t open_mask = 0;
+  // bit l (l > 0): level l's first substep of its parent's current step has been
+  // enqueued, so its U^(1) holds the half-step prolonged ghosts the second reuses
+  uint32_t half_mask = 0;
   int occ[3][2][NSHAPES][2][2] = {};  // resident stage workgroups per CU: [5/8/9 variables][mixed][shape][stage][recording]
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // AMR_STEP_TIMED: around each stage kernel
   bool timed_valid = false;
@@ -1255,6 +1259,8 @@ amr_status amr_hydro_rk2_step(amr_table* t, double* U, const double* dt_dev, int
   if (t->max_level > 0 && (level < 0 || (flags & AMR_STEP_FUSE_DT))) return AMR_EINVAL;
   const bool fuse = (flags & AMR_STEP_FUSE_DT) != 0;
   const int substep = (flags & AMR_STEP_SUBSTEP1) ? 1 : 0;
+  // the second substep reuses the first's half-step ghosts: it needs that first substep
+  if (substep && level > 0 && !(t->half_mask & (1u << level))) return AMR_ESTATE;
   if (flags & AMR_STEP_TIMED) {
     for (auto& e : t->ev)
       if (!e) HIPCHECK(hipEventCreate(&e));
@@ -1311,6 +1317,8 @@ amr_status amr_hydro_rk2_step(amr_table* t, double* U, const double* dt_dev, int
     t->fused_level = -2;
   }
   if (level >= 0 && t->has_kids[level]) t->open_mask |= 1u << level;
+  if (level > 0) t->half_mask = substep ? t->half_mask & ~(1u << level) : t->half_mask | (1u << level);
+  if (level >= 0 && level + 1 < 32) t->half_mask &= ~(1u << (level + 1));  // a new parent step
   return AMR_OK;
 }
 
@@ -1381,6 +1389,7 @@ amr_status amr_hydro_advance(amr_table* t, double* U, const double* dt0_dev, uin
     return amr_hydro_rk2_step(t, U, dt0_dev, -1, 0, stream);
   }
   t->open_mask = 0;  // a whole root step closes every level's recursion
+  t->half_mask = 0;
   for (int l = 0; l <= t->max_level; ++l) {  // tile lists and occupancy before any capture
     TileSet* ts = nullptr;
     amr_status st = get_tiles(t, l, t->shape, t->zslab, &ts);
@@ -1551,6 +1560,7 @@ amr_status amr_autotune(amr_table* t, const double* U, const double* dt_dev, int
   }
   // the candidates' steps leave no recursion open and no level stepped on the caller's U
   t->open_mask = 0;
+  t->half_mask = 0;
   t->last_dt = keep_dt;
   HIPCHECK(launch_fill_i32(stream, t->flag_d, 1, flag_keep));
   HIPCHECK(hipStreamSynchronize(stream));

@@ -87,6 +87,7 @@ def _create(amr, ps, **kw):
     lambda d, ph: setattr(d[0], "ng", 9),
     lambda d, ph: d[0].n.__setitem__(0, 0),
     lambda d, ph: d[0].n.__setitem__(0, 1),          # n < ng in an active dimension
+    lambda d, ph: (setattr(d[0], "ng", 0), d[0].n.__setitem__(0, 1)),  # one cell: the stencil leaves the patch
     lambda d, ph: setattr(d[1], "offset", d[0].offset + 10),  # overlapping storage
     lambda d, ph: setattr(d[0], "offset", -1),
     lambda d, ph: d[0].bc.__setitem__(0, 7),

@@ -120,6 +120,36 @@ def test_autotune_refused_while_a_caller_recursion_is_open(env):
         assert np.array_equal(ps.active(got, p), ps.active(ref, p)), p
 
 
+def test_second_substep_needs_the_first(env):
+    """A level's second substep reuses the half-step ghosts its first substep prolonged: without
+    that first substep since the parent's last step it is refused, and it is refused again once
+    the parent has stepped anew; the refusal enqueues nothing."""
+    torch, A = env
+    ps, U, per, dom = W.two_level_box(Nc=16, fine_lo=(4, 4, 4), fine_n=(8, 8, 8), seed=42)
+    T = A.Table(ps, precision=0, periodic=per, domain=dom)
+    Ud = T.upload(U)
+    T.cfl_dt(Ud, 0.8)
+    dt1 = torch.full((1,), float(T.dt.item()) / 2, dtype=torch.float64, device="cuda")
+    A.amr_hydro_rk2_step(T.h, Ud, T.dt, 0, 0)
+    with pytest.raises(A.AmrError) as ei:
+        A.amr_hydro_rk2_step(T.h, Ud, dt1, 1, A.AMR_STEP_SUBSTEP1)
+    assert ei.value.status == A.AMR_ESTATE
+    A.amr_hydro_rk2_step(T.h, Ud, dt1, 1, 0)
+    A.amr_hydro_rk2_step(T.h, Ud, dt1, 1, A.AMR_STEP_SUBSTEP1)
+    with pytest.raises(A.AmrError) as ei:  # used once per parent step
+        A.amr_hydro_rk2_step(T.h, Ud, dt1, 1, A.AMR_STEP_SUBSTEP1)
+    assert ei.value.status == A.AMR_ESTATE
+    A.amr_flux_correct(T.h, Ud, 0)
+    A.amr_hydro_rk2_step(T.h, Ud, T.dt, 0, 0)
+    A.amr_hydro_rk2_step(T.h, Ud, dt1, 1, 0)
+    A.amr_hydro_rk2_step(T.h, Ud, T.dt, 0, 0)  # the parent steps again: the half step is gone
+    with pytest.raises(A.AmrError) as ei:
+        A.amr_hydro_rk2_step(T.h, Ud, dt1, 1, A.AMR_STEP_SUBSTEP1)
+    assert ei.value.status == A.AMR_ESTATE
+    torch.cuda.synchronize()
+    T.close()
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_fused_maxima_are_read_once_recovery_recipe(env, prec):
     """The fused maxima are read by the first cfl_dt after the step only; after a fused step,
