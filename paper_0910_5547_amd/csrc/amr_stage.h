@@ -42,6 +42,22 @@
 
 namespace amr {
 
+// A struct that the kernel only reads, at an address uniform across the wavefront:
+// read word by word through the constant address space, which the compiler turns into
+// scalar loads into scalar registers (a plain read would be a vector load holding the
+// struct in every lane's registers).
+template <typename S>
+__device__ __forceinline__ S load_uniform(const S* p) {
+  static_assert(sizeof(S) % 4 == 0 && alignof(S) >= 4, "whole words");
+  typedef const __attribute__((address_space(4))) int ConstWord;
+  const ConstWord* w = (const ConstWord*)p;
+  S r;
+  int* d = reinterpret_cast<int*>(&r);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(S) / 4); ++i) d[i] = w[i];
+  return r;
+}
+
 // Occupancy target: three 256-lane workgroups per CU for the FP32-reconstruction
 // instantiations (<= 168 VGPRs), two for FP64 (LDS-bound at two per CU anyway).
 // REC: record fine-face fluxes into the refluxing registers (patches of levels > 0).
@@ -98,7 +114,10 @@ void stage_kernel(StageArgs a) {
   const FaceConsts<RT> K{(RT)C.gamma, (RT)C.gm1, (RT)C.gg1, C.recon, (RT)C.ch, (RT)C.ch2};
   const RT theta = (RT)C.theta;
   const int kind = C.flux;
-  const int sub = WPB == 1 ? 0 : (int)threadIdx.x / TL;  // this lane's tile slot in the workgroup
+  // this lane's tile slot in the workgroup: uniform across the wavefront (a tile is a
+  // whole number of wavefronts), which readfirstlane tells the compiler, so that the
+  // tile and its patch descriptor are scalar loads into scalar registers
+  const int sub = WPB == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)threadIdx.x / TL);
   const int tid = WPB == 1 ? (int)threadIdx.x : (int)threadIdx.x % TL;  // lane in the tile
   int cx = VARW ? 0 : tid % TX, cy = VARW ? 0 : tid / TX;
   auto tile_sync = [] {
@@ -116,8 +135,9 @@ void stage_kernel(StageArgs a) {
   const int buf = sub;
 
   for (int t = blockIdx.x * WPB + sub; t < a.ntiles; t += gridDim.x * WPB) {
-    const Tile T = a.tiles[t];
-    const PatchDev P = a.patches[T.patch];
+    // (t is uniform across the wavefront; the tile list and the descriptors are read-only)
+    const Tile T = load_uniform(a.tiles + t);
+    const PatchDev P = load_uniform(a.patches + T.patch);
     const int tx = VARW ? T.tx : TX;        // tile width (a power of two when VARW)
     const int ty = VARW ? TL / tx : TY;
     const int pitch = tx + 4;                 // LDS row length of the plane
