@@ -165,7 +165,7 @@ typedef struct amr_table amr_table; /* opaque, library-owned */
 
 /* Create a table for `npatch` patches (Sec. 3 hierarchy as a flat list).
  * Copies the descriptors, validates them (AMR_EINVAL on: npatch < 1, n < 1,
- * ng out of range in an active dimension, ng = 0 on a patch of a table with
+ * n < max(2, ng) or ng out of range in an active dimension, ng = 0 on a patch of a table with
  * several levels or with an EXTERNAL face that is not read from one same-shaped
  * sibling, n > 1 in an absent dimension,
  * overlapping storage, unknown bc/flux/precision/exec/recon, nvar not 5, 8 or 9,
