@@ -7,7 +7,7 @@
 //     the primitives of planes z and z+1, the limited z-slope of plane z and the
 //     z-face flux F_{z-1/2}, and loads plane z+2 per step, so every cell of the
 //     column is read from HBM once per stage (its conserved state waits in a
-//     lane-private LDS ring until the update two planes later);
+//     lane-private LDS ring, or in registers, until the update two planes later);
 //   * the x-y plane lives in LDS: the primitives of plane z for the block plus
 //     a 2-cell face halo (no corners: the MOL stencil is a cross, Sec. 4).
 //     Per plane: (1) every cell's limited
@@ -19,10 +19,11 @@
 //     so the flux difference telescopes and totals are conserved to round-off
 //     in both precisions.  The z-face flux of each column is computed between
 //     (2) and (3), overlapping with the other waves' face work.  On 32 x 16
-//     tiles (one workgroup per CU, where every barrier drains the CU) (1) and (2)
-//     are one pass: the lane of a face forms both its states from the primitive
-//     plane (the same slopes, evaluated once per face side), and with the plane
-//     and the fluxes double-buffered one barrier per plane remains;
+//     tiles (one workgroup per CU, where every barrier drains the CU) and on the
+//     FP32 patch-fit tiles (1) and (2) are one pass: the lane of a face forms both
+//     its states from the primitive plane (the same slopes, evaluated once per
+//     face side), and with the plane and the fluxes double-buffered one barrier
+//     per plane remains;
 //   * L(U) is accumulated in FP64 in the order x, y, z (MOL equation), and the
 //     TVD-RK2 stage combine is applied in FP64 before one store per variable.
 // Stage 2 writes U^{n+1} over U^n in place: U^n is only read at the cell being
@@ -91,22 +92,26 @@ void stage_kernel(StageArgs a) {
   // face slots: x faces first, slot row*(nxT+1) + f, then y faces, slot nfx + f*nxT + col
   constexpr int NSLOT = VARW ? 32 * 9 + 33 * 8 : TY * (TX + 1) + (HASY ? (TY + 1) * TX : 0);
   // SB (512-lane tiles, one workgroup per CU: FP32 reconstruction, and FP64 hydro in
-  // stage 1, its stage 2 being short of registers for it): one workgroup barrier per
-  // plane instead of three.
+  // stage 1, its stage 2 being short of registers for it; FP32 hydro on patch-fit tiles,
+  // three workgroups per CU with RREG): one workgroup barrier per plane instead of three.
   // Each lane forms both states of its low x and y faces from the primitive plane itself
   // (the limited slopes of the cells on either side), so no face states pass through LDS;
   // the primitive plane and the fluxes are double-buffered by plane parity, and plane
   // k+1's primitives go to LDS during plane k's face pass.
-  constexpr bool SB = WPB == 1 && NTH == 512 && (Fast<RT>::value || (NV == NVAR && STAGE == 1));
+  // RREG (FP32 hydro on patch-fit tiles): the conserved state of the lane's planes k and k+1
+  // in registers, so that the LDS holds two planes and their fluxes and the single-barrier
+  // scheme keeps three workgroups per CU.
+  constexpr bool RREG = FAST && VARW && NV == NVAR;
+  constexpr bool SB = WPB == 1 && ((NTH == 512 && (Fast<RT>::value || (NV == NVAR && STAGE == 1))) || RREG);
   constexpr int PB = SB ? 2 : WPB;
   __shared__ RT sP[PB][NV][PLANE];  // primitives of the plane (+ face halo), rows of tx + 4
   // face states; sFL then holds the flux (SB: the flux only)
   __shared__ RT sFL[PB][NV][NSLOT], sFR[SB ? 1 : WPB][NV][SB ? 1 : NSLOT];
   // conserved state of this lane's cell in planes k and k+1 (3D), for the update:
   // lane-private, kept in LDS rather than registers or a second read (FP32
-  // instantiations with workgroup tiles; the others re-read the cell, their LDS
-  // budget being spent)
-  constexpr bool RING = FAST && WPB == 1 && NV == NVAR;
+  // instantiations with workgroup tiles other than the patch-fit ones, which keep it
+  // in registers; the others re-read the cell, their LDS budget being spent)
+  constexpr bool RING = FAST && WPB == 1 && NV == NVAR && !RREG;
   __shared__ double sV[RING ? 2 : 1][NV][RING ? NTH : 1];
 
   Consts C = a.c;
@@ -196,6 +201,7 @@ void stage_kernel(StageArgs a) {
     // z-direction register queue (3D only): primitives of planes k and k+1, the
     // z-slope of plane k and the flux F_{k-1/2}
     RT qz[NV], qz1[NV], sgz[NV], Fzm[NV];
+    double VcA[RREG ? NV : 1], VcB[RREG ? NV : 1];  // RREG: conserved state of planes k, k+1
     if (hasz) {
       double u[NV];
       RT qa[NV], qb[NV];
@@ -209,11 +215,19 @@ void stage_kernel(StageArgs a) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) sV[T.z0 & 1][v][threadIdx.x] = u[v];
       }
+      if constexpr (RREG) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) VcA[v] = u[v];
+      }
       load_col(T.z0 + 1, u);
       bad |= cons2prim<RT, NV>(u, C, qz1);
       if constexpr (RING) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) sV[(T.z0 + 1) & 1][v][threadIdx.x] = u[v];
+      }
+      if constexpr (RREG) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) VcB[v] = u[v];
       }
       RT qL[NV], qR[NV];
 #pragma unroll
@@ -349,6 +363,10 @@ void stage_kernel(StageArgs a) {
 #pragma unroll
           for (int v = 0; v < NV; ++v) sV[T.z0 & 1][v][threadIdx.x] = u[v];
         }
+        if constexpr (RREG) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) VcA[v] = u[v];
+        }
         own_to_lds(qc, T.z0 & 1);
       }
       tile_sync();
@@ -382,6 +400,10 @@ void stage_kernel(StageArgs a) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) sV[k & 1][v][threadIdx.x] = Vn2[v];
           }
+          if constexpr (RREG) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) VcA[v] = Vn2[v];
+          }
         }
         own_to_lds(qc, buf);
         tile_sync();  // (A) plane primitives ready; previous plane's fluxes consumed
@@ -403,6 +425,9 @@ void stage_kernel(StageArgs a) {
         if constexpr (RING) {
 #pragma unroll
           for (int v = 0; v < NV; ++v) Vc[v] = sV[k & 1][v][threadIdx.x];
+        } else if constexpr (RREG) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) Vc[v] = VcA[v];
         } else {
 #pragma unroll
           for (int v = 0; v < NV; ++v) Vc[v] = a.V[ecell + v * SV];
@@ -441,7 +466,7 @@ void stage_kernel(StageArgs a) {
 
       if constexpr (WPB == 1) {
         load_u0();
-        if constexpr (!RING) load_vc();
+        if constexpr (!RING && !RREG) load_vc();
       }
 
       if constexpr (SB) {
@@ -534,7 +559,7 @@ void stage_kernel(StageArgs a) {
       if constexpr (WPB > 1) {
         load_u0();
         load_vc();
-      } else if constexpr (RING) {
+      } else if constexpr (RING || RREG) {
         load_vc();
       }
 
@@ -584,6 +609,10 @@ void stage_kernel(StageArgs a) {
             if constexpr (FAST) L[v] = fma(-d, P.rdx[2], L[v]);
             else L[v] = L[v] - d / P.dx[2];
             if constexpr (RING) sV[k & 1][v][threadIdx.x] = Vn2[v];  // plane k+2 takes plane k's slot
+            if constexpr (RREG) {
+              VcA[v] = VcB[v];
+              VcB[v] = Vn2[v];
+            }
             qz[v] = qz1[v];
             qz1[v] = qn2[v];
             sgz[v] = sg1[v];
