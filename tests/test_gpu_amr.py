@@ -57,10 +57,11 @@ def run_pair(env, case, steps, prec=0, exe=1, shape=None):
     return ps, U, Ug, Uo
 
 
-@pytest.mark.parametrize("exe,shape", [(1, None), (0, None), (1, 1), (1, 4), (1, 5), (1, 6)])
+@pytest.mark.parametrize("exe,shape", [(1, None), (0, None), (1, 1), (1, 4), (1, 5), (1, 6), (1, 7)])
 @pytest.mark.parametrize("case", list(CASES))
 def test_hierarchy_fp64_matches_oracle(env, case, exe, shape):
-    """shape None: the library's default tiling; 1, 4, 5, 6: 32x8 workgroup, 8x8 wavefront, 32x16 (512 threads) and 32x12 (384) tiles."""
+    """shape None: the library's default tiling; 1, 4, 5, 6, 7: 32x8 workgroup, 8x8 wavefront, 32x16 (512 threads),
+    32x12 (384) and patch-fit tiles."""
     if shape is not None and case.endswith("1d"):
         pytest.skip("1D tables have the one 1D tiling")
     log(f"case amr {case} fp64 exec={exe} shape={shape}")
@@ -75,7 +76,7 @@ def test_hierarchy_fp64_matches_oracle(env, case, exe, shape):
     assert np.all(np.abs(t1 - t0) <= 1e-12 * sc), (t1 - t0) / sc
 
 
-@pytest.mark.parametrize("shape", [None, 1, 4, 5])
+@pytest.mark.parametrize("shape", [None, 1, 4, 5, 7])
 @pytest.mark.parametrize("case", list(CASES))
 def test_hierarchy_mixed(env, case, shape):
     if shape is not None and case.endswith("1d"):
