@@ -98,19 +98,22 @@ void stage_kernel(StageArgs a) {
   // (the limited slopes of the cells on either side), so no face states pass through LDS;
   // the primitive plane and the fluxes are double-buffered by plane parity, and plane
   // k+1's primitives go to LDS during plane k's face pass.
-  // RREG (FP32 hydro on patch-fit tiles): the conserved state of the lane's planes k and k+1
-  // in registers, so that the LDS holds two planes and their fluxes and the single-barrier
-  // scheme keeps three workgroups per CU.
-  constexpr bool RREG = FAST && VARW && NV == NVAR;
-  constexpr bool SB = WPB == 1 && ((NTH == 512 && (Fast<RT>::value || (NV == NVAR && STAGE == 1))) || RREG);
+  // RREG: the conserved state of the lane's planes k and k+1 in registers (FP32
+  // reconstruction): on patch-fit hydro tiles, so that the LDS holds two planes and their
+  // fluxes and the single-barrier scheme keeps three workgroups per CU; on the 8- and
+  // 9-variable 32 x 16 tiles and the wavefront tiles, instead of re-reading the cell from
+  // global memory for the update.
+  constexpr bool SB512 = WPB == 1 && NTH == 512 && (Fast<RT>::value || (NV == NVAR && STAGE == 1));
+  constexpr bool RREG = FAST && ((VARW && NV == NVAR) || (SB512 && NV >= NVAR_MHD && !REC) || (WPB > 1 && NV == NVAR));
+  constexpr bool SB = SB512 || (WPB == 1 && RREG);
   constexpr int PB = SB ? 2 : WPB;
   __shared__ RT sP[PB][NV][PLANE];  // primitives of the plane (+ face halo), rows of tx + 4
   // face states; sFL then holds the flux (SB: the flux only)
   __shared__ RT sFL[PB][NV][NSLOT], sFR[SB ? 1 : WPB][NV][SB ? 1 : NSLOT];
   // conserved state of this lane's cell in planes k and k+1 (3D), for the update:
-  // lane-private, kept in LDS rather than registers or a second read (FP32
-  // instantiations with workgroup tiles other than the patch-fit ones, which keep it
-  // in registers; the others re-read the cell, their LDS budget being spent)
+  // lane-private, kept in LDS rather than registers or a second read (FP32 hydro on the
+  // other workgroup tiles; RREG keeps it in registers; the FP64 kernels re-read the cell,
+  // their LDS and register budgets being spent)
   constexpr bool RING = FAST && WPB == 1 && NV == NVAR && !RREG;
   __shared__ double sV[RING ? 2 : 1][NV][RING ? NTH : 1];
 
