@@ -582,10 +582,10 @@ void stage_kernel(StageArgs a) {
           if (hasy) ry = j == 0 ? P.reg[2] : (j == P.n[1] - 1 ? P.reg[3] : -1);
           if (hasz) rz = k == 0 ? P.reg[4] : (k == P.n[2] - 1 ? P.reg[5] : -1);
         }
-        auto record = [&](int64_t e, double F) {
-          double* r = a.reg + e;
-          *r = *r + hdt * F;
-        };
+        // (a no-return atomic add: one lane writes each register element per launch, so
+        // the sum is taken in the same order as a load, add and store, but no load waits -
+        // a load here would make the wave wait for every prefetch in flight)
+        auto record = [&](int64_t e, double F) { (void)unsafeAtomicAdd(a.reg + e, hdt * F); };
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           const double fl = (double)sFL[fb][v][sx], fh = (double)sFL[fb][v][sx + 1];
