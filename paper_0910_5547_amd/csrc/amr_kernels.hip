@@ -51,9 +51,11 @@ __global__ void cfl_finalize(const unsigned long long* smax, int lmin, int lmax,
 }
 
 // ------------------------------------------------------------------ ghosts
-// Same-level EXTERNAL ghost fill, one ghost cell (all nv variables) per lane.
+// Same-level EXTERNAL ghost fill, one ghost cell (all NV variables) per lane; every
+// variable is read before the first store (one round trip, not one per variable).
+template <int NV>
 __global__ __launch_bounds__(NT) void copy_ghosts(const CopyOp* __restrict__ ops, Work w,
-                                                  const PatchDev* __restrict__ patches, double* A, int nv) {
+                                                  const PatchDev* __restrict__ patches, double* A) {
   int c;
   const int o = work_item(w, c);
   if (o < 0) return;
@@ -65,7 +67,11 @@ __global__ __launch_bounds__(NT) void copy_ghosts(const CopyOp* __restrict__ ops
   const int i = op.lo[0] + b[0], j = op.lo[1] + b[1], k = op.lo[2] + b[2];
   const int64_t ed = cell_elem(D, i, j, k);
   const int64_t es = cell_elem(S, i + op.sh[0], j + op.sh[1], k + op.sh[2]);
-  for (int v = 0; v < nv; ++v) A[ed + v * D.S] = A[es + v * S.S];
+  double u[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = A[es + v * S.S];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) A[ed + v * D.S] = u[v];
 }
 
 // dt_l = dt0 / 2^l: factor-2 subcycling of a block-structured hierarchy.
@@ -118,7 +124,9 @@ hipError_t launch_cfl_finalize(hipStream_t s, const unsigned long long* smax, in
   return hipGetLastError();
 }
 hipError_t launch_copy_ghosts(hipStream_t s, const CopyOp* ops, const Work& w, const PatchDev* p, double* A, int nv) {
-  hipLaunchKernelGGL(copy_ghosts, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, A, nv);
+  if (nv == NVAR_MHD) hipLaunchKernelGGL(copy_ghosts<NVAR_MHD>, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, A);
+  else if (nv == NVAR_GLM) hipLaunchKernelGGL(copy_ghosts<NVAR_GLM>, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, A);
+  else hipLaunchKernelGGL(copy_ghosts<NVAR>, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, A);
   return hipGetLastError();
 }
 hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, int n, unsigned long long v) {

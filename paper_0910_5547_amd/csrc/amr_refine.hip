@@ -31,10 +31,13 @@ __device__ __forceinline__ double at_time(const double* Cold, const double* Cnew
 // Fine ghost cell = u(C) + sum_d (+-1/4) minmod(u(C+e_d) - u(C), u(C) - u(C-e_d)),
 // u the time-interpolated coarse state, C the coarse cell holding the fine cell,
 // + for the upper child along d.  The 2^d children of C average to u(C).
+// Every coarse value is loaded before the first store (A, Cold and Cnew may share
+// one arena, so a store between two loads would order them one round trip apart).
+template <int NV>
 __global__ __launch_bounds__(NT) void prolong_ghosts(const ProlongOp* __restrict__ ops, Work w,
                                                      const PatchDev* __restrict__ patches, double* A,
                                                      const double* Cold, const double* Cnew, double alpha,
-                                                     int ndim, int nv) {
+                                                     int ndim) {
   int c;
   const int o = work_item(w, c);
   if (o < 0) return;
@@ -52,18 +55,29 @@ __global__ __launch_bounds__(NT) void prolong_ghosts(const ProlongOp* __restrict
   const int64_t ed = cell_elem(D, loc[0], loc[1], loc[2]);
   const int64_t e0 = cell_elem(Q, cq[0], cq[1], cq[2]);
   const int64_t DS = D.S, QS = Q.S;
-  const int64_t qs[3] = {1, (int64_t)Q.s[0], (int64_t)Q.s[0] * Q.s[1]};
-  for (int v = 0; v < nv; ++v) {
+  // (an inactive dimension's neighbours are the cell itself: loaded, never used)
+  const int64_t qs[3] = {1, ndim > 1 ? (int64_t)Q.s[0] : 0, ndim > 2 ? (int64_t)Q.s[0] * Q.s[1] : 0};
+  double u0[NV], up[3][NV], um[3][NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
     const int64_t ev = e0 + v * QS;
-    const double u0 = at_time(Cold, Cnew, alpha, ev);
-    double val = u0;
-    for (int d = 0; d < ndim; ++d) {
-      const double up = at_time(Cold, Cnew, alpha, ev + qs[d]);
-      const double um = at_time(Cold, Cnew, alpha, ev - qs[d]);
-      const double sg = minmod2(up - u0, u0 - um);
-      const double sgn = (L[d] & 1) ? 0.25 : -0.25;
-      val = val + sgn * sg;
+    u0[v] = at_time(Cold, Cnew, alpha, ev);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      up[d][v] = at_time(Cold, Cnew, alpha, ev + qs[d]);
+      um[d][v] = at_time(Cold, Cnew, alpha, ev - qs[d]);
     }
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double val = u0[v];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (d < ndim) {
+        const double sg = minmod2(up[d][v] - u0[v], u0[v] - um[d][v]);
+        const double sgn = (L[d] & 1) ? 0.25 : -0.25;
+        val = val + sgn * sg;
+      }
     A[ed + v * DS] = val;
   }
 }
@@ -160,6 +174,10 @@ __global__ __launch_bounds__(NT) void flux_fix(const FixOp* __restrict__ ops, Wo
                       : face == 3 ? P.reg[3] : face == 4 ? P.reg[4] : P.reg[5];
   const int64_t e = cell_elem(Q, cc[0], cc[1], cc[2]);
   const double sgn = op.side == 0 ? 1.0 : -1.0;
+  // the coarse cell's values are read before the first store
+  double u[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = U[e + v * Q.S];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     double Rf = 0.0;
@@ -169,16 +187,15 @@ __global__ __launch_bounds__(NT) void flux_fix(const FixOp* __restrict__ ops, Wo
     Rf = Rf / (double)(na * nb);
     double Rc = 0.5 * dtc * (double)F1[v];
     Rc = Rc + 0.5 * dtc * (double)F2[v];
-    double* u = U + e + v * Q.S;
-    *u = *u + sgn * (Rc - Rf) / Q.dx[d];
+    U[e + v * Q.S] = u[v] + sgn * (Rc - Rf) / Q.dx[d];
   }
   if (bad) atomicOr(flag, 1);
 }
 
 // ---------------------------------------------------------------- restriction
+template <int NV>
 __global__ __launch_bounds__(NT) void restrict_cells(const RestrictOp* __restrict__ ops, Work w,
-                                                     const PatchDev* __restrict__ patches, double* U, int ndim,
-                                                     int nv) {
+                                                     const PatchDev* __restrict__ patches, double* U, int ndim) {
   int c;
   const int o = work_item(w, c);
   if (o < 0) return;
@@ -193,19 +210,28 @@ __global__ __launch_bounds__(NT) void restrict_cells(const RestrictOp* __restric
   int f0[3] = {0, 0, 0};
   for (int d = 0; d < ndim; ++d) f0[d] = 2 * cc[d] + op.fo[d];
   const int64_t e = cell_elem(Q, cc[0], cc[1], cc[2]);
-  for (int v = 0; v < nv; ++v) {
-    double acc = 0.0;
+  // every child is read before the first store (one round trip, not one per variable)
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    acc[v] = 0.0;
     for (int dz = 0; dz < mz; ++dz)
       for (int dy = 0; dy < my; ++dy)
-        for (int dx = 0; dx < 2; ++dx) acc = acc + U[cell_elem(P, f0[0] + dx, f0[1] + dy, f0[2] + dz) + v * P.S];
-    U[e + v * Q.S] = acc / inv;
+        for (int dx = 0; dx < 2; ++dx)
+          acc[v] = acc[v] + U[cell_elem(P, f0[0] + dx, f0[1] + dy, f0[2] + dz) + v * P.S];
   }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) U[e + v * Q.S] = acc[v] / inv;
 }
 
 // ---------------------------------------------------------------- launchers
 hipError_t launch_prolong(hipStream_t s, const ProlongOp* ops, const Work& w, const PatchDev* p, double* A,
                           const double* Cold, const double* Cnew, double alpha, int ndim, int nv) {
-  hipLaunchKernelGGL(prolong_ghosts, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, A, Cold, Cnew, alpha, ndim, nv);
+  if (nv == NVAR_MHD)
+    hipLaunchKernelGGL(prolong_ghosts<NVAR_MHD>, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, A, Cold, Cnew, alpha, ndim);
+  else if (nv == NVAR_GLM)
+    hipLaunchKernelGGL(prolong_ghosts<NVAR_GLM>, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, A, Cold, Cnew, alpha, ndim);
+  else hipLaunchKernelGGL(prolong_ghosts<NVAR>, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, A, Cold, Cnew, alpha, ndim);
   return hipGetLastError();
 }
 hipError_t launch_phys(hipStream_t s, const PhysOp* ops, const Work& w, const PatchDev* p, double* A, int nv) {
@@ -233,7 +259,9 @@ hipError_t launch_flux_fix(int mixed, int nv, hipStream_t s, const FixOp* ops, c
 }
 hipError_t launch_restrict(hipStream_t s, const RestrictOp* ops, const Work& w, const PatchDev* p, double* U,
                            int ndim, int nv) {
-  hipLaunchKernelGGL(restrict_cells, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, U, ndim, nv);
+  if (nv == NVAR_MHD) hipLaunchKernelGGL(restrict_cells<NVAR_MHD>, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, U, ndim);
+  else if (nv == NVAR_GLM) hipLaunchKernelGGL(restrict_cells<NVAR_GLM>, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, U, ndim);
+  else hipLaunchKernelGGL(restrict_cells<NVAR>, dim3(w.nblk), dim3(NT), 0, s, ops, w, p, U, ndim);
   return hipGetLastError();
 }
 

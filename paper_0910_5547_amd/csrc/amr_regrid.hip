@@ -66,11 +66,13 @@ hipError_t launch_flag_cells(hipStream_t s, const int* plist, const int64_t* cof
 namespace amr {
 
 // Cells of a new table's patches taken from an old table's patches at the same level:
-// op.dst (new table) box [lo, lo+sz) (dst-local) <- op.src (old table) cells at + sh.
+// op.dst (new table) box [lo, lo+sz) (dst-local) <- op.src (old table) cells at + sh;
+// every variable is read before the first store.
+template <int NV>
 __global__ __launch_bounds__(NT) void copy_cells_x(const CopyOp* __restrict__ ops, Work w,
                                                    const PatchDev* __restrict__ pdst,
                                                    const PatchDev* __restrict__ psrc, double* Adst,
-                                                   const double* __restrict__ Asrc, int nv) {
+                                                   const double* __restrict__ Asrc) {
   int c;
   const int o = work_item(w, c);
   if (o < 0) return;
@@ -82,12 +84,20 @@ __global__ __launch_bounds__(NT) void copy_cells_x(const CopyOp* __restrict__ op
   const int i = op.lo[0] + b[0], j = op.lo[1] + b[1], k = op.lo[2] + b[2];
   const int64_t ed = cell_elem(D, i, j, k);
   const int64_t es = cell_elem(S, i + op.sh[0], j + op.sh[1], k + op.sh[2]);
-  for (int v = 0; v < nv; ++v) Adst[ed + v * D.S] = Asrc[es + v * S.S];
+  double u[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = Asrc[es + v * S.S];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Adst[ed + v * D.S] = u[v];
 }
 
 hipError_t launch_copy_cells_x(hipStream_t s, const CopyOp* ops, const Work& w, const PatchDev* pdst,
                                const PatchDev* psrc, double* Adst, const double* Asrc, int nv) {
-  hipLaunchKernelGGL(copy_cells_x, dim3(w.nblk), dim3(NT), 0, s, ops, w, pdst, psrc, Adst, Asrc, nv);
+  if (nv == NVAR_MHD)
+    hipLaunchKernelGGL(copy_cells_x<NVAR_MHD>, dim3(w.nblk), dim3(NT), 0, s, ops, w, pdst, psrc, Adst, Asrc);
+  else if (nv == NVAR_GLM)
+    hipLaunchKernelGGL(copy_cells_x<NVAR_GLM>, dim3(w.nblk), dim3(NT), 0, s, ops, w, pdst, psrc, Adst, Asrc);
+  else hipLaunchKernelGGL(copy_cells_x<NVAR>, dim3(w.nblk), dim3(NT), 0, s, ops, w, pdst, psrc, Adst, Asrc);
   return hipGetLastError();
 }
 
