@@ -552,6 +552,12 @@ void stage_kernel(StageArgs a) {
         }
         riemann_flux<RT, 2, NV>(qL, qR, K, kind, Fzp);
       }
+      // (a use of the prefetch on every path, before the next memory operation: 3D has
+      // just waited for it, and 1D/2D in the one-barrier scheme does not read it at all.
+      // Left pending on any path, it would be waited for where the loop's end moves it
+      // between registers - after this plane's stores, which the same counter tracks)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) asm volatile("" ::"v"(Vn2[v]));
       if constexpr (SB) {  // plane k+1 into the other buffer (3D: 1D/2D tiles have one plane)
         if (k + 1 < T.z1) {
           halo_to_lds(k + 1, (k + 1) & 1);
