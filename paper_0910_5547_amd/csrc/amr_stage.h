@@ -643,6 +643,13 @@ void stage_kernel(StageArgs a) {
           for (int v = 0; v < NV; ++v) a.out[e + v * SO] = un[v];
           if (STAGE == 2 && a.smax != nullptr) smax = fmax(smax, cell_speed<FAST, NV>(un, C, P, bad));
         }
+        if constexpr (STAGE == 2) {
+          // (U^n used on every path: consumed only where a lane is active, its loads would
+          // be pending at the next plane's first register reuse on a path of idle lanes, and
+          // the wait for them would also wait for this plane's stores, issued after them)
+#pragma unroll
+          for (int v = 0; v < NV; ++v) asm volatile("" ::"v"(U0c[v]));
+        }
       }
     }
     if (STAGE == 2 && a.smax != nullptr) {  // fused next-dt reduction, per level
