@@ -123,12 +123,21 @@ struct Work {
   int pad;
 };
 
+// Workgroup b of a launch runs on XCD b % 8; each XCD takes a contiguous run of the
+// list instead (XCD x its q + (x < r) workgroups, q = n / 8, r = n % 8, from x q + min(x, r)
+// on), so that neighbouring boxes' shared lines meet in one XCD's L2.  A bijection of [0, n).
+__device__ __forceinline__ int xcd_run(int b, int n) {
+  const int q = n >> 3, r = n & 7, x = b & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
 // The op index (or -1: no cell) and the cell within it of this lane.
 __device__ __forceinline__ int work_item(const Work& w, int& cell) {
   int op = -1;
   cell = 0;
   const int lane = (int)threadIdx.x;
-  for (int s = w.blk[blockIdx.x]; s < w.blk[blockIdx.x + 1]; ++s) {
+  const int b = xcd_run((int)blockIdx.x, w.nblk);
+  for (int s = w.blk[b]; s < w.blk[b + 1]; ++s) {
     const Seg g = w.segs[s];
     const int c = lane - g.lane0;
     if (c >= 0 && c < g.count) {
