@@ -555,7 +555,9 @@ void stage_kernel(StageArgs a) {
       // (a use of the prefetch on every path, before the next memory operation: 3D has
       // just waited for it, and 1D/2D in the one-barrier scheme does not read it at all.
       // Left pending on any path, it would be waited for where the loop's end moves it
-      // between registers - after this plane's stores, which the same counter tracks)
+      // between registers - after this plane's stores, which the same counter tracks.
+      // On the three-barrier tilings the wait lands here and also takes the halo loads
+      // issued at the start of the plane, which have had the face pass to arrive)
 #pragma unroll
       for (int v = 0; v < NV; ++v) asm volatile("" ::"v"(Vn2[v]));
       if constexpr (SB) {  // plane k+1 into the other buffer (3D: 1D/2D tiles have one plane)
@@ -590,7 +592,9 @@ void stage_kernel(StageArgs a) {
         }
         // (a no-return atomic add: one lane writes each register element per launch, so
         // the sum is taken in the same order as a load, add and store, but no load waits -
-        // a load here would make the wave wait for every prefetch in flight)
+        // a load here would make the wave wait for every prefetch in flight.  The registers
+        // are device memory of the table's own allocation; the hardware FP64 add rounds to
+        // nearest like the ALU's, and the hierarchy tests compare the results bit for bit)
         auto record = [&](int64_t e, double F) { (void)unsafeAtomicAdd(a.reg + e, hdt * F); };
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -644,9 +648,11 @@ void stage_kernel(StageArgs a) {
           if (STAGE == 2 && a.smax != nullptr) smax = fmax(smax, cell_speed<FAST, NV>(un, C, P, bad));
         }
         if constexpr (STAGE == 2) {
-          // (U^n used on every path: consumed only where a lane is active, its loads would
-          // be pending at the next plane's first register reuse on a path of idle lanes, and
-          // the wait for them would also wait for this plane's stores, issued after them)
+          // (U^n used on every path: consumed only where a lane is active, its loads stay
+          // pending on a path of idle lanes, and the next plane's first reuse of their
+          // registers waited for them and for every memory operation issued after them,
+          // this plane's stores included.  This use moves that wait here, after the
+          // stores, which measured faster on the patch-fit tiles)
 #pragma unroll
           for (int v = 0; v < NV; ++v) asm volatile("" ::"v"(U0c[v]));
         }
